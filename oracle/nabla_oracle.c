@@ -1,0 +1,682 @@
+/*
+ * nabla_oracle.c -- FP64 CPU oracle for the edge-based median-dual
+ * finite-volume nabla operators on the octahedral reduced Gaussian grid.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness reference against
+ * which the GPU library is checked.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it.  It shares no code, header,
+ * table or helper with the GPU library, and it never reads anything the GPU
+ * library produced: it builds its own grid, its own triangulation, its own
+ * edge list and its own dual geometry from (N, R) alone.
+ *
+ * What it follows:
+ *   - Grid: Section 4.2.3.5 (Gaussian latitudes are the roots of a Legendre
+ *     polynomial; the first point of every parallel sits at x = 0) and
+ *     Section 4.2.3.7 "Octahedral reduced Gaussian grids" (Listing 6: the nx
+ *     array is 20 + 4j up to the equator, mirrored about it); Section 4.2
+ *     (points are equispaced along each parallel).
+ *   - Mesh: Section 4.3 (triangles between the parallels, edges between
+ *     nodes; Eq. 1) and Section 4.3 on vertical extrusion (levels are
+ *     independent prisms, so every level is an independent 2-D problem).
+ *   - Field layout: Section 4.5, Figure 31 (NodeColumns: one vertical column
+ *     contiguous per node, i.e. [node][level]); Listing 12 (gradient output
+ *     has two variables, stored [node][level][2]).
+ *   - Operators: Section 4.7 and Figure 33 (gradient, divergence, curl,
+ *     Laplacian of an edge-based finite-volume method).  The paper names the
+ *     operators without formulas; the discretisation implemented here is the
+ *     textbook median-dual Green-Gauss scheme in the (lon, lat) plane with a
+ *     nodal cos(lat) metric.  Every reading taken where the paper is silent
+ *     is listed in the design notes of the repository and repeated at the
+ *     function that takes it.
+ *
+ * Precision: FP64 throughout.  Build: gcc -O2 -ffp-contract=off -fopenmp,
+ * no fast-math.  Threads partition the LEVELS into disjoint chunks, so no
+ * two threads ever touch the same accumulator and the result does not depend
+ * on the thread count.
+ *
+ * Pins (tests that tie this code to something other than itself):
+ *   latitudes      -> numpy leggauss (library routine), symmetry
+ *   node counts    -> printed counts (Section 4.4, Figure 28) + Listing 6
+ *   triangulation  -> Euler counts, CCW areas, band area, edge multiplicity
+ *   dual geometry  -> sum of areas = 2 pi^2; cell closure; brute-force
+ *                     median-dual polygons built independently in the tests
+ *   gradient       -> exact for linear data (interior), zero for constants,
+ *                     Galerkin identity sum_T |T|/3 grad(phi_T) (brute force)
+ *   divergence     -> exact special cases, telescoping sum(V div) = 0
+ *   curl           -> exact special cases, telescoping sum(V curl) = 0
+ *   Laplacian      -> spherical-harmonic eigenvalue convergence
+ *   all            -> level independence, second-order convergence on random
+ *                     low-degree spherical harmonics away from the poles
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Mesh record (owned by the oracle; opaque to Python except via getters).  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int N;                 /* Gaussian number: parallels per hemisphere      */
+  double R;              /* sphere radius                                   */
+  int nrings;            /* 2N                                              */
+  int32_t *nx;           /* [nrings] points per parallel                    */
+  int64_t *ring_off;     /* [nrings+1] first node of each parallel          */
+  int64_t V;             /* nodes                                           */
+  double *lon, *lat;     /* [V] radians                                     */
+  double *coslat;        /* [V] cos(lat)                                    */
+  int64_t F;             /* triangles                                       */
+  int32_t *tri;          /* [F][3] counter-clockwise in (lon, lat)          */
+  int64_t E;             /* mesh edges                                      */
+  int32_t *edge;         /* [E][2], edge[e][0] < edge[e][1]                 */
+  double *S;             /* [E][2] dual-face normal (S_lon, S_lat), a -> b  */
+  double *A;             /* [V] dual area in the (lon, lat) plane           */
+  double *vol;           /* [V] R^2 cos(lat) A                              */
+  int npole;             /* pole edges                                      */
+  int32_t *pole_edge;    /* [npole][2]                                      */
+  double *pole_normal;   /* [npole] lat-component of the pole face normal   */
+  /* the oracle's own node -> (edge, sign) lists, ascending edge id; used by
+   * the sampled evaluators only                                            */
+  int64_t *adj_ptr;      /* [V+1]                                           */
+  int32_t *adj_edge;     /* [2E]                                            */
+  int32_t *pole_of;      /* [V] pole edge of a node, or -1                  */
+} orc_mesh;
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian latitudes: the 2N roots of the Legendre polynomial P_{2N}(mu),   */
+/* in descending order (north to south).  Section 4.2.3.5.  Newton's method  */
+/* on the three-term recurrence, started from the classical asymptotic      */
+/* guess cos(pi (j + 3/4) / (n + 1/2)).                                      */
+/* ------------------------------------------------------------------------ */
+static void legendre_pair(int n, double x, double *p_n, double *p_nm1) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { *p_n = 1.0; *p_nm1 = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / (double)k;
+    p0 = p1;
+    p1 = pk;
+  }
+  *p_n = p1;
+  *p_nm1 = p0;
+}
+
+int orc_gauss_mu(int N, double *mu) {
+  if (N < 1 || !mu) return -1;
+  const int n = 2 * N;
+  for (int j = 0; j < N; ++j) {
+    double x = cos(ORC_PI * (j + 0.75) / (n + 0.5));
+    int converged = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p, pm1;
+      legendre_pair(n, x, &p, &pm1);
+      double dp = n * (x * p - pm1) / (x * x - 1.0); /* P_n'(x) */
+      double dx = p / dp;
+      x -= dx;
+      if (fabs(dx) <= 1e-15) {
+        if (converged) break; /* one extra step after convergence */
+        converged = 1;
+      }
+    }
+    mu[j] = x;          /* northern hemisphere: descending positive roots */
+    mu[n - 1 - j] = -x; /* southern mirror                                */
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small helpers                                                             */
+/* ------------------------------------------------------------------------ */
+static int cmp_i64(const void *a, const void *b) {
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* Unwrap longitude x so that it lies within pi of the reference xref. */
+static double unwrap(double x, double xref) {
+  while (x - xref > ORC_PI) x -= 2.0 * ORC_PI;
+  while (x - xref < -ORC_PI) x += 2.0 * ORC_PI;
+  return x;
+}
+
+/* Edge id of the unordered pair (p, q); edges are sorted lexicographically,
+ * first[a] is the first edge whose smaller node is a.                       */
+static int64_t find_edge(const orc_mesh *m, const int64_t *first, int32_t p,
+                         int32_t q) {
+  int32_t a = p < q ? p : q, b = p < q ? q : p;
+  int64_t lo = first[a], hi = first[a + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    int32_t bb = m->edge[2 * mid + 1];
+    if (bb == b) return mid;
+    if (bb < b) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+void orc_mesh_free(orc_mesh *m) {
+  if (!m) return;
+  free(m->nx); free(m->ring_off); free(m->lon); free(m->lat); free(m->coslat);
+  free(m->tri); free(m->edge); free(m->S); free(m->A); free(m->vol);
+  free(m->pole_edge); free(m->pole_normal); free(m->adj_ptr);
+  free(m->adj_edge); free(m->pole_of);
+  free(m);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Build grid O<N>, its triangulation, edges and median-dual geometry.       */
+/* ------------------------------------------------------------------------ */
+orc_mesh *orc_mesh_build(int N, double R) {
+  if (N < 1 || !(R > 0.0)) return NULL;
+  orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+  if (!m) return NULL;
+  m->N = N;
+  m->R = R;
+  m->nrings = 2 * N;
+  const int nr = m->nrings;
+
+  /* --- grid: Section 4.2.3.7, Listing 6 (nx = 20 + 4j, mirrored) -------- */
+  m->nx = (int32_t *)malloc(sizeof(int32_t) * nr);
+  m->ring_off = (int64_t *)malloc(sizeof(int64_t) * (nr + 1));
+  for (int j = 0; j < N; ++j) {
+    m->nx[j] = 20 + 4 * j;
+    m->nx[nr - 1 - j] = m->nx[j];
+  }
+  m->ring_off[0] = 0;
+  for (int j = 0; j < nr; ++j) m->ring_off[j + 1] = m->ring_off[j] + m->nx[j];
+  const int64_t V = m->ring_off[nr];
+  m->V = V;
+
+  double *mu = (double *)malloc(sizeof(double) * nr);
+  orc_gauss_mu(N, mu);
+  m->lon = (double *)malloc(sizeof(double) * V);
+  m->lat = (double *)malloc(sizeof(double) * V);
+  m->coslat = (double *)malloc(sizeof(double) * V);
+  for (int j = 0; j < nr; ++j) {
+    double th = asin(mu[j]);
+    for (int i = 0; i < m->nx[j]; ++i) {
+      int64_t id = m->ring_off[j] + i;
+      /* equispaced along the parallel, first point at lon = 0 (Sec 4.2.3.5) */
+      m->lon[id] = 2.0 * ORC_PI * (double)i / (double)m->nx[j];
+      m->lat[id] = th;
+      m->coslat[id] = cos(th);
+    }
+  }
+  free(mu);
+
+  /* --- triangulation between consecutive parallels (zipper rule) --------
+   * Upper ring u with nu points, lower ring l with nl points; a, b count the
+   * points consumed.  The next upper point lies at lon 2pi(a+1)/nu and the
+   * next lower point at 2pi(b+1)/nl; the one further west is consumed first
+   * (compared exactly in integers).  On a tie the ring with more points
+   * advances; with equal counts the lower ring advances.                   */
+  int64_t F = 0;
+  for (int j = 0; j + 1 < nr; ++j) F += m->nx[j] + m->nx[j + 1];
+  m->F = F;
+  m->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * F);
+  int64_t t = 0;
+  for (int j = 0; j + 1 < nr; ++j) {
+    const int64_t nu = m->nx[j], nl = m->nx[j + 1];
+    const int64_t ou = m->ring_off[j], ol = m->ring_off[j + 1];
+    int64_t a = 0, b = 0;
+    while (a < nu || b < nl) {
+      int64_t up = (a + 1) * nl, lo = (b + 1) * nu;
+      int advance_upper;
+      if (up < lo) advance_upper = 1;
+      else if (up > lo) advance_upper = 0;
+      else advance_upper = (nu > nl) ? 1 : 0;
+      if (a == nu) advance_upper = 0;
+      if (b == nl) advance_upper = 1;
+      int32_t Ua = (int32_t)(ou + (a % nu)), Lb = (int32_t)(ol + (b % nl));
+      if (advance_upper) {
+        m->tri[3 * t + 0] = Ua;
+        m->tri[3 * t + 1] = Lb;
+        m->tri[3 * t + 2] = (int32_t)(ou + ((a + 1) % nu));
+        ++a;
+      } else {
+        m->tri[3 * t + 0] = Ua;
+        m->tri[3 * t + 1] = Lb;
+        m->tri[3 * t + 2] = (int32_t)(ol + ((b + 1) % nl));
+        ++b;
+      }
+      ++t;
+    }
+  }
+
+  /* --- unique edges (a < b), sorted lexicographically; id = rank -------- */
+  int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * 3 * F);
+  for (int64_t f = 0; f < F; ++f) {
+    for (int k = 0; k < 3; ++k) {
+      int64_t p = m->tri[3 * f + k], q = m->tri[3 * f + (k + 1) % 3];
+      int64_t a = p < q ? p : q, b = p < q ? q : p;
+      keys[3 * f + k] = a * V + b;
+    }
+  }
+  qsort(keys, (size_t)(3 * F), sizeof(int64_t), cmp_i64);
+  int64_t E = 0;
+  for (int64_t k = 0; k < 3 * F; ++k)
+    if (k == 0 || keys[k] != keys[k - 1]) keys[E++] = keys[k];
+  m->E = E;
+  m->edge = (int32_t *)malloc(sizeof(int32_t) * 2 * E);
+  for (int64_t e = 0; e < E; ++e) {
+    m->edge[2 * e + 0] = (int32_t)(keys[e] / V);
+    m->edge[2 * e + 1] = (int32_t)(keys[e] % V);
+  }
+  free(keys);
+  int64_t *first = (int64_t *)malloc(sizeof(int64_t) * (V + 1));
+  {
+    int64_t e = 0;
+    for (int64_t a = 0; a <= V; ++a) {
+      while (e < E && m->edge[2 * e] < a) ++e;
+      first[a] = e;
+    }
+  }
+
+  /* --- median-dual geometry in the (lon, lat) plane ----------------------
+   * Per triangle, coordinates unwrapped relative to its first vertex.
+   * For every triangle edge the dual-face segment runs from the edge
+   * midpoint to the triangle centroid; its normal (d_lat, -d_lon) is
+   * oriented from the edge's first node a towards its second node b and
+   * added to S_e.  Every node receives one third of the triangle's area.  */
+  m->S = (double *)calloc((size_t)(2 * E), sizeof(double));
+  m->A = (double *)calloc((size_t)V, sizeof(double));
+  for (int64_t f = 0; f < F; ++f) {
+    int32_t id[3];
+    double x[3], y[3];
+    for (int k = 0; k < 3; ++k) {
+      id[k] = m->tri[3 * f + k];
+      x[k] = m->lon[id[k]];
+      y[k] = m->lat[id[k]];
+    }
+    x[1] = unwrap(x[1], x[0]);
+    x[2] = unwrap(x[2], x[0]);
+    const double cx = (x[0] + x[1] + x[2]) / 3.0;
+    const double cy = (y[0] + y[1] + y[2]) / 3.0;
+    const double area =
+        0.5 * ((x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]));
+    for (int k = 0; k < 3; ++k) m->A[id[k]] += area / 3.0;
+    for (int k = 0; k < 3; ++k) {
+      const int u = k, v = (k + 1) % 3;
+      const int64_t e = find_edge(m, first, id[u], id[v]);
+      const double mx = 0.5 * (x[u] + x[v]), my = 0.5 * (y[u] + y[v]);
+      const double dx = cx - mx, dy = cy - my;
+      double nxv = dy, nyv = -dx;
+      /* direction a -> b, a the smaller node id */
+      const int ia = (id[u] < id[v]) ? u : v, ib = (ia == u) ? v : u;
+      const double ex = x[ib] - x[ia], ey = y[ib] - y[ia];
+      if (nxv * ex + nyv * ey < 0.0) { nxv = -nxv; nyv = -nyv; }
+      m->S[2 * e + 0] += nxv;
+      m->S[2 * e + 1] += nyv;
+    }
+  }
+
+  /* --- polar closure -----------------------------------------------------
+   * The dual cells of the first and last parallel extend to lat = +-pi/2.
+   * Each edge along a polar parallel gains the straight segment from its
+   * midpoint to the pole line; each polar node gains the rectangle
+   * dlon0 x (pi/2 - |lat0|); its face on the pole line (length dlon0,
+   * outward normal (0, sigma dlon0)) is carried by the node's pole edge,
+   * which pairs it with the node half-way round the same parallel.       */
+  const double dlon0 = 2.0 * ORC_PI / 20.0;
+  m->npole = 20;
+  m->pole_edge = (int32_t *)malloc(sizeof(int32_t) * 2 * m->npole);
+  m->pole_normal = (double *)malloc(sizeof(double) * m->npole);
+  for (int side = 0; side < 2; ++side) {
+    const int j = side == 0 ? 0 : nr - 1;
+    const double sigma = side == 0 ? 1.0 : -1.0;
+    const int64_t off = m->ring_off[j];
+    const int n = m->nx[j];
+    const double th = m->lat[off];
+    const double ext = 0.5 * ORC_PI - fabs(th);
+    for (int i = 0; i < n; ++i) {
+      const int32_t p = (int32_t)(off + i), q = (int32_t)(off + (i + 1) % n);
+      const int64_t e = find_edge(m, first, p, q);
+      const int32_t a = m->edge[2 * e], b = m->edge[2 * e + 1];
+      const double ex = unwrap(m->lon[b], m->lon[a]) - m->lon[a];
+      /* segment from the midpoint straight to the pole line */
+      const double dy = sigma * ext; /* d = (0, dy) */
+      double nxv = dy, nyv = 0.0;
+      if (nxv * ex < 0.0) nxv = -nxv;
+      m->S[2 * e + 0] += nxv;
+      m->S[2 * e + 1] += nyv;
+      m->A[p] += dlon0 * ext;
+    }
+    for (int i = 0; i < n / 2; ++i) {
+      const int k = side * (n / 2) + i;
+      m->pole_edge[2 * k + 0] = (int32_t)(off + i);
+      m->pole_edge[2 * k + 1] = (int32_t)(off + i + n / 2);
+      m->pole_normal[k] = sigma * dlon0;
+    }
+  }
+
+  /* physical dual volume with the nodal metric: V_i = R^2 cos(lat_i) A_i */
+  m->vol = (double *)malloc(sizeof(double) * V);
+  for (int64_t i = 0; i < V; ++i) m->vol[i] = R * R * m->coslat[i] * m->A[i];
+
+  /* --- the oracle's own node -> edge lists (ascending edge id) ---------- */
+  m->adj_ptr = (int64_t *)calloc((size_t)(V + 1), sizeof(int64_t));
+  m->adj_edge = (int32_t *)malloc(sizeof(int32_t) * 2 * E);
+  for (int64_t e = 0; e < E; ++e) {
+    m->adj_ptr[m->edge[2 * e] + 1]++;
+    m->adj_ptr[m->edge[2 * e + 1] + 1]++;
+  }
+  for (int64_t i = 0; i < V; ++i) m->adj_ptr[i + 1] += m->adj_ptr[i];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * V);
+  for (int64_t i = 0; i < V; ++i) fill[i] = m->adj_ptr[i];
+  for (int64_t e = 0; e < E; ++e) {
+    m->adj_edge[fill[m->edge[2 * e]]++] = (int32_t)e;
+    m->adj_edge[fill[m->edge[2 * e + 1]]++] = (int32_t)e;
+  }
+  free(fill);
+  m->pole_of = (int32_t *)malloc(sizeof(int32_t) * V);
+  for (int64_t i = 0; i < V; ++i) m->pole_of[i] = -1;
+  for (int k = 0; k < m->npole; ++k) {
+    m->pole_of[m->pole_edge[2 * k]] = k;
+    m->pole_of[m->pole_edge[2 * k + 1]] = k;
+  }
+  free(first);
+  return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Getters (copy-out) for the tests                                          */
+/* ------------------------------------------------------------------------ */
+void orc_mesh_sizes(const orc_mesh *m, int64_t *out) {
+  out[0] = m->V; out[1] = m->E; out[2] = m->F; out[3] = m->npole;
+  out[4] = m->nrings; out[5] = m->N;
+}
+void orc_mesh_copy(const orc_mesh *m, int32_t *nx, int64_t *ring_off,
+                   double *lon, double *lat, int32_t *tri, int32_t *edge,
+                   double *S, double *A, double *vol, int32_t *pole_edge,
+                   double *pole_normal) {
+  if (nx) memcpy(nx, m->nx, sizeof(int32_t) * m->nrings);
+  if (ring_off) memcpy(ring_off, m->ring_off, sizeof(int64_t) * (m->nrings + 1));
+  if (lon) memcpy(lon, m->lon, sizeof(double) * m->V);
+  if (lat) memcpy(lat, m->lat, sizeof(double) * m->V);
+  if (tri) memcpy(tri, m->tri, sizeof(int32_t) * 3 * m->F);
+  if (edge) memcpy(edge, m->edge, sizeof(int32_t) * 2 * m->E);
+  if (S) memcpy(S, m->S, sizeof(double) * 2 * m->E);
+  if (A) memcpy(A, m->A, sizeof(double) * m->V);
+  if (vol) memcpy(vol, m->vol, sizeof(double) * m->V);
+  if (pole_edge) memcpy(pole_edge, m->pole_edge, sizeof(int32_t) * 2 * m->npole);
+  if (pole_normal) memcpy(pole_normal, m->pole_normal, sizeof(double) * m->npole);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level chunking: threads own disjoint level ranges.                        */
+/* ------------------------------------------------------------------------ */
+static int n_chunks(int nlev) {
+  int nt = 1;
+#ifdef _OPENMP
+  nt = omp_get_max_threads();
+#endif
+  return nt < nlev ? nt : nlev;
+}
+
+int orc_threads_used(int nlev) { return n_chunks(nlev); }
+
+/* ------------------------------------------------------------------------ */
+/* Gradient.  For every edge e = (a, b) and level k the edge value is        */
+/* phi_e = (phi_a + phi_b)/2; the flux S_e phi_e is added to a and taken     */
+/* from b.  Pole edges add sigma dlon0 (phi_a + phi_b)/2 to the lat          */
+/* component of BOTH their nodes (each node's own face on the pole line).   */
+/* Output: physical components (zonal, meridional):                          */
+/*   grad_lon = G_lon / (R cos(lat_i) A_i),   grad_lat = G_lat / (R A_i).    */
+/* f: [V][nlev];  out: [V][nlev][2].                                         */
+/* ------------------------------------------------------------------------ */
+int orc_gradient(const orc_mesh *m, int nlev, const double *f, double *out) {
+  if (!m || nlev < 1 || !f || !out) return -1;
+  const int64_t V = m->V, E = m->E;
+  const int nc = n_chunks(nlev);
+  memset(out, 0, sizeof(double) * (size_t)(V * nlev * 2));
+#pragma omp parallel for schedule(static, 1)
+  for (int c = 0; c < nc; ++c) {
+    const int k0 = (int)((int64_t)c * nlev / nc);
+    const int k1 = (int)((int64_t)(c + 1) * nlev / nc);
+    for (int64_t e = 0; e < E; ++e) {
+      const int64_t a = m->edge[2 * e], b = m->edge[2 * e + 1];
+      const double Sx = m->S[2 * e], Sy = m->S[2 * e + 1];
+      for (int k = k0; k < k1; ++k) {
+        const double fe = 0.5 * (f[a * nlev + k] + f[b * nlev + k]);
+        const double Fx = Sx * fe, Fy = Sy * fe;
+        out[(a * nlev + k) * 2 + 0] += Fx;
+        out[(a * nlev + k) * 2 + 1] += Fy;
+        out[(b * nlev + k) * 2 + 0] -= Fx;
+        out[(b * nlev + k) * 2 + 1] -= Fy;
+      }
+    }
+    for (int p = 0; p < m->npole; ++p) {
+      const int64_t a = m->pole_edge[2 * p], b = m->pole_edge[2 * p + 1];
+      const double Sy = m->pole_normal[p];
+      for (int k = k0; k < k1; ++k) {
+        const double fe = 0.5 * (f[a * nlev + k] + f[b * nlev + k]);
+        out[(a * nlev + k) * 2 + 1] += Sy * fe;
+        out[(b * nlev + k) * 2 + 1] += Sy * fe;
+      }
+    }
+    for (int64_t i = 0; i < V; ++i) {
+      const double sx = m->R * m->coslat[i] * m->A[i];
+      const double sy = m->R * m->A[i];
+      for (int k = k0; k < k1; ++k) {
+        out[(i * nlev + k) * 2 + 0] /= sx;
+        out[(i * nlev + k) * 2 + 1] /= sy;
+      }
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Divergence of a physical vector field (u east, v north), [V][nlev][2].   */
+/* W = v cos(lat) is formed at the nodes; the edge flux is                  */
+/* S_lon u_e + S_lat W_e with edge averages u_e, W_e.  Pole edges carry     */
+/* nothing: W vanishes on the pole line.                                     */
+/*   div_i = sum_e s_ie flux_e / (R cos(lat_i) A_i).                         */
+/* Curl (radial component) is the same with (v, -u cos(lat)).               */
+/* ------------------------------------------------------------------------ */
+static int div_or_curl(const orc_mesh *m, int nlev, const double *uv,
+                       double *out, int curl) {
+  if (!m || nlev < 1 || !uv || !out) return -1;
+  const int64_t V = m->V, E = m->E;
+  const int nc = n_chunks(nlev);
+  memset(out, 0, sizeof(double) * (size_t)(V * nlev));
+#pragma omp parallel for schedule(static, 1)
+  for (int c = 0; c < nc; ++c) {
+    const int k0 = (int)((int64_t)c * nlev / nc);
+    const int k1 = (int)((int64_t)(c + 1) * nlev / nc);
+    for (int64_t e = 0; e < E; ++e) {
+      const int64_t a = m->edge[2 * e], b = m->edge[2 * e + 1];
+      const double Sx = m->S[2 * e], Sy = m->S[2 * e + 1];
+      const double ca = m->coslat[a], cb = m->coslat[b];
+      for (int k = k0; k < k1; ++k) {
+        const double ua = uv[(a * nlev + k) * 2], va = uv[(a * nlev + k) * 2 + 1];
+        const double ub = uv[(b * nlev + k) * 2], vb = uv[(b * nlev + k) * 2 + 1];
+        double flux;
+        if (!curl) {
+          const double ue = 0.5 * (ua + ub);
+          const double We = 0.5 * (va * ca + vb * cb);
+          flux = Sx * ue + Sy * We;
+        } else {
+          const double ve = 0.5 * (va + vb);
+          const double Ze = 0.5 * (ua * ca + ub * cb);
+          flux = Sx * ve - Sy * Ze;
+        }
+        out[a * nlev + k] += flux;
+        out[b * nlev + k] -= flux;
+      }
+    }
+    for (int64_t i = 0; i < V; ++i) {
+      const double s = m->R * m->coslat[i] * m->A[i];
+      for (int k = k0; k < k1; ++k) out[i * nlev + k] /= s;
+    }
+  }
+  return 0;
+}
+
+int orc_divergence(const orc_mesh *m, int nlev, const double *uv, double *out) {
+  return div_or_curl(m, nlev, uv, out, 0);
+}
+int orc_curl(const orc_mesh *m, int nlev, const double *uv, double *out) {
+  return div_or_curl(m, nlev, uv, out, 1);
+}
+
+/* Laplacian = divergence of the gradient, both discrete (two passes). */
+int orc_laplacian(const orc_mesh *m, int nlev, const double *f, double *out) {
+  if (!m || nlev < 1 || !f || !out) return -1;
+  double *g = (double *)malloc(sizeof(double) * (size_t)(m->V * nlev * 2));
+  if (!g) return -2;
+  int rc = orc_gradient(m, nlev, f, g);
+  if (rc == 0) rc = orc_divergence(m, nlev, g, out);
+  free(g);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampled evaluation: the same operators at selected nodes only, summing    */
+/* over the node's own edges in ascending edge id and the pole edge last --  */
+/* the order in which the full edge loop above reaches each accumulator, so  */
+/* the sampled values are bitwise equal to the full ones.                     */
+/* ------------------------------------------------------------------------ */
+static void grad_one(const orc_mesh *m, int nlev, const double *f, int64_t i,
+                     double *o /* [nlev][2] */) {
+  for (int k = 0; k < nlev; ++k) { o[2 * k] = 0.0; o[2 * k + 1] = 0.0; }
+  for (int64_t r = m->adj_ptr[i]; r < m->adj_ptr[i + 1]; ++r) {
+    const int64_t e = m->adj_edge[r];
+    const int64_t a = m->edge[2 * e], b = m->edge[2 * e + 1];
+    const double Sx = m->S[2 * e], Sy = m->S[2 * e + 1];
+    for (int k = 0; k < nlev; ++k) {
+      const double fe = 0.5 * (f[a * nlev + k] + f[b * nlev + k]);
+      const double Fx = Sx * fe, Fy = Sy * fe;
+      if (a == i) { o[2 * k] += Fx; o[2 * k + 1] += Fy; }
+      else        { o[2 * k] -= Fx; o[2 * k + 1] -= Fy; }
+    }
+  }
+  const int p = m->pole_of[i];
+  if (p >= 0) {
+    const int64_t a = m->pole_edge[2 * p], b = m->pole_edge[2 * p + 1];
+    const double Sy = m->pole_normal[p];
+    for (int k = 0; k < nlev; ++k) {
+      const double fe = 0.5 * (f[a * nlev + k] + f[b * nlev + k]);
+      o[2 * k + 1] += Sy * fe;
+    }
+  }
+  const double sx = m->R * m->coslat[i] * m->A[i], sy = m->R * m->A[i];
+  for (int k = 0; k < nlev; ++k) { o[2 * k] /= sx; o[2 * k + 1] /= sy; }
+}
+
+/* uvval(n, k, c): vector component c of node n at level k, looked up through
+ * an accessor so that the Laplacian can feed sampled gradients.            */
+typedef double (*uv_get)(const void *ctx, int64_t n, int k, int c);
+
+static void divcurl_one(const orc_mesh *m, int nlev, uv_get get,
+                        const void *ctx, int64_t i, double *o, int curl) {
+  for (int k = 0; k < nlev; ++k) o[k] = 0.0;
+  for (int64_t r = m->adj_ptr[i]; r < m->adj_ptr[i + 1]; ++r) {
+    const int64_t e = m->adj_edge[r];
+    const int64_t a = m->edge[2 * e], b = m->edge[2 * e + 1];
+    const double Sx = m->S[2 * e], Sy = m->S[2 * e + 1];
+    const double ca = m->coslat[a], cb = m->coslat[b];
+    for (int k = 0; k < nlev; ++k) {
+      const double ua = get(ctx, a, k, 0), va = get(ctx, a, k, 1);
+      const double ub = get(ctx, b, k, 0), vb = get(ctx, b, k, 1);
+      double flux;
+      if (!curl) {
+        const double ue = 0.5 * (ua + ub);
+        const double We = 0.5 * (va * ca + vb * cb);
+        flux = Sx * ue + Sy * We;
+      } else {
+        const double ve = 0.5 * (va + vb);
+        const double Ze = 0.5 * (ua * ca + ub * cb);
+        flux = Sx * ve - Sy * Ze;
+      }
+      if (a == i) o[k] += flux; else o[k] -= flux;
+    }
+  }
+  const double s = m->R * m->coslat[i] * m->A[i];
+  for (int k = 0; k < nlev; ++k) o[k] /= s;
+}
+
+typedef struct { const double *uv; int nlev; } dense_ctx;
+static double dense_get(const void *ctx, int64_t n, int k, int c) {
+  const dense_ctx *d = (const dense_ctx *)ctx;
+  return d->uv[(n * d->nlev + k) * 2 + c];
+}
+
+static int check_sel(const orc_mesh *m, int64_t nsel, const int64_t *sel) {
+  for (int64_t s = 0; s < nsel; ++s)
+    if (sel[s] < 0 || sel[s] >= m->V) return -1;
+  return 0;
+}
+
+int orc_gradient_at(const orc_mesh *m, int nlev, const double *f,
+                    int64_t nsel, const int64_t *sel, double *out) {
+  if (!m || nlev < 1 || !f || !out || (nsel && !sel) || check_sel(m, nsel, sel))
+    return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < nsel; ++s)
+    grad_one(m, nlev, f, sel[s], out + s * nlev * 2);
+  return 0;
+}
+
+static int divcurl_at(const orc_mesh *m, int nlev, const double *uv,
+                      int64_t nsel, const int64_t *sel, double *out, int curl) {
+  if (!m || nlev < 1 || !uv || !out || (nsel && !sel) || check_sel(m, nsel, sel))
+    return -1;
+  dense_ctx ctx = {uv, nlev};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < nsel; ++s)
+    divcurl_one(m, nlev, dense_get, &ctx, sel[s], out + s * nlev, curl);
+  return 0;
+}
+int orc_divergence_at(const orc_mesh *m, int nlev, const double *uv,
+                      int64_t nsel, const int64_t *sel, double *out) {
+  return divcurl_at(m, nlev, uv, nsel, sel, out, 0);
+}
+int orc_curl_at(const orc_mesh *m, int nlev, const double *uv, int64_t nsel,
+                const int64_t *sel, double *out) {
+  return divcurl_at(m, nlev, uv, nsel, sel, out, 1);
+}
+
+/* Sampled Laplacian: gradients at every node of the sampled nodes' 1-ring,
+ * then the divergence of those gradients at the sampled nodes.            */
+typedef struct { const int64_t *slot; const double *g; int nlev; } ring_ctx;
+static double ring_get(const void *ctx, int64_t n, int k, int c) {
+  const ring_ctx *r = (const ring_ctx *)ctx;
+  return r->g[(r->slot[n] * r->nlev + k) * 2 + c];
+}
+
+int orc_laplacian_at(const orc_mesh *m, int nlev, const double *f,
+                     int64_t nsel, const int64_t *sel, double *out) {
+  if (!m || nlev < 1 || !f || !out || (nsel && !sel) || check_sel(m, nsel, sel))
+    return -1;
+  int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * m->V);
+  if (!slot) return -2;
+  for (int64_t i = 0; i < m->V; ++i) slot[i] = -1;
+  int64_t nring = 0;
+  for (int64_t s = 0; s < nsel; ++s) {
+    const int64_t i = sel[s];
+    if (slot[i] < 0) slot[i] = nring++;
+    for (int64_t r = m->adj_ptr[i]; r < m->adj_ptr[i + 1]; ++r) {
+      const int64_t e = m->adj_edge[r];
+      const int64_t o = m->edge[2 * e] == i ? m->edge[2 * e + 1] : m->edge[2 * e];
+      if (slot[o] < 0) slot[o] = nring++;
+    }
+  }
+  int64_t *nodes = (int64_t *)malloc(sizeof(int64_t) * (nring ? nring : 1));
+  double *g = (double *)malloc(sizeof(double) * (size_t)((nring ? nring : 1) * nlev * 2));
+  if (!nodes || !g) { free(slot); free(nodes); free(g); return -2; }
+  for (int64_t i = 0; i < m->V; ++i)
+    if (slot[i] >= 0) nodes[slot[i]] = i;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < nring; ++q) grad_one(m, nlev, f, nodes[q], g + q * nlev * 2);
+  ring_ctx ctx = {slot, g, nlev};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < nsel; ++s)
+    divcurl_one(m, nlev, ring_get, &ctx, sel[s], out + s * nlev, 0);
+  free(slot); free(nodes); free(g);
+  return 0;
+}
