@@ -1,0 +1,221 @@
+/*
+ * atlas_nabla.h -- C ABI of the MI355X (gfx950) library for the edge-based
+ * median-dual finite-volume nabla operators on the octahedral reduced
+ * Gaussian grid.
+ *
+ * Paper anchors (Atlas, ESCAPE D1.3, arXiv:1908.06091):
+ *   grid       Section 4.2.3.5, Section 4.2.3.7 and Listing 6
+ *   mesh       Section 4.3 (nodes, cells, edges; Eq. 1; block and
+ *              irregular connectivity tables; vertical levels extruded)
+ *   fields     Section 4.5 and Figure 31 (NodeColumns: a node's vertical
+ *              column is contiguous, layout [node][level]); Listing 12
+ *              (gradient output has two variables)
+ *   operators  Section 4.7, Figure 33 and Listing 12 (fvm::Method and
+ *              Nabla: gradient, divergence, curl, Laplacian)
+ *   device     Section 5 (connectivity and fields resident on the device,
+ *              copied to it once)
+ *   C layer    Section 4.1 and Figure 3 (an opaque handle to a native object
+ *              driven through plain C functions)
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an atlas_status; ATLAS_OK (0) is success.  On
+ *     failure nothing has been enqueued and atlas_last_error() returns a
+ *     thread-local message describing the first problem found.
+ *   - Field pointers are DEVICE pointers owned by the caller.  Scalar
+ *     fields are [nnodes][nlev]; vector fields are [nnodes][nlev][2] with
+ *     the two components interleaved (zonal, meridional).  Pointers must be
+ *     aligned to the element size and input and output must not overlap.
+ *   - Operator calls only enqueue work on `stream` (0 = the null stream);
+ *     they never synchronise the host.  Buffers must stay valid until the
+ *     stream has passed the call.  An asynchronous device fault surfaces at
+ *     the caller's next synchronisation.
+ *   - Every operator is deterministic: each node sums its own edges in a
+ *     fixed order without atomics, so repeated calls give identical bits,
+ *     whatever the launch shape.
+ */
+#ifndef ATLAS_NABLA_H
+#define ATLAS_NABLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ATLAS_OK = 0,
+  ATLAS_EINVAL = -1,   /* invalid argument or malformed mesh description  */
+  ATLAS_ENOMEM = -2,   /* host or device allocation failed / over budget  */
+  ATLAS_EDEVICE = -3,  /* a HIP runtime call failed                        */
+  ATLAS_EBUSY = -4,    /* resource in use (e.g. freeing a registered mesh) */
+  ATLAS_ESTATE = -5,   /* call not valid in the object's current state    */
+  ATLAS_ETIMEOUT = -6  /* a bounded wait expired                           */
+} atlas_status;
+
+typedef enum { ATLAS_F32 = 0, ATLAS_F64 = 1 } atlas_dtype;
+
+typedef enum {
+  ATLAS_OP_GRADIENT = 0,
+  ATLAS_OP_DIVERGENCE = 1,
+  ATLAS_OP_CURL = 2,
+  ATLAS_OP_LAPLACIAN = 3
+} atlas_op;
+
+typedef struct atlas_mesh_s *atlas_mesh_t;
+
+/*
+ * Host description of a median-dual mesh (all pointers are HOST pointers,
+ * read only; FP64 geometry in the (lon, lat) plane, radians).
+ *
+ *   nnodes, lon, lat, cos_lat   node coordinates and cos(lat), [nnodes]
+ *   nrings, ring_off            optional: nodes grouped by parallel,
+ *                               ring_off[nrings+1]; 0 / NULL = derive the
+ *                               parallels from runs of equal latitude
+ *   nedges, edge2node           [nedges][2], edge2node[e][0] < [e][1]
+ *   node2edge_ptr, node2edge    CSR node -> edge, [nnodes+1] and [2*nedges],
+ *                               each row in ascending edge id (this is the
+ *                               summation order of every node)
+ *   node2edge_sign              [2*nedges], +1 if the node is edge2node[e][0],
+ *                               -1 if it is edge2node[e][1]
+ *   dual_volumes                [nnodes] physical dual volumes
+ *                               V_i = R^2 cos(lat_i) A_i
+ *   dual_normals                [nedges][2] dual-face normal (S_lon, S_lat),
+ *                               oriented from edge2node[e][0] to [e][1]
+ *   npole_edges, pole_edges     [npole_edges][2] pole edges: pairs of nodes
+ *                               on the first or last parallel half-way round
+ *   pole_normals                [npole_edges] lat component of the pole-face
+ *                               normal carried by each pole edge (+-2pi/nx)
+ *   radius                      sphere radius R
+ */
+typedef struct {
+  int64_t nnodes;
+  const double *lon, *lat, *cos_lat;
+  int32_t nrings;
+  const int64_t *ring_off;
+  int64_t nedges;
+  const int32_t *edge2node;
+  const int64_t *node2edge_ptr;
+  const int32_t *node2edge;
+  const int8_t *node2edge_sign;
+  const double *dual_volumes;
+  const double *dual_normals;
+  int64_t npole_edges;
+  const int32_t *pole_edges;
+  const double *pole_normals;
+  double radius;
+} atlas_mesh_desc;
+
+/* Sizes of an uploaded mesh. */
+typedef struct {
+  int64_t nnodes, nedges, nincidences, npole_edges, ntiles;
+  int32_t nrings, max_degree;
+  size_t device_bytes;      /* device memory held by the mesh store        */
+  double geometry_bytes_per_call; /* mesh bytes one operator pass reads   */
+} atlas_mesh_info;
+
+/* ---------------------------------------------------------------------- */
+/* Host problem setup (Section 4.2.3.7 grid, Section 4.3 mesh generator,   */
+/* Section 4.7 fvm::Method geometry).                                      */
+/* ---------------------------------------------------------------------- */
+
+/* Build the description of grid O<N> (2N Gaussian parallels with
+ * 20 + 4j points, mirrored) triangulated between consecutive parallels,
+ * with its median-dual geometry on a sphere of radius `radius`.  The arrays
+ * are owned by the library; release them with atlas_mesh_desc_free.
+ * Errors: ATLAS_EINVAL for N < 1, N > 8192 or radius <= 0; ATLAS_ENOMEM. */
+atlas_status atlas_mesh_desc_octahedral(int32_t N, double radius,
+                                        atlas_mesh_desc **out);
+atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc);
+
+/* ---------------------------------------------------------------------- */
+/* Device mesh store (Section 5: connectivity and geometry resident on     */
+/* the device, copied once).                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Validate `desc`, copy it to the current device (synchronous) and derive
+ * the per-node scales.  The host arrays may be freed on return.  The mesh
+ * belongs to the library until atlas_mesh_free.
+ * Errors: ATLAS_EINVAL (malformed description: counts, index ranges, CSR
+ * order, signs, non-positive volumes, non-finite geometry), ATLAS_ENOMEM,
+ * ATLAS_EDEVICE. */
+atlas_status atlas_mesh_upload(const atlas_mesh_desc *desc, atlas_mesh_t *out);
+
+/* Convenience: atlas_mesh_desc_octahedral + atlas_mesh_upload. */
+atlas_status atlas_mesh_create_octahedral(int32_t N, double radius,
+                                          atlas_mesh_t *out);
+
+/* Release the device store.  ATLAS_EBUSY if a server still holds it. */
+atlas_status atlas_mesh_free(atlas_mesh_t mesh);
+atlas_status atlas_mesh_get_info(atlas_mesh_t mesh, atlas_mesh_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* Operators (Section 4.7, Figure 33, Listing 12).                          */
+/*   gradient   f [V][nlev]       -> out [V][nlev][2] (zonal, meridional)   */
+/*   divergence (u,v) [V][nlev][2] -> out [V][nlev]                          */
+/*   curl       (u,v) [V][nlev][2] -> out [V][nlev] (radial component)       */
+/*   laplacian  f [V][nlev]       -> out [V][nlev], = divergence(gradient)  */
+/* dtype ATLAS_F64: FP64 fields and arithmetic.  dtype ATLAS_F32: FP32      */
+/* fields, FP64 geometry, FP32 edge terms with a compensated (Kahan) node   */
+/* sum, final scaling in FP64.                                              */
+/* Errors (nothing enqueued): ATLAS_EINVAL for a NULL or misaligned pointer,*/
+/* nlev < 1, overlapping input/output, unknown dtype; ATLAS_EDEVICE if the  */
+/* launch fails.                                                            */
+/* ---------------------------------------------------------------------- */
+atlas_status atlas_nabla_gradient(atlas_mesh_t mesh, const void *f, int32_t nlev,
+                                  atlas_dtype dtype, void *out, hipStream_t stream);
+atlas_status atlas_nabla_divergence(atlas_mesh_t mesh, const void *uv,
+                                    int32_t nlev, atlas_dtype dtype, void *out,
+                                    hipStream_t stream);
+atlas_status atlas_nabla_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
+                              atlas_dtype dtype, void *out, hipStream_t stream);
+/* workspace: device buffer of atlas_laplacian_workspace_bytes() bytes, or
+ * NULL to use a workspace the mesh keeps (grown on first use with
+ * hipMalloc; calls that share it on different streams must be ordered by
+ * the caller). */
+atlas_status atlas_nabla_laplacian(atlas_mesh_t mesh, const void *f, int32_t nlev,
+                                   atlas_dtype dtype, void *out, void *workspace,
+                                   hipStream_t stream);
+size_t atlas_laplacian_workspace_bytes(atlas_mesh_t mesh, int32_t nlev,
+                                       atlas_dtype dtype);
+
+/* ---------------------------------------------------------------------- */
+/* Launch shapes.  Every shape gives bitwise-identical results.            */
+/* ---------------------------------------------------------------------- */
+typedef enum {
+  ATLAS_VARIANT_AUTO = 0,   /* autotuned choice (or built-in default)      */
+  ATLAS_VARIANT_COLUMN = 1, /* one wavefront per node, lanes over levels   */
+  ATLAS_VARIANT_FLAT = 2,   /* lanes over flattened (node, level) pairs    */
+  ATLAS_VARIANT_FLUX = 3    /* two kernels: edge fluxes into an [E][nlev]
+                               buffer (EdgeColumns-like), then the gather  */
+} atlas_variant;
+
+typedef struct {
+  int32_t variant;          /* atlas_variant                                */
+  int32_t block_threads;    /* 64, 128, 256, 512 or 1024                    */
+  int32_t nodes_per_block;  /* column/flat: processing positions per block  */
+} atlas_launch;
+
+/* Apply `op` with an explicit launch shape (tests, autotuner).  For
+ * ATLAS_VARIANT_FLUX, `workspace` must hold atlas_flux_workspace_bytes();
+ * for the Laplacian it must hold the larger of the two requirements.
+ * shape == NULL is the same as the named entry points. */
+atlas_status atlas_nabla_apply(atlas_mesh_t mesh, atlas_op op, const void *in,
+                               int32_t nlev, atlas_dtype dtype, void *out,
+                               void *workspace, const atlas_launch *shape,
+                               hipStream_t stream);
+size_t atlas_flux_workspace_bytes(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
+                                  atlas_dtype dtype);
+
+/* Thread-local description of the last failure on this thread. */
+const char *atlas_last_error(void);
+
+/* Library version string. */
+const char *atlas_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ATLAS_NABLA_H */

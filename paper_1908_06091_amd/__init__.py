@@ -1,0 +1,213 @@
+"""Python binding of ``libatlas_nabla.so`` (MI355X / gfx950).
+
+Argument marshalling only: every operator runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  There is no CPU
+fallback: without the built library every call raises.
+
+Names follow the C ABI in ``include/atlas_nabla.h`` (Atlas, Section 4.7 /
+Listing 12: ``Nabla.gradient(in, out)`` and friends on NodeColumns fields,
+Section 4.5 / Figure 31 layout [node][level]).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+from . import _abi
+from ._abi import (ATLAS_F32, ATLAS_F64, ATLAS_OP_CURL, ATLAS_OP_DIVERGENCE,  # noqa: F401
+                   ATLAS_OP_GRADIENT, ATLAS_OP_LAPLACIAN, VARIANT_AUTO, VARIANT_COLUMN,
+                   VARIANT_FLAT, VARIANT_FLUX, AtlasError, Launch, MeshDesc, MeshInfo)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libatlas_nabla.so")
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    from .build import build as _build
+    return _build(verbose=verbose)
+
+
+def lib():
+    """The loaded library (built first if no library is present)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                build()
+            _lib = _abi.bind(ctypes.CDLL(LIB_PATH))
+        return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise AtlasError(rc, lib().atlas_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return ATLAS_F64
+    if t.dtype == torch.float32:
+        return ATLAS_F32
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, what):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mesh_desc_octahedral(N: int, radius: float = 1.0) -> dict:
+    """The library's host description of O<N> (grid, triangulation, edges,
+    signed node->edge table, median-dual geometry), copied into numpy."""
+    L = lib()
+    p = ctypes.POINTER(MeshDesc)()
+    _check(L.atlas_mesh_desc_octahedral(int(N), float(radius), ctypes.byref(p)))
+    try:
+        return _abi.desc_to_numpy(p.contents)
+    finally:
+        L.atlas_mesh_desc_free(p)
+
+
+class Mesh:
+    """A mesh resident on the current device (``atlas_mesh_upload``)."""
+
+    def __init__(self, N: int | None = None, radius: float = 1.0, *, desc: dict | None = None):
+        L = lib()
+        self._lib = L
+        self._h = ctypes.c_void_p()
+        if desc is not None:
+            c_desc, self._keep = _abi.numpy_to_desc(desc)
+            _check(L.atlas_mesh_upload(ctypes.byref(c_desc), ctypes.byref(self._h)))
+        else:
+            _check(L.atlas_mesh_create_octahedral(int(N), float(radius), ctypes.byref(self._h)))
+        info = MeshInfo()
+        _check(L.atlas_mesh_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+        self.nnodes = int(info.nnodes)
+        self.nedges = int(info.nedges)
+        self.N = N
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(self._lib.atlas_mesh_free(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shape helpers ------------------------------------------------------
+    def _nlev_scalar(self, t):
+        if t.dim() == 1:
+            n = 1
+        elif t.dim() == 2:
+            n = t.shape[1]
+        else:
+            raise ValueError("scalar field must be [V] or [V, nlev]")
+        if t.shape[0] != self.nnodes:
+            raise ValueError(f"field has {t.shape[0]} nodes, mesh has {self.nnodes}")
+        return int(n)
+
+    def _nlev_vector(self, t):
+        if t.dim() == 2 and t.shape[1] == 2:
+            n = 1
+        elif t.dim() == 3 and t.shape[2] == 2:
+            n = t.shape[1]
+        else:
+            raise ValueError("vector field must be [V, 2] or [V, nlev, 2]")
+        if t.shape[0] != self.nnodes:
+            raise ValueError(f"field has {t.shape[0]} nodes, mesh has {self.nnodes}")
+        return int(n)
+
+    # -- operators ------------------------------------------------------------
+    def apply(self, op: int, x, out=None, *, workspace=None, launch: Launch | None = None,
+              stream=None):
+        torch = _torch()
+        vec_in = op in (ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL)
+        nlev = self._nlev_vector(x) if vec_in else self._nlev_scalar(x)
+        if out is None:
+            shape = (self.nnodes, nlev, 2) if op == ATLAS_OP_GRADIENT else (self.nnodes, nlev)
+            out = torch.empty(shape, dtype=x.dtype, device=x.device)
+        if out.dtype != x.dtype:
+            raise TypeError("output dtype must match the input dtype")
+        ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+        lp = ctypes.byref(launch) if launch is not None else None
+        _check(self._lib.atlas_nabla_apply(self._h, int(op), _dev_ptr(x, "input"), nlev,
+                                           _dtype_code(x), _dev_ptr(out, "output"), ws, lp,
+                                           _stream(stream)))
+        return out
+
+    def gradient(self, f, out=None, stream=None):
+        nlev = self._nlev_scalar(f)
+        if out is None:
+            out = _torch().empty((self.nnodes, nlev, 2), dtype=f.dtype, device=f.device)
+        _check(self._lib.atlas_nabla_gradient(self._h, _dev_ptr(f, "f"), nlev, _dtype_code(f),
+                                              _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def divergence(self, uv, out=None, stream=None):
+        nlev = self._nlev_vector(uv)
+        if out is None:
+            out = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        _check(self._lib.atlas_nabla_divergence(self._h, _dev_ptr(uv, "uv"), nlev,
+                                                _dtype_code(uv), _dev_ptr(out, "out"),
+                                                _stream(stream)))
+        return out
+
+    def curl(self, uv, out=None, stream=None):
+        nlev = self._nlev_vector(uv)
+        if out is None:
+            out = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        _check(self._lib.atlas_nabla_curl(self._h, _dev_ptr(uv, "uv"), nlev, _dtype_code(uv),
+                                          _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def laplacian(self, f, out=None, workspace=None, stream=None):
+        nlev = self._nlev_scalar(f)
+        if out is None:
+            out = _torch().empty((self.nnodes, nlev), dtype=f.dtype, device=f.device)
+        ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+        _check(self._lib.atlas_nabla_laplacian(self._h, _dev_ptr(f, "f"), nlev, _dtype_code(f),
+                                               _dev_ptr(out, "out"), ws, _stream(stream)))
+        return out
+
+    def laplacian_workspace_bytes(self, nlev: int, dtype_code: int) -> int:
+        return int(self._lib.atlas_laplacian_workspace_bytes(self._h, int(nlev), int(dtype_code)))
+
+    def flux_workspace_bytes(self, op: int, nlev: int, dtype_code: int) -> int:
+        return int(self._lib.atlas_flux_workspace_bytes(self._h, int(op), int(nlev),
+                                                        int(dtype_code)))
+
+
+__all__ = ["Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
+           "ATLAS_F32", "ATLAS_F64", "ATLAS_OP_GRADIENT", "ATLAS_OP_DIVERGENCE",
+           "ATLAS_OP_CURL", "ATLAS_OP_LAPLACIAN", "VARIANT_AUTO", "VARIANT_COLUMN",
+           "VARIANT_FLAT", "VARIANT_FLUX"]

@@ -1,0 +1,148 @@
+"""ctypes declarations mirroring ``include/atlas_nabla.h``."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+ATLAS_F32, ATLAS_F64 = 0, 1
+ATLAS_OP_GRADIENT, ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL, ATLAS_OP_LAPLACIAN = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_COLUMN, VARIANT_FLAT, VARIANT_FLUX = 0, 1, 2, 3
+
+STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EDEVICE",
+          -4: "ATLAS_EBUSY", -5: "ATLAS_ESTATE", -6: "ATLAS_ETIMEOUT"}
+
+
+class AtlasError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("nnodes", ctypes.c_int64), ("lon", _dp), ("lat", _dp), ("cos_lat", _dp),
+        ("nrings", ctypes.c_int32), ("ring_off", _i64p),
+        ("nedges", ctypes.c_int64), ("edge2node", _i32p),
+        ("node2edge_ptr", _i64p), ("node2edge", _i32p), ("node2edge_sign", _i8p),
+        ("dual_volumes", _dp), ("dual_normals", _dp),
+        ("npole_edges", ctypes.c_int64), ("pole_edges", _i32p), ("pole_normals", _dp),
+        ("radius", ctypes.c_double),
+    ]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [
+        ("nnodes", ctypes.c_int64), ("nedges", ctypes.c_int64),
+        ("nincidences", ctypes.c_int64), ("npole_edges", ctypes.c_int64),
+        ("ntiles", ctypes.c_int64), ("nrings", ctypes.c_int32),
+        ("max_degree", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
+        ("geometry_bytes_per_call", ctypes.c_double),
+    ]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("nodes_per_block", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); every symbol the header declares
+SIGNATURES = {
+    "atlas_last_error": (ctypes.c_char_p, []),
+    "atlas_version": (ctypes.c_char_p, []),
+    "atlas_mesh_desc_octahedral": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double,
+                                                  ctypes.POINTER(ctypes.POINTER(MeshDesc))]),
+    "atlas_mesh_desc_free": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
+    "atlas_mesh_upload": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_mesh_create_octahedral": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double,
+                                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_mesh_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "atlas_mesh_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshInfo)]),
+    "atlas_nabla_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_nabla_divergence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_nabla_curl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_nabla_laplacian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "atlas_laplacian_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int32,
+                                                          ctypes.c_int]),
+    "atlas_nabla_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(Launch),
+                                         ctypes.c_void_p]),
+    "atlas_flux_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int,
+                                                     ctypes.c_int32, ctypes.c_int]),
+}
+
+
+def bind(lib):
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def desc_to_numpy(d: MeshDesc) -> dict:
+    V, E, NP = int(d.nnodes), int(d.nedges), int(d.npole_edges)
+
+    def arr(ptr, n, dt):
+        return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dt, copy=True)
+
+    out = {
+        "lon": arr(d.lon, V, np.float64), "lat": arr(d.lat, V, np.float64),
+        "cos_lat": arr(d.cos_lat, V, np.float64),
+        "edge2node": arr(d.edge2node, 2 * E, np.int32).reshape(E, 2),
+        "node2edge_ptr": arr(d.node2edge_ptr, V + 1, np.int64),
+        "node2edge": arr(d.node2edge, 2 * E, np.int32),
+        "node2edge_sign": arr(d.node2edge_sign, 2 * E, np.int8),
+        "dual_volumes": arr(d.dual_volumes, V, np.float64),
+        "dual_normals": arr(d.dual_normals, 2 * E, np.float64).reshape(E, 2),
+        "pole_edges": arr(d.pole_edges, 2 * NP, np.int32).reshape(NP, 2),
+        "pole_normals": arr(d.pole_normals, NP, np.float64),
+        "radius": float(d.radius),
+    }
+    if d.nrings > 0 and d.ring_off:
+        out["ring_off"] = arr(d.ring_off, int(d.nrings) + 1, np.int64)
+    return out
+
+
+def numpy_to_desc(a: dict):
+    """Build a MeshDesc pointing at (contiguous copies of) numpy arrays;
+    returns (desc, keepalive)."""
+    keep = {}
+
+    def ptr(name, dt, ctype):
+        x = np.ascontiguousarray(a[name], dtype=dt)
+        keep[name] = x
+        return x.ctypes.data_as(ctype)
+
+    d = MeshDesc()
+    d.nnodes = len(a["lon"])
+    d.lon = ptr("lon", np.float64, _dp)
+    d.lat = ptr("lat", np.float64, _dp)
+    d.cos_lat = ptr("cos_lat", np.float64, _dp)
+    if a.get("ring_off") is not None:
+        d.nrings = len(a["ring_off"]) - 1
+        d.ring_off = ptr("ring_off", np.int64, _i64p)
+    d.nedges = len(np.asarray(a["edge2node"]).reshape(-1, 2))
+    d.edge2node = ptr("edge2node", np.int32, _i32p)
+    d.node2edge_ptr = ptr("node2edge_ptr", np.int64, _i64p)
+    d.node2edge = ptr("node2edge", np.int32, _i32p)
+    d.node2edge_sign = ptr("node2edge_sign", np.int8, _i8p)
+    d.dual_volumes = ptr("dual_volumes", np.float64, _dp)
+    d.dual_normals = ptr("dual_normals", np.float64, _dp)
+    d.npole_edges = len(np.asarray(a["pole_normals"]))
+    d.pole_edges = ptr("pole_edges", np.int32, _i32p)
+    d.pole_normals = ptr("pole_normals", np.float64, _dp)
+    d.radius = float(a["radius"])
+    return d, keep

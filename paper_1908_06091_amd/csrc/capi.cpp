@@ -1,0 +1,277 @@
+// capi.cpp -- the extern "C" entry points of atlas_nabla.h.
+//
+// The C layer follows the pattern of Section 4.1 / Figure 3: an opaque
+// handle to a native object, driven through plain C functions that return a
+// status instead of throwing (the grid classes' valid() in Section 4.2.3).
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+
+#include "internal.h"
+
+struct atlas_mesh_s {
+  atlasx::MeshStore *store;
+};
+
+namespace atlasx {
+
+static thread_local std::string g_last_error;
+
+// host mesh descriptions handed out by atlas_mesh_desc_octahedral
+static std::mutex g_desc_mu;
+static std::unordered_map<const atlas_mesh_desc *, HostMesh *> g_descs;
+
+atlas_status fail(atlas_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+atlas_status hip_fail(hipError_t err, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(err);
+  return err == hipErrorOutOfMemory ? ATLAS_ENOMEM : ATLAS_EDEVICE;
+}
+
+atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStore **out);
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static size_t in_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
+  const size_t w = dt == ATLAS_F64 ? 8 : 4;
+  const bool vec_in = op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL;
+  return (size_t)m.d.V * nlev * w * (vec_in ? 2 : 1);
+}
+static size_t out_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
+  const size_t w = dt == ATLAS_F64 ? 8 : 4;
+  return (size_t)m.d.V * nlev * w * (op == ATLAS_OP_GRADIENT ? 2 : 1);
+}
+static size_t lapl_ws_bytes(const MeshStore &m, int nlev, atlas_dtype dt) {
+  const size_t w = dt == ATLAS_F64 ? 8 : 4;
+  return (size_t)m.d.V * nlev * 2 * w;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+// Validates every argument of an operator call before anything is enqueued.
+atlas_status check_call(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
+                        atlas_dtype dt, void *out) {
+  if (!mesh || !mesh->store) return fail(ATLAS_EINVAL, "mesh handle is NULL");
+  if (op < ATLAS_OP_GRADIENT || op > ATLAS_OP_LAPLACIAN) return fail(ATLAS_EINVAL, "unknown operator");
+  if (dt != ATLAS_F32 && dt != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
+  if (nlev < 1) return fail(ATLAS_EINVAL, "nlev must be >= 1");
+  if ((int64_t)mesh->store->d.V * nlev * 2 >= ((int64_t)1 << 31))
+    return fail(ATLAS_EINVAL, "nnodes * nlev too large");
+  if (!in || !out) return fail(ATLAS_EINVAL, "field pointer is NULL");
+  const size_t w = dt == ATLAS_F64 ? 8 : 4;
+  const size_t vw = (op == ATLAS_OP_GRADIENT) ? 2 * w : w;
+  const size_t iw = (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL) ? 2 * w : w;
+  if (!aligned(in, iw) || !aligned(out, vw))
+    return fail(ATLAS_EINVAL, "field pointer not aligned to its element size");
+  const MeshStore &m = *mesh->store;
+  if (overlap(in, in_bytes(m, op, nlev, dt), out, out_bytes(m, op, nlev, dt)))
+    return fail(ATLAS_EINVAL, "input and output overlap");
+  return ATLAS_OK;
+}
+
+static atlas_status internal_ws(MeshStore &m, size_t bytes, void **ws) {
+  std::lock_guard<std::mutex> g(m.ws_mu);
+  if (m.ws_bytes < bytes) {
+    if (m.ws) ATLASX_HIP(hipFree(m.ws));
+    m.ws = nullptr;
+    m.ws_bytes = 0;
+    hipError_t e = hipMalloc(&m.ws, bytes);
+    if (e != hipSuccess) {
+      m.ws = nullptr;
+      return fail(ATLAS_ENOMEM, "cannot allocate the operator workspace");
+    }
+    m.ws_bytes = bytes;
+  }
+  *ws = m.ws;
+  return ATLAS_OK;
+}
+
+LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
+                       atlas_dtype dt);
+
+atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
+                   atlas_dtype dt, void *out, void *workspace, const atlas_launch *shape,
+                   hipStream_t stream) {
+  atlas_status st = check_call(mesh, op, in, nlev, dt, out);
+  if (st != ATLAS_OK) return st;
+  MeshStore &m = *mesh->store;
+  LaunchShape sh = shape_from(shape, m, op, nlev, dt);
+  if (sh.block < 64 || sh.block > 1024 || (sh.block & 63) != 0)
+    return fail(ATLAS_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+  if (sh.nodes_per_block < 0) return fail(ATLAS_EINVAL, "nodes_per_block must be >= 0");
+  size_t need = 0;
+  if (op == ATLAS_OP_LAPLACIAN) need += lapl_ws_bytes(m, nlev, dt);
+  if (sh.variant == ATLAS_VARIANT_FLUX) need += flux_ws_bytes(m, op, nlev, dt);
+  void *ws = workspace;
+  if (need && !ws) {
+    st = internal_ws(m, need, &ws);
+    if (st != ATLAS_OK) return st;
+  }
+  if (ws && !aligned(ws, 16)) return fail(ATLAS_EINVAL, "workspace must be 16-byte aligned");
+  if (ws && (overlap(ws, need, in, in_bytes(m, op, nlev, dt)) ||
+             overlap(ws, need, out, out_bytes(m, op, nlev, dt))))
+    return fail(ATLAS_EINVAL, "workspace overlaps a field");
+  return launch_op(m, op, dt, in, nlev, out, ws, sh, stream);
+}
+
+}  // namespace atlasx
+
+using namespace atlasx;
+
+extern "C" {
+
+const char *atlas_last_error(void) { return g_last_error.c_str(); }
+
+const char *atlas_version(void) { return "atlas-nabla-mi355x 0.1 (gfx950)"; }
+
+atlas_status atlas_mesh_desc_octahedral(int32_t N, double radius, atlas_mesh_desc **out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (N < 1 || N > 8192) return fail(ATLAS_EINVAL, "N must be in [1, 8192]");
+  if (!(radius > 0.0)) return fail(ATLAS_EINVAL, "radius must be positive");
+  HostMesh *h = new (std::nothrow) HostMesh();
+  if (!h) return fail(ATLAS_ENOMEM, "out of host memory");
+  try {
+    build_octahedral(N, radius, *h);
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(ATLAS_ENOMEM, "out of host memory building the mesh");
+  }
+  {
+    std::lock_guard<std::mutex> g(g_desc_mu);
+    g_descs[&h->desc] = h;
+  }
+  *out = &h->desc;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc) {
+  if (!desc) return ATLAS_OK;
+  HostMesh *h = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_desc_mu);
+    auto it = g_descs.find(desc);
+    if (it == g_descs.end())
+      return fail(ATLAS_EINVAL, "description was not created by atlas_mesh_desc_octahedral");
+    h = it->second;
+    g_descs.erase(it);
+  }
+  delete h;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_mesh_upload(const atlas_mesh_desc *desc, atlas_mesh_t *out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  MeshStore *m = nullptr;
+  atlas_status st;
+  try {
+    st = upload_mesh(desc, 4, 16, &m);
+  } catch (const std::bad_alloc &) {
+    return fail(ATLAS_ENOMEM, "out of host memory during upload");
+  }
+  if (st != ATLAS_OK) return st;
+  atlas_mesh_t h = new (std::nothrow) atlas_mesh_s{m};
+  if (!h) {
+    delete m;
+    return fail(ATLAS_ENOMEM, "out of host memory");
+  }
+  *out = h;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_mesh_create_octahedral(int32_t N, double radius, atlas_mesh_t *out) {
+  atlas_mesh_desc *d = nullptr;
+  atlas_status st = atlas_mesh_desc_octahedral(N, radius, &d);
+  if (st != ATLAS_OK) return st;
+  st = atlas_mesh_upload(d, out);
+  atlas_mesh_desc_free(d);
+  return st;
+}
+
+atlas_status atlas_mesh_free(atlas_mesh_t mesh) {
+  if (!mesh) return ATLAS_OK;
+  if (mesh->store && mesh->store->serve_refs > 0)
+    return fail(ATLAS_EBUSY, "mesh is registered with a server");
+  delete mesh->store;
+  delete mesh;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_mesh_get_info(atlas_mesh_t mesh, atlas_mesh_info *info) {
+  if (!mesh || !mesh->store || !info) return fail(ATLAS_EINVAL, "NULL argument");
+  const MeshStore &m = *mesh->store;
+  info->nnodes = m.d.V;
+  info->nedges = m.d.E;
+  info->nincidences = m.nincid;
+  info->npole_edges = m.d.npole;
+  info->ntiles = m.d.ntiles;
+  info->nrings = m.nrings;
+  info->max_degree = m.max_degree;
+  info->device_bytes = m.bytes;
+  info->geometry_bytes_per_call = m.geometry_bytes;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_nabla_apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
+                               atlas_dtype dtype, void *out, void *workspace,
+                               const atlas_launch *shape, hipStream_t stream) {
+  return apply(mesh, op, in, nlev, dtype, out, workspace, shape, stream);
+}
+
+atlas_status atlas_nabla_gradient(atlas_mesh_t mesh, const void *f, int32_t nlev,
+                                  atlas_dtype dtype, void *out, hipStream_t stream) {
+  return apply(mesh, ATLAS_OP_GRADIENT, f, nlev, dtype, out, nullptr, nullptr, stream);
+}
+
+atlas_status atlas_nabla_divergence(atlas_mesh_t mesh, const void *uv, int32_t nlev,
+                                    atlas_dtype dtype, void *out, hipStream_t stream) {
+  return apply(mesh, ATLAS_OP_DIVERGENCE, uv, nlev, dtype, out, nullptr, nullptr, stream);
+}
+
+atlas_status atlas_nabla_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
+                              atlas_dtype dtype, void *out, hipStream_t stream) {
+  return apply(mesh, ATLAS_OP_CURL, uv, nlev, dtype, out, nullptr, nullptr, stream);
+}
+
+atlas_status atlas_nabla_laplacian(atlas_mesh_t mesh, const void *f, int32_t nlev,
+                                   atlas_dtype dtype, void *out, void *workspace,
+                                   hipStream_t stream) {
+  return apply(mesh, ATLAS_OP_LAPLACIAN, f, nlev, dtype, out, workspace, nullptr, stream);
+}
+
+size_t atlas_laplacian_workspace_bytes(atlas_mesh_t mesh, int32_t nlev, atlas_dtype dtype) {
+  if (!mesh || !mesh->store || nlev < 1) return 0;
+  return lapl_ws_bytes(*mesh->store, nlev, dtype);
+}
+
+size_t atlas_flux_workspace_bytes(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
+                                  atlas_dtype dtype) {
+  if (!mesh || !mesh->store || nlev < 1) return 0;
+  return flux_ws_bytes(*mesh->store, op, nlev, dtype);
+}
+
+}  // extern "C"
+
+namespace atlasx {
+LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
+                       atlas_dtype dt) {
+  LaunchShape s = default_shape(m, op, nlev, dt);
+  if (l && l->variant != ATLAS_VARIANT_AUTO) {
+    s.variant = l->variant;
+    s.block = l->block_threads;
+    s.nodes_per_block = l->nodes_per_block;
+  }
+  return s;
+}
+}  // namespace atlasx

@@ -1,0 +1,100 @@
+// internal.h -- shared declarations of the MI355X nabla library (not part of
+// the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "atlas_nabla.h"
+
+namespace atlasx {
+
+// ---------------------------------------------------------------- errors
+atlas_status fail(atlas_status code, const std::string &msg);
+atlas_status hip_fail(hipError_t err, const char *what);
+#define ATLASX_HIP(call)                                   \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return ::atlasx::hip_fail(e_, #call); \
+  } while (0)
+
+// ------------------------------------------------------- host-side mesh
+struct HostMesh {
+  int N = 0;
+  double radius = 1.0;
+  std::vector<int32_t> nx;
+  std::vector<int64_t> ring_off;
+  std::vector<double> lon, lat, cos_lat;
+  std::vector<int32_t> edge2node;
+  std::vector<int64_t> node2edge_ptr;
+  std::vector<int32_t> node2edge;
+  std::vector<int8_t> node2edge_sign;
+  std::vector<double> dual_volumes, dual_normals;
+  std::vector<int32_t> pole_edges;
+  std::vector<double> pole_normals;
+  atlas_mesh_desc desc{};
+  void fill_desc();
+};
+
+int build_octahedral(int N, double R, HostMesh &h);
+
+// ------------------------------------------------------ device mesh store
+// All "position" arrays follow the processing order: the nodes re-ordered
+// into tiles (bands of parallels x longitude sectors) so that a tile's
+// neighbours were touched by the tiles just before it.
+constexpr uint32_t kPoleBit = 0x80000000u;
+
+struct DevMesh {
+  int32_t V = 0;          // nodes
+  int32_t E = 0;          // mesh edges
+  int32_t npole = 0;      // pole edges
+  int32_t ntiles = 0;     // tiles in the processing order
+  const int32_t *perm = nullptr;     // [V]   node at position p
+  const int32_t *rowp = nullptr;     // [V+1] incidence range of position p
+  const int32_t *nbr = nullptr;      // [I]   neighbour node | kPoleBit
+  const double2 *S = nullptr;        // [I]   signed dual normal (s S_lon, s S_lat)
+  const int32_t *inc_edge = nullptr; // [I]   flux slot (E + k for pole edge k)
+  const double *alpha = nullptr;     // [V]   R / V_i          (by position)
+  const double *beta = nullptr;      // [V]   R cos(lat_i)/V_i (by position)
+  const double *coslat = nullptr;    // [V]   cos(lat)         (by node id)
+  const int32_t *tile_ptr = nullptr; // [ntiles+1] position range of a tile
+  const int32_t *e2n = nullptr;      // [E+npole][2] endpoints (flux kernel)
+  const double2 *eS = nullptr;       // [E+npole] unsigned normals; pole: (0, sigma dlon0)
+};
+
+struct MeshStore {
+  DevMesh d;
+  int device = 0;
+  int64_t nincid = 0;
+  int32_t nrings = 0, max_degree = 0;
+  size_t bytes = 0;
+  std::vector<void *> allocations;
+  // internal Laplacian / flux workspace, grown on demand
+  std::mutex ws_mu;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  int serve_refs = 0;
+  double geometry_bytes = 0.0;
+  ~MeshStore();
+};
+
+// ------------------------------------------------------------- kernels
+struct LaunchShape {
+  int variant = ATLAS_VARIANT_COLUMN;
+  int block = 256;
+  int nodes_per_block = 0;  // 0 = the mesh's tiles
+};
+
+atlas_status launch_op(const MeshStore &m, atlas_op op, atlas_dtype dt,
+                       const void *in, int nlev, void *out, void *ws,
+                       const LaunchShape &shape, hipStream_t s);
+size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
+atlas_status derive_scales(MeshStore &m, const double *vol_by_pos,
+                           const double *cos_by_pos, double radius);
+LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
+
+}  // namespace atlasx

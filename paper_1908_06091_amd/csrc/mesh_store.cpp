@@ -1,0 +1,262 @@
+// mesh_store.cpp -- device mesh store: validation of a host mesh
+// description, the processing order (tiles), the signed node->edge table in
+// that order, and the one-time copy to the device.
+//
+// Section 4.3 (Block/Irregular connectivity: the node->edge table is an
+// irregular table, edge2node a block table) and Section 5 (mesh data is
+// made available on the device once, then stays resident).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace atlasx {
+
+MeshStore::~MeshStore() {
+  for (void *p : allocations) (void)hipFree(p);
+  if (ws) (void)hipFree(ws);
+}
+
+namespace {
+
+atlas_status validate(const atlas_mesh_desc *d) {
+  if (!d) return fail(ATLAS_EINVAL, "mesh description is NULL");
+  const int64_t V = d->nnodes, E = d->nedges;
+  if (V < 1 || V >= (int64_t)1 << 31)
+    return fail(ATLAS_EINVAL, "nnodes must be in [1, 2^31)");
+  if (E < 1 || 2 * E >= (int64_t)1 << 31)
+    return fail(ATLAS_EINVAL, "nedges must be in [1, 2^30)");
+  if (!d->lon || !d->lat || !d->cos_lat || !d->edge2node || !d->node2edge_ptr ||
+      !d->node2edge || !d->node2edge_sign || !d->dual_volumes || !d->dual_normals)
+    return fail(ATLAS_EINVAL, "a required mesh array is NULL");
+  if (d->npole_edges < 0 || (d->npole_edges > 0 && (!d->pole_edges || !d->pole_normals)))
+    return fail(ATLAS_EINVAL, "pole edge arrays missing");
+  if (!(d->radius > 0.0) || !std::isfinite(d->radius))
+    return fail(ATLAS_EINVAL, "radius must be positive and finite");
+  for (int64_t e = 0; e < E; ++e) {
+    const int32_t a = d->edge2node[2 * e], b = d->edge2node[2 * e + 1];
+    if (a < 0 || b >= V || !(a < b))
+      return fail(ATLAS_EINVAL, "edge2node[" + std::to_string(e) + "] must satisfy 0 <= a < b < nnodes");
+    if (!std::isfinite(d->dual_normals[2 * e]) || !std::isfinite(d->dual_normals[2 * e + 1]))
+      return fail(ATLAS_EINVAL, "non-finite dual normal at edge " + std::to_string(e));
+  }
+  if (d->node2edge_ptr[0] != 0 || d->node2edge_ptr[V] != 2 * E)
+    return fail(ATLAS_EINVAL, "node2edge_ptr must run from 0 to 2*nedges");
+  std::vector<uint8_t> seen(E, 0);
+  for (int64_t i = 0; i < V; ++i) {
+    const int64_t r0 = d->node2edge_ptr[i], r1 = d->node2edge_ptr[i + 1];
+    if (r1 < r0) return fail(ATLAS_EINVAL, "node2edge_ptr is not monotone");
+    for (int64_t r = r0; r < r1; ++r) {
+      const int32_t e = d->node2edge[r];
+      if (e < 0 || e >= E) return fail(ATLAS_EINVAL, "node2edge entry out of range");
+      if (r > r0 && !(d->node2edge[r - 1] < e))
+        return fail(ATLAS_EINVAL, "node2edge rows must list edges in ascending id");
+      const int8_t s = d->node2edge_sign[r];
+      const int32_t a = d->edge2node[2 * e], b = d->edge2node[2 * e + 1];
+      if (!((s == 1 && a == i) || (s == -1 && b == i)))
+        return fail(ATLAS_EINVAL, "node2edge_sign / endpoint mismatch at node " + std::to_string(i));
+      seen[e] |= (s == 1) ? 1 : 2;
+    }
+    if (!(d->dual_volumes[i] > 0.0) || !std::isfinite(d->dual_volumes[i]))
+      return fail(ATLAS_EINVAL, "dual volume must be positive at node " + std::to_string(i));
+    if (!(d->cos_lat[i] > 0.0) || d->cos_lat[i] > 1.0 || !std::isfinite(d->lat[i]) ||
+        !std::isfinite(d->lon[i]))
+      return fail(ATLAS_EINVAL, "bad coordinates at node " + std::to_string(i));
+  }
+  for (int64_t e = 0; e < E; ++e)
+    if (seen[e] != 3) return fail(ATLAS_EINVAL, "edge " + std::to_string(e) + " missing from node2edge");
+  std::vector<uint8_t> polar(V, 0);
+  for (int64_t k = 0; k < d->npole_edges; ++k) {
+    const int32_t a = d->pole_edges[2 * k], b = d->pole_edges[2 * k + 1];
+    if (a < 0 || b < 0 || a >= V || b >= V || a == b)
+      return fail(ATLAS_EINVAL, "pole edge endpoints out of range");
+    if (polar[a]++ || polar[b]++)
+      return fail(ATLAS_EINVAL, "a node belongs to more than one pole edge");
+    if (!std::isfinite(d->pole_normals[k])) return fail(ATLAS_EINVAL, "non-finite pole normal");
+  }
+  return ATLAS_OK;
+}
+
+// Parallels: explicit ring_off, or runs of equal latitude in node order.
+std::vector<int64_t> rings_of(const atlas_mesh_desc *d) {
+  std::vector<int64_t> off;
+  if (d->nrings > 0 && d->ring_off) {
+    off.assign(d->ring_off, d->ring_off + d->nrings + 1);
+    bool ok = off.front() == 0 && off.back() == d->nnodes;
+    for (size_t j = 0; ok && j + 1 < off.size(); ++j) ok = off[j] < off[j + 1];
+    if (ok) return off;
+    off.clear();
+  }
+  off.push_back(0);
+  for (int64_t i = 1; i < d->nnodes; ++i)
+    if (d->lat[i] != d->lat[i - 1]) off.push_back(i);
+  off.push_back(d->nnodes);
+  return off;
+}
+
+}  // namespace
+
+// Processing order: bands of `band` parallels; each band is cut into
+// longitude sectors holding about `width` nodes of its widest parallel;
+// a tile is one sector of one band, listed parallel by parallel.  Meshes
+// without a parallel structure fall back to blocks of consecutive nodes.
+static void processing_order(const atlas_mesh_desc *d, int band, int width,
+                             std::vector<int32_t> &perm, std::vector<int32_t> &tile_ptr,
+                             int32_t &nrings) {
+  const int64_t V = d->nnodes;
+  std::vector<int64_t> off = rings_of(d);
+  const int64_t nr = (int64_t)off.size() - 1;
+  nrings = (int32_t)nr;
+  perm.clear();
+  perm.reserve(V);
+  tile_ptr.assign(1, 0);
+  if (nr > V / 4) {
+    for (int64_t i = 0; i < V; ++i) {
+      perm.push_back((int32_t)i);
+      if ((i + 1) % (band * width) == 0 || i + 1 == V) tile_ptr.push_back((int32_t)(i + 1));
+    }
+    return;
+  }
+  const double twopi = 6.283185307179586476925;
+  for (int64_t j0 = 0; j0 < nr; j0 += band) {
+    const int64_t j1 = std::min(nr, j0 + band);
+    int64_t widest = 0;
+    for (int64_t j = j0; j < j1; ++j) widest = std::max(widest, off[j + 1] - off[j]);
+    const int64_t nsec = std::max<int64_t>(1, (widest + width / 2) / width);
+    std::vector<std::vector<int32_t>> bucket(nsec);
+    for (int64_t j = j0; j < j1; ++j) {
+      for (int64_t i = off[j]; i < off[j + 1]; ++i) {
+        double x = std::fmod(d->lon[i], twopi);
+        if (x < 0) x += twopi;
+        int64_t sec = (int64_t)(x / twopi * (double)nsec);
+        if (sec >= nsec) sec = nsec - 1;
+        bucket[sec].push_back((int32_t)i);
+      }
+    }
+    for (int64_t s = 0; s < nsec; ++s) {
+      perm.insert(perm.end(), bucket[s].begin(), bucket[s].end());
+      if ((int64_t)perm.size() > tile_ptr.back()) tile_ptr.push_back((int32_t)perm.size());
+    }
+  }
+}
+
+template <class T>
+static atlas_status upload_array(MeshStore &m, const std::vector<T> &h, const T **dptr) {
+  void *p = nullptr;
+  const size_t bytes = std::max<size_t>(1, h.size() * sizeof(T));
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(ATLAS_ENOMEM, "hipMalloc of mesh store failed");
+  m.allocations.push_back(p);
+  m.bytes += bytes;
+  if (!h.empty()) ATLASX_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dptr = static_cast<const T *>(p);
+  return ATLAS_OK;
+}
+
+atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStore **out) {
+  atlas_status st = validate(d);
+  if (st != ATLAS_OK) return st;
+  const int64_t V = d->nnodes, E = d->nedges, NP = d->npole_edges;
+
+  std::vector<int32_t> perm, tile_ptr;
+  int32_t nrings = 0;
+  processing_order(d, band, width, perm, tile_ptr, nrings);
+  if ((int64_t)perm.size() != V) return fail(ATLAS_EINVAL, "processing order lost nodes");
+
+  std::vector<int32_t> pole_of(V, -1);
+  for (int64_t k = 0; k < NP; ++k) {
+    pole_of[d->pole_edges[2 * k]] = (int32_t)k;
+    pole_of[d->pole_edges[2 * k + 1]] = (int32_t)k;
+  }
+  // incidences in processing order: mesh edges in ascending id, pole last
+  std::vector<int32_t> rowp(V + 1, 0), nbr, inc_edge;
+  std::vector<double2> S;
+  std::vector<double> vol_p(V), cos_p(V);
+  nbr.reserve(2 * E + 2 * NP);
+  inc_edge.reserve(2 * E + 2 * NP);
+  S.reserve(2 * E + 2 * NP);
+  int32_t maxdeg = 0;
+  for (int64_t p = 0; p < V; ++p) {
+    const int32_t i = perm[p];
+    for (int64_t r = d->node2edge_ptr[i]; r < d->node2edge_ptr[i + 1]; ++r) {
+      const int32_t e = d->node2edge[r];
+      const int8_t s = d->node2edge_sign[r];
+      const int32_t other = s > 0 ? d->edge2node[2 * e + 1] : d->edge2node[2 * e];
+      nbr.push_back(other);
+      inc_edge.push_back(s > 0 ? e : (int32_t)(e | (int32_t)kPoleBit));
+      S.push_back(make_double2(s * d->dual_normals[2 * e], s * d->dual_normals[2 * e + 1]));
+    }
+    if (pole_of[i] >= 0) {
+      const int32_t k = pole_of[i];
+      const int32_t a = d->pole_edges[2 * k], b = d->pole_edges[2 * k + 1];
+      nbr.push_back((int32_t)((uint32_t)(a == i ? b : a) | kPoleBit));
+      inc_edge.push_back((int32_t)(E + k));
+      S.push_back(make_double2(0.0, d->pole_normals[k]));
+    }
+    rowp[p + 1] = (int32_t)nbr.size();
+    maxdeg = std::max(maxdeg, rowp[p + 1] - rowp[p]);
+    vol_p[p] = d->dual_volumes[i];
+    cos_p[p] = d->cos_lat[i];
+  }
+  if (maxdeg > 64) return fail(ATLAS_EINVAL, "node degree above 64");
+  std::vector<int32_t> e2n(2 * (E + NP));
+  std::vector<double2> eS(E + NP);
+  for (int64_t e = 0; e < E; ++e) {
+    e2n[2 * e] = d->edge2node[2 * e];
+    e2n[2 * e + 1] = d->edge2node[2 * e + 1];
+    eS[e] = make_double2(d->dual_normals[2 * e], d->dual_normals[2 * e + 1]);
+  }
+  for (int64_t k = 0; k < NP; ++k) {
+    e2n[2 * (E + k)] = d->pole_edges[2 * k];
+    e2n[2 * (E + k) + 1] = d->pole_edges[2 * k + 1];
+    eS[E + k] = make_double2(0.0, d->pole_normals[k]);
+  }
+  std::vector<double> cos_n(d->cos_lat, d->cos_lat + V);
+
+  MeshStore *m = new (std::nothrow) MeshStore();
+  if (!m) return fail(ATLAS_ENOMEM, "out of host memory");
+  (void)hipGetDevice(&m->device);
+  m->d.V = (int32_t)V;
+  m->d.E = (int32_t)E;
+  m->d.npole = (int32_t)NP;
+  m->d.ntiles = (int32_t)tile_ptr.size() - 1;
+  m->nincid = (int64_t)nbr.size();
+  m->nrings = nrings;
+  m->max_degree = maxdeg;
+  const double *vol_d = nullptr, *cos_pd = nullptr;
+  std::vector<double> zeros(V, 0.0);
+  if ((st = upload_array(*m, perm, &m->d.perm)) != ATLAS_OK ||
+      (st = upload_array(*m, rowp, &m->d.rowp)) != ATLAS_OK ||
+      (st = upload_array(*m, nbr, &m->d.nbr)) != ATLAS_OK ||
+      (st = upload_array(*m, S, &m->d.S)) != ATLAS_OK ||
+      (st = upload_array(*m, inc_edge, &m->d.inc_edge)) != ATLAS_OK ||
+      (st = upload_array(*m, zeros, &m->d.alpha)) != ATLAS_OK ||
+      (st = upload_array(*m, zeros, &m->d.beta)) != ATLAS_OK ||
+      (st = upload_array(*m, cos_n, &m->d.coslat)) != ATLAS_OK ||
+      (st = upload_array(*m, tile_ptr, &m->d.tile_ptr)) != ATLAS_OK ||
+      (st = upload_array(*m, e2n, &m->d.e2n)) != ATLAS_OK ||
+      (st = upload_array(*m, eS, &m->d.eS)) != ATLAS_OK ||
+      (st = upload_array(*m, vol_p, &vol_d)) != ATLAS_OK ||
+      (st = upload_array(*m, cos_p, &cos_pd)) != ATLAS_OK) {
+    delete m;
+    return st;
+  }
+  if ((st = derive_scales(*m, vol_d, cos_pd, d->radius)) != ATLAS_OK) {
+    delete m;
+    return st;
+  }
+  // the two temporaries are only read by the derivation kernel
+  (void)hipDeviceSynchronize();
+  // bytes one operator pass reads from the mesh store (column/flat forms):
+  // per position perm + rowp + alpha/beta; per incidence nbr + S;
+  // per node cos(lat) (div/curl)
+  m->geometry_bytes = (double)V * (4 + 4 + 16) + (double)m->nincid * (4 + 16);
+  *out = m;
+  return ATLAS_OK;
+}
+
+}  // namespace atlasx
