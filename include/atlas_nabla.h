@@ -143,6 +143,22 @@ atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc);
  * ATLAS_EDEVICE. */
 atlas_status atlas_mesh_upload(const atlas_mesh_desc *desc, atlas_mesh_t *out);
 
+/* Processing layout of the device store: the nodes are visited in tiles,
+ * each tile one longitude sector (about `sector_nodes` nodes of its widest
+ * parallel) of a band of `band_rings` consecutive parallels, so that a
+ * tile's neighbours were touched just before it.  Zero fields take the
+ * library defaults.  Results do not depend on the layout. */
+typedef struct {
+  int32_t band_rings;
+  int32_t sector_nodes;
+} atlas_mesh_layout;
+
+/* atlas_mesh_upload with an explicit layout (NULL = defaults).
+ * Errors: as atlas_mesh_upload; ATLAS_EINVAL for a negative field. */
+atlas_status atlas_mesh_upload_ex(const atlas_mesh_desc *desc,
+                                  const atlas_mesh_layout *layout,
+                                  atlas_mesh_t *out);
+
 /* Convenience: atlas_mesh_desc_octahedral + atlas_mesh_upload. */
 atlas_status atlas_mesh_create_octahedral(int32_t N, double radius,
                                           atlas_mesh_t *out);
@@ -188,14 +204,23 @@ typedef enum {
   ATLAS_VARIANT_AUTO = 0,   /* autotuned choice (or built-in default)      */
   ATLAS_VARIANT_COLUMN = 1, /* one wavefront per node, lanes over levels   */
   ATLAS_VARIANT_FLAT = 2,   /* lanes over flattened (node, level) pairs    */
-  ATLAS_VARIANT_FLUX = 3    /* two kernels: edge fluxes into an [E][nlev]
+  ATLAS_VARIANT_FLUX = 3,   /* two kernels: edge fluxes into an [E][nlev]
                                buffer (EdgeColumns-like), then the gather  */
+  ATLAS_VARIANT_SWEEP = 4   /* one workgroup per (tile, level chunk) walks
+                               its band parallel by parallel, keeping three
+                               consecutive parallels' columns in LDS       */
 } atlas_variant;
 
 typedef struct {
   int32_t variant;          /* atlas_variant                                */
   int32_t block_threads;    /* 64, 128, 256, 512 or 1024                    */
-  int32_t nodes_per_block;  /* column/flat: processing positions per block  */
+  int32_t nodes_per_block;  /* column/flat: processing positions per block;
+                               0 = the mesh's tiles                         */
+  int32_t level_chunk;      /* column: levels per unit of work (1..64); the
+                               units run chunk by chunk over the whole mesh
+                               so a parallel's columns are still cached when
+                               the next parallel reads them; 0 = all levels
+                               in one unit                                  */
 } atlas_launch;
 
 /* Apply `op` with an explicit launch shape (tests, autotuner).  For
@@ -208,6 +233,14 @@ atlas_status atlas_nabla_apply(atlas_mesh_t mesh, atlas_op op, const void *in,
                                hipStream_t stream);
 size_t atlas_flux_workspace_bytes(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
                                   atlas_dtype dtype);
+
+/* Streaming reference with the gradient's byte pattern: reads n elements of
+ * `in` and writes each twice into `out` (2n elements), fully coalesced.
+ * Used to report the practically reachable HBM bandwidth next to the
+ * operators' roofline.  elem_bytes: 4 or 8.  Device pointers, 16-byte
+ * aligned, n even.  Errors: ATLAS_EINVAL, ATLAS_EDEVICE. */
+atlas_status atlas_bandwidth_probe(const void *in, void *out, int64_t n, int32_t elem_bytes,
+                                   hipStream_t stream);
 
 /* Thread-local description of the last failure on this thread. */
 const char *atlas_last_error(void);

@@ -19,7 +19,8 @@ import numpy as np
 from . import _abi
 from ._abi import (ATLAS_F32, ATLAS_F64, ATLAS_OP_CURL, ATLAS_OP_DIVERGENCE,  # noqa: F401
                    ATLAS_OP_GRADIENT, ATLAS_OP_LAPLACIAN, VARIANT_AUTO, VARIANT_COLUMN,
-                   VARIANT_FLAT, VARIANT_FLUX, AtlasError, Launch, MeshDesc, MeshInfo)
+                   VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP, AtlasError, Launch, Layout, MeshDesc,
+                   MeshInfo)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libatlas_nabla.so")
@@ -90,16 +91,31 @@ def mesh_desc_octahedral(N: int, radius: float = 1.0) -> dict:
         L.atlas_mesh_desc_free(p)
 
 
+def bandwidth_probe(x, out, stream=None):
+    """Streaming reference: read x (n elements), write 2n elements to out."""
+    n = x.numel()
+    if out.numel() < 2 * n or out.dtype != x.dtype:
+        raise ValueError("out must hold 2 * x.numel() elements of x's dtype")
+    _check(lib().atlas_bandwidth_probe(_dev_ptr(x, "x"), _dev_ptr(out, "out"), n - (n & 1),
+                                       x.element_size(), _stream(stream)))
+    return out
+
+
 class Mesh:
     """A mesh resident on the current device (``atlas_mesh_upload``)."""
 
-    def __init__(self, N: int | None = None, radius: float = 1.0, *, desc: dict | None = None):
+    def __init__(self, N: int | None = None, radius: float = 1.0, *, desc: dict | None = None,
+                 layout: tuple[int, int] | None = None):
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
+        if layout is not None and desc is None:
+            desc = mesh_desc_octahedral(N, radius)
         if desc is not None:
-            c_desc, self._keep = _abi.numpy_to_desc(desc)
-            _check(L.atlas_mesh_upload(ctypes.byref(c_desc), ctypes.byref(self._h)))
+            c_desc, keep = _abi.numpy_to_desc(desc)
+            lay = ctypes.byref(Layout(*layout)) if layout is not None else None
+            _check(L.atlas_mesh_upload_ex(ctypes.byref(c_desc), lay, ctypes.byref(self._h)))
+            del keep
         else:
             _check(L.atlas_mesh_create_octahedral(int(N), float(radius), ctypes.byref(self._h)))
         info = MeshInfo()
@@ -210,4 +226,4 @@ class Mesh:
 __all__ = ["Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
            "ATLAS_F32", "ATLAS_F64", "ATLAS_OP_GRADIENT", "ATLAS_OP_DIVERGENCE",
            "ATLAS_OP_CURL", "ATLAS_OP_LAPLACIAN", "VARIANT_AUTO", "VARIANT_COLUMN",
-           "VARIANT_FLAT", "VARIANT_FLUX"]
+           "VARIANT_FLAT", "VARIANT_FLUX", "VARIANT_SWEEP"]

@@ -7,7 +7,7 @@ import numpy as np
 
 ATLAS_F32, ATLAS_F64 = 0, 1
 ATLAS_OP_GRADIENT, ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL, ATLAS_OP_LAPLACIAN = 0, 1, 2, 3
-VARIANT_AUTO, VARIANT_COLUMN, VARIANT_FLAT, VARIANT_FLUX = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_COLUMN, VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP = 0, 1, 2, 3, 4
 
 STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EDEVICE",
           -4: "ATLAS_EBUSY", -5: "ATLAS_ESTATE", -6: "ATLAS_ETIMEOUT"}
@@ -47,9 +47,13 @@ class MeshInfo(ctypes.Structure):
     ]
 
 
+class Layout(ctypes.Structure):
+    _fields_ = [("band_rings", ctypes.c_int32), ("sector_nodes", ctypes.c_int32)]
+
+
 class Launch(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("nodes_per_block", ctypes.c_int32)]
+                ("nodes_per_block", ctypes.c_int32), ("level_chunk", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol the header declares
@@ -60,6 +64,8 @@ SIGNATURES = {
                                                   ctypes.POINTER(ctypes.POINTER(MeshDesc))]),
     "atlas_mesh_desc_free": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
     "atlas_mesh_upload": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_mesh_upload_ex": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Layout),
+                                            ctypes.POINTER(ctypes.c_void_p)]),
     "atlas_mesh_create_octahedral": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double,
                                                     ctypes.POINTER(ctypes.c_void_p)]),
     "atlas_mesh_free": (ctypes.c_int, [ctypes.c_void_p]),
@@ -79,6 +85,8 @@ SIGNATURES = {
                                          ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.POINTER(Launch),
                                          ctypes.c_void_p]),
+    "atlas_bandwidth_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_int32, ctypes.c_void_p]),
     "atlas_flux_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int,
                                                      ctypes.c_int32, ctypes.c_int]),
 }

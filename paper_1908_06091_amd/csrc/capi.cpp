@@ -109,6 +109,8 @@ atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
   if (sh.block < 64 || sh.block > 1024 || (sh.block & 63) != 0)
     return fail(ATLAS_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
   if (sh.nodes_per_block < 0) return fail(ATLAS_EINVAL, "nodes_per_block must be >= 0");
+  if (sh.level_chunk < 0 || sh.level_chunk > 64)
+    return fail(ATLAS_EINVAL, "level_chunk must be in [0, 64]");
   size_t need = 0;
   if (op == ATLAS_OP_LAPLACIAN) need += lapl_ws_bytes(m, nlev, dt);
   if (sh.variant == ATLAS_VARIANT_FLUX) need += flux_ws_bytes(m, op, nlev, dt);
@@ -171,12 +173,24 @@ atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc) {
 }
 
 atlas_status atlas_mesh_upload(const atlas_mesh_desc *desc, atlas_mesh_t *out) {
+  return atlas_mesh_upload_ex(desc, nullptr, out);
+}
+
+atlas_status atlas_mesh_upload_ex(const atlas_mesh_desc *desc, const atlas_mesh_layout *layout,
+                                  atlas_mesh_t *out) {
   if (!out) return fail(ATLAS_EINVAL, "out is NULL");
   *out = nullptr;
+  int band = kDefaultBand, width = kDefaultWidth;
+  if (layout) {
+    if (layout->band_rings < 0 || layout->sector_nodes < 0)
+      return fail(ATLAS_EINVAL, "layout fields must be >= 0");
+    if (layout->band_rings) band = layout->band_rings;
+    if (layout->sector_nodes) width = layout->sector_nodes;
+  }
   MeshStore *m = nullptr;
   atlas_status st;
   try {
-    st = upload_mesh(desc, 4, 16, &m);
+    st = upload_mesh(desc, band, width, &m);
   } catch (const std::bad_alloc &) {
     return fail(ATLAS_ENOMEM, "out of host memory during upload");
   }
@@ -255,6 +269,17 @@ size_t atlas_laplacian_workspace_bytes(atlas_mesh_t mesh, int32_t nlev, atlas_dt
   return lapl_ws_bytes(*mesh->store, nlev, dtype);
 }
 
+atlas_status atlas_bandwidth_probe(const void *in, void *out, int64_t n, int32_t elem_bytes,
+                                   hipStream_t stream) {
+  if (!in || !out) return fail(ATLAS_EINVAL, "NULL pointer");
+  if (n < 2 || (n & 1)) return fail(ATLAS_EINVAL, "n must be even and >= 2");
+  if (elem_bytes != 4 && elem_bytes != 8) return fail(ATLAS_EINVAL, "elem_bytes must be 4 or 8");
+  if (!aligned(in, 16) || !aligned(out, 16)) return fail(ATLAS_EINVAL, "pointers must be 16-byte aligned");
+  if (overlap(in, (size_t)n * elem_bytes, out, (size_t)2 * n * elem_bytes))
+    return fail(ATLAS_EINVAL, "input and output overlap");
+  return bandwidth_probe(in, out, n, elem_bytes, stream);
+}
+
 size_t atlas_flux_workspace_bytes(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
                                   atlas_dtype dtype) {
   if (!mesh || !mesh->store || nlev < 1) return 0;
@@ -271,6 +296,7 @@ LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, i
     s.variant = l->variant;
     s.block = l->block_threads;
     s.nodes_per_block = l->nodes_per_block;
+    s.level_chunk = l->level_chunk;
   }
   return s;
 }

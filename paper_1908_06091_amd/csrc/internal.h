@@ -47,6 +47,8 @@ int build_octahedral(int N, double R, HostMesh &h);
 // into tiles (bands of parallels x longitude sectors) so that a tile's
 // neighbours were touched by the tiles just before it.
 constexpr uint32_t kPoleBit = 0x80000000u;
+constexpr int kDefaultBand = 32;   // parallels per band of the processing order
+constexpr int kDefaultWidth = 32;  // nodes per sector of a band's widest parallel
 
 struct DevMesh {
   int32_t V = 0;          // nodes
@@ -64,6 +66,15 @@ struct DevMesh {
   const int32_t *tile_ptr = nullptr; // [ntiles+1] position range of a tile
   const int32_t *e2n = nullptr;      // [E+npole][2] endpoints (flux kernel)
   const double2 *eS = nullptr;       // [E+npole] unsigned normals; pole: (0, sigma dlon0)
+  // parallel-sweep plan: per tile, the parallels it touches (its own and
+  // one above / below), each as a segment of consecutive nodes
+  int32_t sweep_ok = 0;              // plan valid for this mesh
+  int32_t segmax = 0;                // longest segment (nodes)
+  const int32_t *tile_seg = nullptr; // [ntiles+1] segment range of a tile
+  const int4 *seg = nullptr;         // {ring offset, ring size, first index, length}
+  const int2 *seg_pos = nullptr;     // owned positions of the segment [lo, hi)
+  const int32_t *selfslot = nullptr; // [V]  slot of position p in its segment
+  const int32_t *lref = nullptr;     // [I]  ((dq + 1) << 16) | slot, -1 = pole edge
 };
 
 struct MeshStore {
@@ -87,6 +98,7 @@ struct LaunchShape {
   int variant = ATLAS_VARIANT_COLUMN;
   int block = 256;
   int nodes_per_block = 0;  // 0 = the mesh's tiles
+  int level_chunk = 0;      // column form: levels per unit, 0 = all
 };
 
 atlas_status launch_op(const MeshStore &m, atlas_op op, atlas_dtype dt,
@@ -95,6 +107,7 @@ atlas_status launch_op(const MeshStore &m, atlas_op op, atlas_dtype dt,
 size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
 atlas_status derive_scales(MeshStore &m, const double *vol_by_pos,
                            const double *cos_by_pos, double radius);
+atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hipStream_t st);
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
 
 }  // namespace atlasx

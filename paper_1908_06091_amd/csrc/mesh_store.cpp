@@ -6,6 +6,7 @@
 // irregular table, edge2node a block table) and Section 5 (mesh data is
 // made available on the device once, then stays resident).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -144,6 +145,103 @@ static void processing_order(const atlas_mesh_desc *d, int band, int width,
   }
 }
 
+// Parallel-sweep plan.  For every tile: the parallels it owns plus one
+// above and one below, each reduced to the shortest cyclic run of nodes that
+// holds the tile's own nodes and all their neighbours; the slot of every
+// position in its run and of every neighbour in its run.  A kernel keeps
+// the runs of three consecutive parallels in LDS and reads every neighbour
+// from there.  Returns false if a neighbour lies more than one parallel away
+// (then the plan is not used).
+struct SweepPlan {
+  std::vector<int32_t> tile_seg, selfslot, lref;
+  std::vector<int4> seg;
+  std::vector<int2> seg_pos;
+  int32_t segmax = 0;
+};
+
+static bool sweep_plan(const std::vector<int64_t> &off, const std::vector<int32_t> &perm,
+                       const std::vector<int32_t> &tile_ptr, const std::vector<int32_t> &rowp,
+                       const std::vector<int32_t> &nbr, SweepPlan &sp) {
+  const int64_t V = (int64_t)perm.size();
+  const int64_t nr = (int64_t)off.size() - 1;
+  std::vector<int32_t> ring_of(V);
+  for (int64_t j = 0; j < nr; ++j)
+    for (int64_t i = off[j]; i < off[j + 1]; ++i) ring_of[i] = (int32_t)j;
+  const int64_t T = (int64_t)tile_ptr.size() - 1;
+  sp.tile_seg.assign(1, 0);
+  sp.selfslot.assign(V, 0);
+  sp.lref.assign(nbr.size(), -1);
+  std::vector<std::vector<int32_t>> need;
+  for (int64_t t = 0; t < T; ++t) {
+    const int32_t p0 = tile_ptr[t], p1 = tile_ptr[t + 1];
+    int32_t jmin = INT32_MAX, jmax = -1;
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t j = ring_of[perm[p]];
+      if (p > p0 && j < ring_of[perm[p - 1]]) return false;  // parallels in order
+      jmin = std::min(jmin, j);
+      jmax = std::max(jmax, j);
+    }
+    const int32_t rlo = std::max<int32_t>(0, jmin - 1);
+    const int32_t rhi = std::min<int32_t>((int32_t)nr - 1, jmax + 1);
+    need.assign(rhi - rlo + 1, {});
+    std::vector<int2> pos(rhi - rlo + 1, make_int2(0, 0));
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t i = perm[p], j = ring_of[i];
+      need[j - rlo].push_back((int32_t)(i - off[j]));
+      if (pos[j - rlo].y == 0) pos[j - rlo] = make_int2(p, p + 1);
+      else pos[j - rlo].y = p + 1;
+      for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
+        if ((uint32_t)nbr[r] & kPoleBit) continue;
+        const int32_t n = nbr[r], jn = ring_of[n];
+        if (jn < j - 1 || jn > j + 1) return false;
+        need[jn - rlo].push_back((int32_t)(n - off[jn]));
+      }
+    }
+    std::vector<int32_t> lo(rhi - rlo + 1), len(rhi - rlo + 1);
+    for (int32_t q = 0; q <= rhi - rlo; ++q) {
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      auto &a = need[q];
+      std::sort(a.begin(), a.end());
+      a.erase(std::unique(a.begin(), a.end()), a.end());
+      if (a.empty()) { lo[q] = 0; len[q] = 0; }
+      else if ((int32_t)a.size() == nx) { lo[q] = 0; len[q] = nx; }
+      else {
+        // the run is the complement of the widest cyclic gap
+        int32_t best = -1, at = 0;
+        for (size_t k = 0; k < a.size(); ++k) {
+          const int32_t g = (k + 1 < a.size()) ? a[k + 1] - a[k] : a[0] + nx - a[k];
+          if (g > best) { best = g; at = (int32_t)k; }
+        }
+        lo[q] = a[(at + 1) % a.size()];
+        len[q] = nx - best + 1;
+      }
+      if (len[q] >= 65536) return false;
+      sp.segmax = std::max(sp.segmax, len[q]);
+      sp.seg.push_back(make_int4((int32_t)off[rlo + q], nx, lo[q], len[q]));
+      sp.seg_pos.push_back(pos[q]);
+    }
+    sp.tile_seg.push_back((int32_t)sp.seg.size());
+    auto slot = [&](int32_t node, int32_t q) {
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      int32_t s = (int32_t)(node - off[rlo + q]) - lo[q];
+      if (s < 0) s += nx;
+      return s;
+    };
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t i = perm[p], q = ring_of[i] - rlo;
+      sp.selfslot[p] = slot(i, q);
+      for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
+        if ((uint32_t)nbr[r] & kPoleBit) continue;
+        const int32_t qn = ring_of[nbr[r]] - rlo;
+        const int32_t s = slot(nbr[r], qn);
+        if (s >= len[qn]) return false;
+        sp.lref[r] = ((qn - q + 1) << 16) | s;
+      }
+    }
+  }
+  return true;
+}
+
 template <class T>
 static atlas_status upload_array(MeshStore &m, const std::vector<T> &h, const T **dptr) {
   void *p = nullptr;
@@ -216,6 +314,9 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
     eS[E + k] = make_double2(0.0, d->pole_normals[k]);
   }
   std::vector<double> cos_n(d->cos_lat, d->cos_lat + V);
+  SweepPlan sp;
+  const bool sweep_ok = nrings <= V / 4 && sweep_plan(rings_of(d), perm, tile_ptr, rowp, nbr, sp);
+  if (!sweep_ok) sp = SweepPlan();
 
   MeshStore *m = new (std::nothrow) MeshStore();
   if (!m) return fail(ATLAS_ENOMEM, "out of host memory");
@@ -227,6 +328,8 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->nincid = (int64_t)nbr.size();
   m->nrings = nrings;
   m->max_degree = maxdeg;
+  m->d.sweep_ok = sweep_ok ? 1 : 0;
+  m->d.segmax = sp.segmax;
   const double *vol_d = nullptr, *cos_pd = nullptr;
   std::vector<double> zeros(V, 0.0);
   if ((st = upload_array(*m, perm, &m->d.perm)) != ATLAS_OK ||
@@ -241,7 +344,12 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
       (st = upload_array(*m, e2n, &m->d.e2n)) != ATLAS_OK ||
       (st = upload_array(*m, eS, &m->d.eS)) != ATLAS_OK ||
       (st = upload_array(*m, vol_p, &vol_d)) != ATLAS_OK ||
-      (st = upload_array(*m, cos_p, &cos_pd)) != ATLAS_OK) {
+      (st = upload_array(*m, cos_p, &cos_pd)) != ATLAS_OK ||
+      (st = upload_array(*m, sp.tile_seg, &m->d.tile_seg)) != ATLAS_OK ||
+      (st = upload_array(*m, sp.seg, &m->d.seg)) != ATLAS_OK ||
+      (st = upload_array(*m, sp.seg_pos, &m->d.seg_pos)) != ATLAS_OK ||
+      (st = upload_array(*m, sp.selfslot, &m->d.selfslot)) != ATLAS_OK ||
+      (st = upload_array(*m, sp.lref, &m->d.lref)) != ATLAS_OK) {
     delete m;
     return st;
   }

@@ -34,16 +34,16 @@ namespace atlasx {
 
 enum { OP_GRAD = 0, OP_DIV = 1, OP_CURL = 2 };
 
+// native 2-vectors (kept in registers; also the [node][level][2] element)
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
 // Tiles are numbered so that each XCD (workgroups are dealt round-robin to
 // the 8 XCDs) receives a contiguous run of the processing order and keeps
 // neighbouring columns in its own L2.
 __device__ __forceinline__ int xcd_tile(int b, int per_xcd) {
   return (b & 7) * per_xcd + (b >> 3);
 }
-
-struct PosInfo {
-  int node, r0, r1;
-};
 
 // Chunked tiles: either the mesh's tiles or fixed blocks of positions.
 __device__ __forceinline__ bool tile_range(const DevMesh &m, int tile, int npb,
@@ -61,97 +61,10 @@ __device__ __forceinline__ bool tile_range(const DevMesh &m, int tile, int npb,
 }
 
 // ---------------------------------------------------------------------------
-// One output element (position p, level k) -- FP64 sum form.
-// ---------------------------------------------------------------------------
-template <int OP>
-__device__ __forceinline__ void element_f64(const DevMesh &m, const double *__restrict__ in,
-                                            double *__restrict__ out, int nlev, int p,
-                                            int node, int r0, int r1, int k) {
-  const size_t L = (size_t)nlev;
-  if (OP == OP_GRAD) {
-    const double xi = in[(size_t)node * L + k];
-    double gl = 0.0, gt = 0.0;
-    int r = r0;
-    for (; r + 4 <= r1; r += 4) {
-      uint32_t nb[4];
-      double2 s[4];
-      double xn[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        nb[j] = (uint32_t)m.nbr[r + j];
-        s[j] = m.S[r + j];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xn[j] = in[(size_t)(nb[j] & ~kPoleBit) * L + k];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double xe = 0.5 * (xi + xn[j]);
-        if (!(nb[j] & kPoleBit)) gl = gl + s[j].x * xe;
-        gt = gt + s[j].y * xe;
-      }
-    }
-    for (; r < r1; ++r) {
-      const uint32_t nb = (uint32_t)m.nbr[r];
-      const double2 s = m.S[r];
-      const double xe = 0.5 * (xi + in[(size_t)(nb & ~kPoleBit) * L + k]);
-      if (!(nb & kPoleBit)) gl = gl + s.x * xe;
-      gt = gt + s.y * xe;
-    }
-    double2 o;
-    o.x = m.alpha[p] * gl;
-    o.y = m.beta[p] * gt;
-    reinterpret_cast<double2 *>(out)[(size_t)node * L + k] = o;
-  } else {
-    const double2 *vin = reinterpret_cast<const double2 *>(in);
-    const double2 ui = vin[(size_t)node * L + k];
-    const double ci = m.coslat[node];
-    // divergence: (a, b) = (u, v cos); curl: (a, b) = (v, u cos), minus sign
-    const double ai = (OP == OP_DIV) ? ui.x : ui.y;
-    const double bi = ((OP == OP_DIV) ? ui.y : ui.x) * ci;
-    double acc = 0.0;
-    int r = r0;
-    for (; r + 4 <= r1; r += 4) {
-      uint32_t nb[4];
-      double2 s[4], un[4];
-      double cn[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        nb[j] = (uint32_t)m.nbr[r + j];
-        s[j] = m.S[r + j];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t n = nb[j] & ~kPoleBit;
-        un[j] = vin[(size_t)n * L + k];
-        cn[j] = m.coslat[n];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (nb[j] & kPoleBit) continue;
-        const double an = (OP == OP_DIV) ? un[j].x : un[j].y;
-        const double bn = ((OP == OP_DIV) ? un[j].y : un[j].x) * cn[j];
-        const double ae = 0.5 * (ai + an), be = 0.5 * (bi + bn);
-        const double f = (OP == OP_DIV) ? s[j].x * ae + s[j].y * be : s[j].x * ae - s[j].y * be;
-        acc = acc + f;
-      }
-    }
-    for (; r < r1; ++r) {
-      const uint32_t nb = (uint32_t)m.nbr[r];
-      if (nb & kPoleBit) continue;
-      const double2 s = m.S[r];
-      const double2 un = vin[(size_t)nb * L + k];
-      const double an = (OP == OP_DIV) ? un.x : un.y;
-      const double bn = ((OP == OP_DIV) ? un.y : un.x) * m.coslat[nb];
-      const double ae = 0.5 * (ai + an), be = 0.5 * (bi + bn);
-      const double f = (OP == OP_DIV) ? s.x * ae + s.y * be : s.x * ae - s.y * be;
-      acc = acc + f;
-    }
-    out[(size_t)node * L + k] = m.alpha[p] * acc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// One output element -- FP32 fields, difference form, Kahan node sums.
+// Per-element arithmetic.  A policy holds the running state of one output
+// element (one node, one level) and is fed the node's incidences in CSR
+// order; every launch form drives the same policy, so all forms produce the
+// same bits.
 // ---------------------------------------------------------------------------
 struct Kahan {
   float s = 0.0f, c = 0.0f;
@@ -168,7 +81,7 @@ struct Kahan {
 // mesh edge, negated for the two ends of a pole edge).
 template <int OP>
 __device__ __forceinline__ void diff_terms_f32(const double2 &s, float xi, float xn,
-                                               float2 ui, float2 un, double ci, double cn,
+                                               v2f ui, v2f un, double ci, double cn,
                                                float &tx, float &ty, float &t) {
   if (OP == OP_GRAD) {
     const float h = 0.5f * (xn - xi);
@@ -187,115 +100,264 @@ __device__ __forceinline__ void diff_terms_f32(const double2 &s, float xi, float
   }
 }
 
-template <int OP>
-__device__ __forceinline__ void element_f32(const DevMesh &m, const float *__restrict__ in,
-                                            float *__restrict__ out, int nlev, int p,
-                                            int node, int r0, int r1, int k) {
-  const size_t L = (size_t)nlev;
-  if (OP == OP_GRAD) {
-    const float xi = in[(size_t)node * L + k];
-    Kahan kx, ky;
-    double cx = 0.0, cy = 0.0;
-    int r = r0;
-    for (; r + 4 <= r1; r += 4) {
-      uint32_t nb[4];
-      double2 s[4];
-      float xn[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        nb[j] = (uint32_t)m.nbr[r + j];
-        s[j] = m.S[r + j];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xn[j] = in[(size_t)(nb[j] & ~kPoleBit) * L + k];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float tx, ty, t;
-        diff_terms_f32<OP_GRAD>(s[j], xi, xn[j], float2{}, float2{}, 0.0, 0.0, tx, ty, t);
-        if (!(nb[j] & kPoleBit)) { kx.add(tx); cx = cx + s[j].x; }
-        ky.add(ty);
-        cy = cy + s[j].y;
-      }
-    }
-    for (; r < r1; ++r) {
-      const uint32_t nb = (uint32_t)m.nbr[r];
-      const double2 s = m.S[r];
-      const float xn = in[(size_t)(nb & ~kPoleBit) * L + k];
-      float tx, ty, t;
-      diff_terms_f32<OP_GRAD>(s, xi, xn, float2{}, float2{}, 0.0, 0.0, tx, ty, t);
-      if (!(nb & kPoleBit)) { kx.add(tx); cx = cx + s.x; }
-      ky.add(ty);
-      cy = cy + s.y;
-    }
-    float2 o;
-    o.x = (float)(m.alpha[p] * (kx.value() + cx * (double)xi));
-    o.y = (float)(m.beta[p] * (ky.value() + cy * (double)xi));
-    reinterpret_cast<float2 *>(out)[(size_t)node * L + k] = o;
-  } else {
-    const float2 *vin = reinterpret_cast<const float2 *>(in);
-    const float2 ui = vin[(size_t)node * L + k];
-    const double ci = m.coslat[node];
-    Kahan ka;
-    double cx = 0.0, cy = 0.0;
-    int r = r0;
-    for (; r + 4 <= r1; r += 4) {
-      uint32_t nb[4];
-      double2 s[4];
-      float2 un[4];
-      double cn[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        nb[j] = (uint32_t)m.nbr[r + j];
-        s[j] = m.S[r + j];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t n = nb[j] & ~kPoleBit;
-        un[j] = vin[(size_t)n * L + k];
-        cn[j] = m.coslat[n];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (nb[j] & kPoleBit) continue;
-        float tx, ty, t;
-        diff_terms_f32<OP>(s[j], 0.0f, 0.0f, ui, un[j], ci, cn[j], tx, ty, t);
-        ka.add(t);
-        cx = cx + s[j].x;
-        cy = cy + s[j].y;
-      }
-    }
-    for (; r < r1; ++r) {
-      const uint32_t nb = (uint32_t)m.nbr[r];
-      if (nb & kPoleBit) continue;
-      const double2 s = m.S[r];
-      float tx, ty, t;
-      diff_terms_f32<OP>(s, 0.0f, 0.0f, ui, vin[(size_t)nb * L + k], ci, m.coslat[nb], tx, ty, t);
-      ka.add(t);
-      cx = cx + s.x;
-      cy = cy + s.y;
-    }
-    const double a_i = (OP == OP_DIV) ? (double)ui.x : (double)ui.y;
-    const double b_i = ((OP == OP_DIV) ? (double)ui.y : (double)ui.x) * ci;
+// Output stores are non-temporal (streamed past the caches, so they do not
+// evict input columns that neighbours still need); ATLASX_CACHED_STORE
+// selects ordinary stores.
+__device__ __forceinline__ void st_out(double *p, double v) {
+#ifndef ATLASX_CACHED_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+__device__ __forceinline__ void st_out(float *p, float v) {
+#ifndef ATLASX_CACHED_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+__device__ __forceinline__ void st_out2(double *p, double x, double y) {
+  v2d v = {x, y};
+#ifndef ATLASX_CACHED_STORE
+  __builtin_nontemporal_store(v, reinterpret_cast<v2d *>(p));
+#else
+  *reinterpret_cast<v2d *>(p) = v;
+#endif
+}
+__device__ __forceinline__ void st_out2(float *p, float x, float y) {
+  v2f v = {x, y};
+#ifndef ATLASX_CACHED_STORE
+  __builtin_nontemporal_store(v, reinterpret_cast<v2f *>(p));
+#else
+  *reinterpret_cast<v2f *>(p) = v;
+#endif
+}
+
+template <class T, int OP> struct Pol;
+
+// FP64 gradient: G += sS (x_i + x_n)/2; the pole edge feeds the lat part.
+template <> struct Pol<double, OP_GRAD> {
+  using V = double;
+  static constexpr bool kVecIn = false, kVecOut = true;
+  struct St { double xi, gl, gt; };
+  static __device__ __forceinline__ void init(St &s, V xi, double) { s.xi = xi; s.gl = 0.0; s.gt = 0.0; }
+  static __device__ __forceinline__ void add(St &s, V xn, const double2 &S, bool pole, double) {
+    const double xe = 0.5 * (s.xi + xn);
+    if (!pole) s.gl = s.gl + S.x * xe;
+    s.gt = s.gt + S.y * xe;
+  }
+  static __device__ __forceinline__ void store(double *out, size_t idx, const St &s, double al,
+                                               double be, double, double, double) {
+    st_out2(out + 2 * idx, al * s.gl, be * s.gt);
+  }
+};
+
+// FP64 divergence / curl: sum of sS_lon a_e +- sS_lat b_e with edge
+// averages of a = u (v) and b = v cos (u cos); pole edges do not enter.
+template <int OP> struct PolDC64 {
+  using V = v2d;
+  static constexpr bool kVecIn = true, kVecOut = false;
+  struct St { double ai, bi, acc; };
+  static __device__ __forceinline__ void init(St &s, V ui, double ci) {
+    s.ai = (OP == OP_DIV) ? ui.x : ui.y;
+    s.bi = ((OP == OP_DIV) ? ui.y : ui.x) * ci;
+    s.acc = 0.0;
+  }
+  static __device__ __forceinline__ void add(St &s, V un, const double2 &S, bool, double cn) {
+    const double an = (OP == OP_DIV) ? un.x : un.y;
+    const double bn = ((OP == OP_DIV) ? un.y : un.x) * cn;
+    const double ae = 0.5 * (s.ai + an), be = 0.5 * (s.bi + bn);
+    const double f = (OP == OP_DIV) ? S.x * ae + S.y * be : S.x * ae - S.y * be;
+    s.acc = s.acc + f;
+  }
+  static __device__ __forceinline__ void store(double *out, size_t idx, const St &s, double al,
+                                               double, double, double, double) {
+    st_out(out + idx, al * s.acc);
+  }
+};
+template <> struct Pol<double, OP_DIV> : PolDC64<OP_DIV> {};
+template <> struct Pol<double, OP_CURL> : PolDC64<OP_CURL> {};
+
+// FP32 gradient, difference form with Kahan sums; the closure sums
+// (cx, cy) = sum sS are formed in FP64 by the caller.
+template <> struct Pol<float, OP_GRAD> {
+  using V = float;
+  static constexpr bool kVecIn = false, kVecOut = true;
+  struct St { float xi; Kahan kx, ky; };
+  static __device__ __forceinline__ void init(St &s, V xi, double) { s.xi = xi; s.kx = Kahan(); s.ky = Kahan(); }
+  static __device__ __forceinline__ void add(St &s, V xn, const double2 &S, bool pole, double) {
+    float tx, ty, t;
+    diff_terms_f32<OP_GRAD>(S, s.xi, xn, v2f{}, v2f{}, 0.0, 0.0, tx, ty, t);
+    if (!pole) s.kx.add(tx);
+    s.ky.add(ty);
+  }
+  static __device__ __forceinline__ void store(float *out, size_t idx, const St &s, double al,
+                                               double be, double cx, double cy, double) {
+    st_out2(out + 2 * idx, (float)(al * (s.kx.value() + cx * (double)s.xi)),
+            (float)(be * (s.ky.value() + cy * (double)s.xi)));
+  }
+};
+
+template <int OP> struct PolDC32 {
+  using V = v2f;
+  static constexpr bool kVecIn = true, kVecOut = false;
+  struct St { v2f ui; double ci; Kahan ka; };
+  static __device__ __forceinline__ void init(St &s, V ui, double ci) { s.ui = ui; s.ci = ci; s.ka = Kahan(); }
+  static __device__ __forceinline__ void add(St &s, V un, const double2 &S, bool, double cn) {
+    float tx, ty, t;
+    diff_terms_f32<OP>(S, 0.0f, 0.0f, s.ui, un, s.ci, cn, tx, ty, t);
+    s.ka.add(t);
+  }
+  static __device__ __forceinline__ void store(float *out, size_t idx, const St &s, double al,
+                                               double, double cx, double cy, double) {
+    const double a_i = (OP == OP_DIV) ? (double)s.ui.x : (double)s.ui.y;
+    const double b_i = ((OP == OP_DIV) ? (double)s.ui.y : (double)s.ui.x) * s.ci;
     const double closure = (OP == OP_DIV) ? cx * a_i + cy * b_i : cx * a_i - cy * b_i;
-    out[(size_t)node * L + k] = (float)(m.alpha[p] * (ka.value() + closure));
+    st_out(out + idx, (float)(al * (s.ka.value() + closure)));
+  }
+};
+template <> struct Pol<float, OP_DIV> : PolDC32<OP_DIV> {};
+template <> struct Pol<float, OP_CURL> : PolDC32<OP_CURL> {};
+
+// Closure sums of a node (FP32 forms): sum over the incidences that enter
+// the operator of the signed normals.
+template <int OP>
+__device__ __forceinline__ void closure_add(double &cx, double &cy, const double2 &S, bool pole) {
+  if (OP == OP_GRAD) {
+    if (!pole) cx = cx + S.x;
+    cy = cy + S.y;
+  } else if (!pole) {
+    cx = cx + S.x;
+    cy = cy + S.y;
   }
 }
 
+// One element at level k (any nlev); used by the generic column loop and
+// by the flat form.
 template <class T, int OP>
 __device__ __forceinline__ void element(const DevMesh &m, const T *__restrict__ in,
-                                        T *__restrict__ out, int nlev, int p, int node,
-                                        int r0, int r1, int k) {
-  if constexpr (sizeof(T) == 8)
-    element_f64<OP>(m, in, out, nlev, p, node, r0, r1, k);
-  else
-    element_f32<OP>(m, in, out, nlev, p, node, r0, r1, k);
+                                        T *__restrict__ out, int nlev, int p, int node, int r0,
+                                        int r1, int k) {
+  using P = Pol<T, OP>;
+  using V = typename P::V;
+  const V *vin = reinterpret_cast<const V *>(in);
+  const size_t L = (size_t)nlev;
+  const double ci = P::kVecIn ? m.coslat[node] : 0.0;
+  typename P::St st;
+  P::init(st, vin[(size_t)node * L + k], ci);
+  double cx = 0.0, cy = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    const uint32_t nb = (uint32_t)m.nbr[r];
+    const bool pole = (nb & kPoleBit) != 0;
+    if (P::kVecIn && pole) continue;
+    const double2 S = m.S[r];
+    const size_t n = nb & ~kPoleBit;
+    const double cn = P::kVecIn ? m.coslat[n] : 0.0;
+    closure_add<OP>(cx, cy, S, pole);
+    P::add(st, vin[n * L + k], S, pole, cn);
+  }
+  const double al = m.alpha[p], be = P::kVecOut ? m.beta[p] : 0.0;
+  P::store(out, (size_t)node * L + k, st, al, be, cx, cy, ci);
+}
+
+// Chunked column form: work units are (level chunk, tile), chunk-major, so
+// the whole mesh is swept once per chunk and consecutive parallels of one
+// chunk meet in the XCD's L2.  One wavefront per position; lanes over the
+// chunk's levels.
+template <class T, int OP>
+__global__ void __launch_bounds__(1024) k_column_chunked(DevMesh m, const T *__restrict__ in,
+                                                         T *__restrict__ out, int nlev, int npb,
+                                                         int kc, int ntiles, int per_xcd) {
+  const int u = xcd_tile(blockIdx.x, per_xcd);
+  const int c = u / ntiles;
+  int p0, p1;
+  if (!tile_range(m, u - c * ntiles, npb, p0, p1)) return;
+  const int k0 = c * kc;
+  if (k0 >= nlev) return;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int k = k0 + lane;
+  const bool active = lane < kc && k < nlev;
+  for (int p = p0 + wave; p < p1; p += nw) {
+    const int node = __builtin_amdgcn_readfirstlane(m.perm[p]);
+    const int r0 = __builtin_amdgcn_readfirstlane(m.rowp[p]);
+    const int r1 = __builtin_amdgcn_readfirstlane(m.rowp[p + 1]);
+    if (active) element<T, OP>(m, in, out, nlev, p, node, r0, r1, k);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Column form: one wavefront per position, lanes over levels.  The node's
-// incidence range is wavefront-uniform.
+// Column form: one wavefront per position, lanes over levels; NCH chunks of
+// 64 levels are processed together and the neighbours are fetched in groups
+// of four, so up to 4*NCH column loads are in flight per wavefront.  The
+// node's incidence range is wavefront-uniform (scalar loads).
 // ---------------------------------------------------------------------------
-template <class T, int OP>
+template <class T, int OP, int NCH>
+__device__ __forceinline__ void column_node(const DevMesh &m, const T *__restrict__ in,
+                                            T *__restrict__ out, int nlev, int p, int node,
+                                            int r0, int r1, int lane) {
+  using P = Pol<T, OP>;
+  using V = typename P::V;
+  const V *vin = reinterpret_cast<const V *>(in);
+  const size_t L = (size_t)nlev;
+  int kk[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) kk[c] = min(lane + 64 * c, nlev - 1);  // clamped, in bounds
+  const double ci = P::kVecIn ? m.coslat[node] : 0.0;
+  typename P::St st[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) P::init(st[c], vin[(size_t)node * L + kk[c]], ci);
+  double cx = 0.0, cy = 0.0;
+  int r = r0;
+  for (; r + 4 <= r1; r += 4) {
+    uint32_t nb[4];
+    double2 S[4];
+    double cn[4];
+    V xn[4][NCH];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      nb[j] = (uint32_t)m.nbr[r + j];
+      S[j] = m.S[r + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const size_t n = nb[j] & ~kPoleBit;
+      cn[j] = P::kVecIn ? m.coslat[n] : 0.0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) xn[j][c] = vin[n * L + kk[c]];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool pole = (nb[j] & kPoleBit) != 0;
+      if (P::kVecIn && pole) continue;
+      closure_add<OP>(cx, cy, S[j], pole);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) P::add(st[c], xn[j][c], S[j], pole, cn[j]);
+    }
+  }
+  for (; r < r1; ++r) {
+    const uint32_t nb = (uint32_t)m.nbr[r];
+    const bool pole = (nb & kPoleBit) != 0;
+    if (P::kVecIn && pole) continue;
+    const double2 S = m.S[r];
+    const size_t n = nb & ~kPoleBit;
+    const double cn = P::kVecIn ? m.coslat[n] : 0.0;
+    V xn[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) xn[c] = vin[n * L + kk[c]];
+    closure_add<OP>(cx, cy, S, pole);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) P::add(st[c], xn[c], S, pole, cn);
+  }
+  const double al = m.alpha[p], be = P::kVecOut ? m.beta[p] : 0.0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+    if (lane + 64 * c < nlev) P::store(out, (size_t)node * L + lane + 64 * c, st[c], al, be, cx, cy, ci);
+}
+
+template <class T, int OP, int NCH>
 __global__ void __launch_bounds__(1024) k_column(DevMesh m, const T *__restrict__ in,
                                                  T *__restrict__ out, int nlev, int npb,
                                                  int per_xcd) {
@@ -308,7 +370,140 @@ __global__ void __launch_bounds__(1024) k_column(DevMesh m, const T *__restrict_
     const int node = __builtin_amdgcn_readfirstlane(m.perm[p]);
     const int r0 = __builtin_amdgcn_readfirstlane(m.rowp[p]);
     const int r1 = __builtin_amdgcn_readfirstlane(m.rowp[p + 1]);
-    for (int k = lane; k < nlev; k += 64) element<T, OP>(m, in, out, nlev, p, node, r0, r1, k);
+    if (NCH > 0) {
+      column_node<T, OP, (NCH > 0 ? NCH : 1)>(m, in, out, nlev, p, node, r0, r1, lane);
+    } else {
+      // any nlev: chunks of 64 levels one after another
+      for (int k = lane; k < nlev; k += 64) element<T, OP>(m, in, out, nlev, p, node, r0, r1, k);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel-sweep form.  A workgroup owns one tile (a longitude sector of a
+// band of parallels) and one chunk of levels.  It walks down the band one
+// parallel at a time, keeping the runs of the parallels above, at and below
+// the current one in a 4-slot LDS ring buffer; while it computes parallel q
+// it has the loads of parallel q+2 in flight (staged through registers).
+// Every column is read from memory once per chunk plus a thin halo; every
+// neighbour comes from LDS.  One wavefront per position, lanes over levels.
+// ---------------------------------------------------------------------------
+template <class T, int OP, int EPT>
+__global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ in,
+                                               T *__restrict__ out, int nlev, int kcmax,
+                                               int ntiles, int per_xcd) {
+  using P = Pol<T, OP>;
+  using V = typename P::V;
+  constexpr int G = 8;  // incidences fetched together
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V *buf = reinterpret_cast<V *>(smem_raw);
+  const int u = xcd_tile(blockIdx.x, per_xcd);
+  const int c = u / ntiles;
+  const int tile = u - c * ntiles;
+  const int k0 = c * kcmax;
+  if (k0 >= nlev) return;
+  const int kc = min(kcmax, nlev - k0);
+  const int s0 = m.tile_seg[tile];
+  const int nseg = m.tile_seg[tile + 1] - s0;
+  const int slot_stride = m.segmax * kc;  // elements per LDS slot
+  const V *vin = reinterpret_cast<const V *>(in);
+  const size_t L = (size_t)nlev;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const bool lane_on = lane < kc;
+
+  // staging: wavefront w moves nodes w, w+nw, ... of a run; lanes = levels
+  V regs[EPT];
+  auto fetch = [&](int q) {
+    const int4 sg = m.seg[s0 + q];  // ring offset, ring size, first index, length
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int t = wave + i * nw;
+      if (t < sg.w && lane_on) {
+        int ii = sg.z + t;
+        if (ii >= sg.y) ii -= sg.y;
+        regs[i] = vin[(size_t)(sg.x + ii) * L + k0 + lane];
+      }
+    }
+  };
+  auto deposit = [&](int q) {
+    const int len = m.seg[s0 + q].w;
+    V *b = buf + (q & 3) * slot_stride;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int t = wave + i * nw;
+      if (t < len && lane_on) b[t * kc + lane] = regs[i];
+    }
+  };
+
+  // first and last parallel with positions of this tile
+  int qa = nseg, qb = -1;
+  for (int q = 0; q < nseg; ++q) {
+    const int2 pr = m.seg_pos[s0 + q];
+    if (pr.y > pr.x) {
+      qa = min(qa, q);
+      qb = q;
+    }
+  }
+  if (qb < 0) return;
+  for (int q = 0; q <= min(nseg - 1, qa + 1); ++q) {
+    fetch(q);
+    deposit(q);
+  }
+  __syncthreads();
+  for (int q = qa; q <= qb; ++q) {
+    const bool pf = q + 2 < nseg;
+    if (pf) fetch(q + 2);
+    const int2 pr = m.seg_pos[s0 + q];
+    if (lane_on) {
+      const V *bq = buf + (q & 3) * slot_stride;
+      for (int p = pr.x + wave; p < pr.y; p += nw) {
+        const int node = __builtin_amdgcn_readfirstlane(m.perm[p]);
+        const int r0 = __builtin_amdgcn_readfirstlane(m.rowp[p]);
+        const int r1 = __builtin_amdgcn_readfirstlane(m.rowp[p + 1]);
+        const int ts = __builtin_amdgcn_readfirstlane(m.selfslot[p]);
+        const double ci = P::kVecIn ? m.coslat[node] : 0.0;
+        typename P::St st;
+        P::init(st, bq[ts * kc + lane], ci);
+        double cx = 0.0, cy = 0.0;
+        for (int rb = r0; rb < r1; rb += G) {
+          // all loads of the group first (indices clamped into the row),
+          // then the accumulation in row order
+          int lr[G];
+          uint32_t nb[G];
+          double2 S[G];
+          V xn[G];
+          double cn[G];
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            const int r = min(rb + j, r1 - 1);
+            lr[j] = m.lref[r];
+            nb[j] = (uint32_t)m.nbr[r];
+            S[j] = m.S[r];
+          }
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            const int l = lr[j] < 0 ? (1 << 16) | ts : lr[j];  // pole: placeholder
+            xn[j] = buf[((q + (l >> 16) - 1) & 3) * slot_stride + (l & 0xffff) * kc + lane];
+            cn[j] = P::kVecIn ? m.coslat[nb[j] & ~kPoleBit] : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            if (rb + j >= r1) break;
+            const bool pole = lr[j] < 0;
+            if (P::kVecIn && pole) continue;
+            if (pole) xn[j] = vin[(size_t)(nb[j] & ~kPoleBit) * L + k0 + lane];
+            closure_add<OP>(cx, cy, S[j], pole);
+            P::add(st, xn[j], S[j], pole, cn[j]);
+          }
+        }
+        const double al = m.alpha[p], be = P::kVecOut ? m.beta[p] : 0.0;
+        P::store(out, (size_t)node * L + k0 + lane, st, al, be, cx, cy, ci);
+      }
+    }
+    if (pf) deposit(q + 2);
+    __syncthreads();
   }
 }
 
@@ -369,14 +564,14 @@ __global__ void __launch_bounds__(256) k_edge_flux(DevMesh m, const T *__restric
       // difference form seen from endpoint a (neighbour b)
       float tx, ty, t;
       if (OP == OP_GRAD) {
-        diff_terms_f32<OP_GRAD>(S, in[(size_t)a * L + k], in[(size_t)b * L + k], float2{},
-                                float2{}, 0.0, 0.0, tx, ty, t);
+        diff_terms_f32<OP_GRAD>(S, in[(size_t)a * L + k], in[(size_t)b * L + k], v2f{},
+                                v2f{}, 0.0, 0.0, tx, ty, t);
         float2 f;
         f.x = tx;
         f.y = ty;
         reinterpret_cast<float2 *>(flux)[g] = f;
       } else {
-        const float2 *vin = reinterpret_cast<const float2 *>(in);
+        const v2f *vin = reinterpret_cast<const v2f *>(in);
         diff_terms_f32<OP>(S, 0.0f, 0.0f, vin[(size_t)a * L + k], vin[(size_t)b * L + k],
                            m.coslat[a], m.coslat[b], tx, ty, t);
         flux[g] = t;
@@ -469,6 +664,36 @@ __global__ void __launch_bounds__(1024) k_gather_flux(DevMesh m, const T *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Streaming reference: read n, write 2n (the gradient's byte pattern).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_stream_r1w2(const T *__restrict__ x, T *__restrict__ y,
+                                                     int64_t n2) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 *xv = reinterpret_cast<const v2 *>(x);
+  v2 *yv = reinterpret_cast<v2 *>(y);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const v2 v = xv[i];
+    v2 a = {v.x, v.x}, b = {v.y, v.y};
+    yv[2 * i] = a;
+    yv[2 * i + 1] = b;
+  }
+}
+
+atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hipStream_t st) {
+  const int64_t n2 = n / 2;
+  if (elem == 8)
+    hipLaunchKernelGGL(k_stream_r1w2<double>, dim3(65536), dim3(256), 0, st,
+                       static_cast<const double *>(in), static_cast<double *>(out), n2);
+  else
+    hipLaunchKernelGGL(k_stream_r1w2<float>, dim3(65536), dim3(256), 0, st,
+                       static_cast<const float *>(in), static_cast<float *>(out), n2);
+  ATLASX_HIP(hipGetLastError());
+  return ATLAS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Per-node scales, derived once at upload: alpha = R/V, beta = R cos/V.
 // ---------------------------------------------------------------------------
 __global__ void k_derive_scales(int V, const double *__restrict__ vol,
@@ -512,6 +737,16 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   return s;
 }
 
+constexpr size_t kMaxLds = 160 * 1024;
+
+// Levels per chunk of the sweep form: at most 64 (one per lane), split
+// evenly (137 -> 46, 46, 45).
+static int sweep_chunk(int nlev, int want) {
+  if (want > 0) return min(want, 64);
+  const int n = (nlev + 63) / 64;
+  return (nlev + n - 1) / n;
+}
+
 template <class T, int OP>
 static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *out, void *ws,
                                  const LaunchShape &sh, hipStream_t st) {
@@ -521,10 +756,27 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
   const int per_xcd = (ntiles + 7) / 8;
   const dim3 grid(per_xcd * 8), block(sh.block);
   switch (sh.variant) {
-    case ATLAS_VARIANT_COLUMN:
-      hipLaunchKernelGGL((k_column<T, OP>), grid, block, 0, st, m, in, out, nlev,
-                         sh.nodes_per_block, per_xcd);
+    case ATLAS_VARIANT_COLUMN: {
+      if (sh.level_chunk > 0) {
+        const int nchunk = (nlev + sh.level_chunk - 1) / sh.level_chunk;
+        const int units = ntiles * nchunk;
+        const int per = (units + 7) / 8;
+        hipLaunchKernelGGL((k_column_chunked<T, OP>), dim3(per * 8), block, 0, st, m, in, out,
+                           nlev, sh.nodes_per_block, sh.level_chunk, ntiles, per);
+        break;
+      }
+      const int nch = (nlev + 63) / 64;
+#define ATLASX_COL(N)                                                                  \
+  hipLaunchKernelGGL((k_column<T, OP, N>), grid, block, 0, st, m, in, out, nlev,       \
+                     sh.nodes_per_block, per_xcd)
+      if (nch == 1) ATLASX_COL(1);
+      else if (nch == 2) ATLASX_COL(2);
+      else if (nch == 3) ATLASX_COL(3);
+      else if (nch == 4) ATLASX_COL(4);
+      else ATLASX_COL(0);
+#undef ATLASX_COL
       break;
+    }
     case ATLAS_VARIANT_FLAT:
       hipLaunchKernelGGL((k_flat<T, OP>), grid, block, 0, st, m, in, out, nlev,
                          sh.nodes_per_block, per_xcd);
@@ -538,6 +790,35 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       const int per = (m.ntiles + 7) / 8;
       hipLaunchKernelGGL((k_gather_flux<T, OP>), dim3(per * 8), block, 0, st, m, in,
                          (const T *)flux, out, nlev, per);
+      break;
+    }
+    case ATLAS_VARIANT_SWEEP: {
+      if (!m.sweep_ok) return fail(ATLAS_EINVAL, "the sweep form needs a mesh of parallels");
+      if (sh.nodes_per_block > 0)
+        return fail(ATLAS_EINVAL, "the sweep form runs on the mesh's tiles (nodes_per_block = 0)");
+      // the chunk shrinks until a parallel's run fits the staging registers
+      // (16 elements per thread) and four runs fit in LDS
+      if (sh.block > 512) return fail(ATLAS_EINVAL, "the sweep form takes at most 512 threads");
+      // wavefront w stages nodes w, w + nw, ... of a run: EPT >= segmax / nw;
+      // four runs of kc levels must fit in LDS (the chunk shrinks if needed)
+      const size_t vbytes = sizeof(T) * (OP == OP_GRAD ? 1 : 2);
+      int kc = sweep_chunk(nlev, sh.level_chunk);
+      kc = min(kc, (int)(kMaxLds / (4 * vbytes * (size_t)max(1, m.segmax))));
+      if (kc < 1) return fail(ATLAS_EINVAL, "sweep tile too large for LDS");
+      const int nchunk = (nlev + kc - 1) / kc;
+      const size_t lds = (size_t)4 * m.segmax * kc * vbytes;
+      const int need = (m.segmax + (sh.block >> 6) - 1) / (sh.block >> 6);
+      const int units = m.ntiles * nchunk;
+      const int per = (units + 7) / 8;
+      void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
+      if (need <= 4) kern = k_sweep<T, OP, 4>;
+      else if (need <= 8) kern = k_sweep<T, OP, 8>;
+      else if (need <= 16) kern = k_sweep<T, OP, 16>;
+      else if (need <= 32) kern = k_sweep<T, OP, 32>;
+      else return fail(ATLAS_EINVAL, "sweep tile too large for the block size");
+      ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(kern, dim3(per * 8), block, lds, st, m, in, out, nlev, kc, m.ntiles, per);
       break;
     }
     default:

@@ -93,6 +93,11 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
                 shapes.append(P.Launch(variant, block, npb))
     shapes.append(P.Launch(P.VARIANT_FLUX, 256, 0))
     shapes.append(P.Launch(P.VARIANT_FLUX, 64, 0))
+    for block in (64, 256, 512):
+        for kc in (0, 1, 5, 32):
+            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))
+    for kc in (1, 7, 64):
+        shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, kc))
     for sh in shapes:
         got = _run(P, gm, op, x, launch=sh)
         assert torch.equal(got, base), (sh.variant, sh.block_threads, sh.nodes_per_block)
