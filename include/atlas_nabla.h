@@ -221,6 +221,13 @@ typedef struct {
                                so a parallel's columns are still cached when
                                the next parallel reads them; 0 = all levels
                                in one unit                                  */
+  int32_t blocks_per_cu;    /* column/flat: > 0 launches a persistent grid of
+                               this many workgroups per compute unit; each
+                               XCD's wavefronts then walk that XCD's share of
+                               the processing order together, one position
+                               per wavefront per step, so the set of columns
+                               in flight stays small enough for the L2;
+                               0 = one workgroup per tile                   */
 } atlas_launch;
 
 /* Apply `op` with an explicit launch shape (tests, autotuner).  For

@@ -53,7 +53,8 @@ class Layout(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("nodes_per_block", ctypes.c_int32), ("level_chunk", ctypes.c_int32)]
+                ("nodes_per_block", ctypes.c_int32), ("level_chunk", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol the header declares

@@ -47,8 +47,16 @@ int build_octahedral(int N, double R, HostMesh &h);
 // into tiles (bands of parallels x longitude sectors) so that a tile's
 // neighbours were touched by the tiles just before it.
 constexpr uint32_t kPoleBit = 0x80000000u;
+constexpr int kIncPad = 8;
+constexpr int32_t kLrefPole = 1 << 30;  // sweep reference of a pole edge         // incidence arrays carry one extra group
 constexpr int kDefaultBand = 32;   // parallels per band of the processing order
 constexpr int kDefaultWidth = 32;  // nodes per sector of a band's widest parallel
+
+// One processing position, packed for a single scalar load.
+struct __align__(32) PosRec {
+  int32_t node, r0, r1, selfslot;
+  double alpha, beta;
+};
 
 struct DevMesh {
   int32_t V = 0;          // nodes
@@ -64,17 +72,21 @@ struct DevMesh {
   const double *beta = nullptr;      // [V]   R cos(lat_i)/V_i (by position)
   const double *coslat = nullptr;    // [V]   cos(lat)         (by node id)
   const int32_t *tile_ptr = nullptr; // [ntiles+1] position range of a tile
+  const PosRec *pos = nullptr;       // [V]   packed position records
   const int32_t *e2n = nullptr;      // [E+npole][2] endpoints (flux kernel)
   const double2 *eS = nullptr;       // [E+npole] unsigned normals; pole: (0, sigma dlon0)
   // parallel-sweep plan: per tile, the parallels it touches (its own and
   // one above / below), each as a segment of consecutive nodes
+  int32_t maxdeg = 0;                // longest incidence row
   int32_t sweep_ok = 0;              // plan valid for this mesh
   int32_t segmax = 0;                // longest segment (nodes)
   const int32_t *tile_seg = nullptr; // [ntiles+1] segment range of a tile
   const int4 *seg = nullptr;         // {ring offset, ring size, first index, length}
   const int2 *seg_pos = nullptr;     // owned positions of the segment [lo, hi)
   const int32_t *selfslot = nullptr; // [V]  slot of position p in its segment
-  const int32_t *lref = nullptr;     // [I]  ((dq + 1) << 16) | slot, -1 = pole edge
+  const int32_t *lref = nullptr;     // [I]  ((dq + 1) << 16) | slot, plus
+                                     //      kLrefPole for a pole edge
+  const double *ncos = nullptr;      // [I]  cos(lat) of the incidence's neighbour
 };
 
 struct MeshStore {
@@ -99,7 +111,10 @@ struct LaunchShape {
   int block = 256;
   int nodes_per_block = 0;  // 0 = the mesh's tiles
   int level_chunk = 0;      // column form: levels per unit, 0 = all
+  int blocks_per_cu = 0;    // > 0: persistent wave-cyclic grid
 };
+
+int device_cu_count();
 
 atlas_status launch_op(const MeshStore &m, atlas_op op, atlas_dtype dt,
                        const void *in, int nlev, void *out, void *ws,

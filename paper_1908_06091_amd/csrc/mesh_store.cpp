@@ -191,8 +191,7 @@ static bool sweep_plan(const std::vector<int64_t> &off, const std::vector<int32_
       if (pos[j - rlo].y == 0) pos[j - rlo] = make_int2(p, p + 1);
       else pos[j - rlo].y = p + 1;
       for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
-        if ((uint32_t)nbr[r] & kPoleBit) continue;
-        const int32_t n = nbr[r], jn = ring_of[n];
+        const int32_t n = (int32_t)((uint32_t)nbr[r] & ~kPoleBit), jn = ring_of[n];
         if (jn < j - 1 || jn > j + 1) return false;
         need[jn - rlo].push_back((int32_t)(n - off[jn]));
       }
@@ -231,11 +230,12 @@ static bool sweep_plan(const std::vector<int64_t> &off, const std::vector<int32_
       const int32_t i = perm[p], q = ring_of[i] - rlo;
       sp.selfslot[p] = slot(i, q);
       for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
-        if ((uint32_t)nbr[r] & kPoleBit) continue;
-        const int32_t qn = ring_of[nbr[r]] - rlo;
-        const int32_t s = slot(nbr[r], qn);
+        const bool pole = ((uint32_t)nbr[r] & kPoleBit) != 0;
+        const int32_t n = (int32_t)((uint32_t)nbr[r] & ~kPoleBit);
+        const int32_t qn = ring_of[n] - rlo;
+        const int32_t s = slot(n, qn);
         if (s >= len[qn]) return false;
-        sp.lref[r] = ((qn - q + 1) << 16) | s;
+        sp.lref[r] = (pole ? kLrefPole : 0) | ((qn - q + 1) << 16) | s;
       }
     }
   }
@@ -317,6 +317,17 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   SweepPlan sp;
   const bool sweep_ok = nrings <= V / 4 && sweep_plan(rings_of(d), perm, tile_ptr, rowp, nbr, sp);
   if (!sweep_ok) sp = SweepPlan();
+  // cos(lat) of every incidence's neighbour, so a node's row is read with
+  // contiguous loads
+  std::vector<double> ncos(nbr.size());
+  for (size_t r = 0; r < nbr.size(); ++r) ncos[r] = d->cos_lat[(uint32_t)nbr[r] & ~kPoleBit];
+  // kernels read the incidences of a node in groups of kIncPad without
+  // clamping: pad every incidence array by one group
+  nbr.resize(nbr.size() + kIncPad, 0);
+  S.resize(S.size() + kIncPad, make_double2(0.0, 0.0));
+  inc_edge.resize(inc_edge.size() + kIncPad, 0);
+  ncos.resize(ncos.size() + kIncPad, 1.0);
+  sp.lref.resize(sp.lref.size() + kIncPad, 1 << 16);
 
   MeshStore *m = new (std::nothrow) MeshStore();
   if (!m) return fail(ATLAS_ENOMEM, "out of host memory");
@@ -325,9 +336,10 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->d.E = (int32_t)E;
   m->d.npole = (int32_t)NP;
   m->d.ntiles = (int32_t)tile_ptr.size() - 1;
-  m->nincid = (int64_t)nbr.size();
+  m->nincid = (int64_t)nbr.size() - kIncPad;
   m->nrings = nrings;
   m->max_degree = maxdeg;
+  m->d.maxdeg = maxdeg;
   m->d.sweep_ok = sweep_ok ? 1 : 0;
   m->d.segmax = sp.segmax;
   const double *vol_d = nullptr, *cos_pd = nullptr;
@@ -349,7 +361,21 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
       (st = upload_array(*m, sp.seg, &m->d.seg)) != ATLAS_OK ||
       (st = upload_array(*m, sp.seg_pos, &m->d.seg_pos)) != ATLAS_OK ||
       (st = upload_array(*m, sp.selfslot, &m->d.selfslot)) != ATLAS_OK ||
-      (st = upload_array(*m, sp.lref, &m->d.lref)) != ATLAS_OK) {
+      (st = upload_array(*m, sp.lref, &m->d.lref)) != ATLAS_OK ||
+      (st = upload_array(*m, ncos, &m->d.ncos)) != ATLAS_OK) {
+    delete m;
+    return st;
+  }
+  std::vector<PosRec> pos(V);
+  for (int64_t p = 0; p < V; ++p) {
+    pos[p].node = perm[p];
+    pos[p].r0 = rowp[p];
+    pos[p].r1 = rowp[p + 1];
+    pos[p].selfslot = sweep_ok ? sp.selfslot[p] : 0;
+    pos[p].alpha = 0.0;  // derived on the device below
+    pos[p].beta = 0.0;
+  }
+  if ((st = upload_array(*m, pos, &m->d.pos)) != ATLAS_OK) {
     delete m;
     return st;
   }

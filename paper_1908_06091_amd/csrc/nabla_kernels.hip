@@ -138,6 +138,7 @@ template <class T, int OP> struct Pol;
 
 // FP64 gradient: G += sS (x_i + x_n)/2; the pole edge feeds the lat part.
 template <> struct Pol<double, OP_GRAD> {
+  static constexpr int kOp = OP_GRAD;
   using V = double;
   static constexpr bool kVecIn = false, kVecOut = true;
   struct St { double xi, gl, gt; };
@@ -156,6 +157,7 @@ template <> struct Pol<double, OP_GRAD> {
 // FP64 divergence / curl: sum of sS_lon a_e +- sS_lat b_e with edge
 // averages of a = u (v) and b = v cos (u cos); pole edges do not enter.
 template <int OP> struct PolDC64 {
+  static constexpr int kOp = OP;
   using V = v2d;
   static constexpr bool kVecIn = true, kVecOut = false;
   struct St { double ai, bi, acc; };
@@ -182,6 +184,7 @@ template <> struct Pol<double, OP_CURL> : PolDC64<OP_CURL> {};
 // FP32 gradient, difference form with Kahan sums; the closure sums
 // (cx, cy) = sum sS are formed in FP64 by the caller.
 template <> struct Pol<float, OP_GRAD> {
+  static constexpr int kOp = OP_GRAD;
   using V = float;
   static constexpr bool kVecIn = false, kVecOut = true;
   struct St { float xi; Kahan kx, ky; };
@@ -200,6 +203,7 @@ template <> struct Pol<float, OP_GRAD> {
 };
 
 template <int OP> struct PolDC32 {
+  static constexpr int kOp = OP;
   using V = v2f;
   static constexpr bool kVecIn = true, kVecOut = false;
   struct St { v2f ui; double ci; Kahan ka; };
@@ -289,19 +293,62 @@ __global__ void __launch_bounds__(1024) k_column_chunked(DevMesh m, const T *__r
 }
 
 // ---------------------------------------------------------------------------
-// Column form: one wavefront per position, lanes over levels; NCH chunks of
-// 64 levels are processed together and the neighbours are fetched in groups
-// of four, so up to 4*NCH column loads are in flight per wavefront.  The
-// node's incidence range is wavefront-uniform (scalar loads).
+// Column form: one wavefront per position, lanes over levels.  NCH chunks
+// of 64 levels are processed together and all of a node's incidences (up to
+// G) are fetched in one round trip, so up to G*NCH column loads are in
+// flight per wavefront.  The position record and the incidence rows are
+// wavefront-uniform (scalar loads); the next position's record is fetched
+// while the current one is computed.
 // ---------------------------------------------------------------------------
-template <class T, int OP, int NCH>
+// One group of up to G incidences starting at rb: every load first (the
+// incidence arrays are padded, so entries past the row name valid nodes and
+// need no branch), then the accumulation in row order.
+template <class P, int NCH, int G>
+__device__ __forceinline__ void column_group(const DevMesh &m, const typename P::V *__restrict__ vin,
+                                             size_t L, const int (&kk)[NCH], int rb, int n,
+                                             typename P::St (&st)[NCH], double &cx, double &cy) {
+  using V = typename P::V;
+  uint32_t nb[G];
+  double2 S[G];
+  double cn[G];
+  V xn[G][NCH];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    nb[j] = (uint32_t)m.nbr[rb + j];
+    S[j] = m.S[rb + j];
+    cn[j] = P::kVecIn ? m.ncos[rb + j] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const size_t q = nb[j] & ~kPoleBit;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) xn[j][c] = vin[q * L + kk[c]];
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    if (j < n) {
+      const bool pole = (nb[j] & kPoleBit) != 0;
+      if (!(P::kVecIn && pole)) {
+        closure_add<P::kOp>(cx, cy, S[j], pole);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) P::add(st[c], xn[j][c], S[j], pole, cn[j]);
+      }
+    }
+  }
+}
+
+// ONE_GROUP: every row has at most G incidences and is handled by a single
+// group without a loop (a loop back-edge makes the compiler wait for every
+// outstanding memory operation, stores included, before the next loads).
+template <class T, int OP, int NCH, int G, bool ONE_GROUP>
 __device__ __forceinline__ void column_node(const DevMesh &m, const T *__restrict__ in,
-                                            T *__restrict__ out, int nlev, int p, int node,
-                                            int r0, int r1, int lane) {
+                                            T *__restrict__ out, int nlev, const PosRec &pr,
+                                            int lane) {
   using P = Pol<T, OP>;
   using V = typename P::V;
   const V *vin = reinterpret_cast<const V *>(in);
   const size_t L = (size_t)nlev;
+  const int node = pr.node, r0 = pr.r0, r1 = pr.r1;
   int kk[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) kk[c] = min(lane + 64 * c, nlev - 1);  // clamped, in bounds
@@ -310,72 +357,61 @@ __device__ __forceinline__ void column_node(const DevMesh &m, const T *__restric
 #pragma unroll
   for (int c = 0; c < NCH; ++c) P::init(st[c], vin[(size_t)node * L + kk[c]], ci);
   double cx = 0.0, cy = 0.0;
-  int r = r0;
-  for (; r + 4 <= r1; r += 4) {
-    uint32_t nb[4];
-    double2 S[4];
-    double cn[4];
-    V xn[4][NCH];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      nb[j] = (uint32_t)m.nbr[r + j];
-      S[j] = m.S[r + j];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const size_t n = nb[j] & ~kPoleBit;
-      cn[j] = P::kVecIn ? m.coslat[n] : 0.0;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) xn[j][c] = vin[n * L + kk[c]];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bool pole = (nb[j] & kPoleBit) != 0;
-      if (P::kVecIn && pole) continue;
-      closure_add<OP>(cx, cy, S[j], pole);
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) P::add(st[c], xn[j][c], S[j], pole, cn[j]);
-    }
+  if (ONE_GROUP) {
+    column_group<P, NCH, G>(m, vin, L, kk, r0, r1 - r0, st, cx, cy);
+  } else {
+    for (int rb = r0; rb < r1; rb += G) column_group<P, NCH, G>(m, vin, L, kk, rb, min(G, r1 - rb), st, cx, cy);
   }
-  for (; r < r1; ++r) {
-    const uint32_t nb = (uint32_t)m.nbr[r];
-    const bool pole = (nb & kPoleBit) != 0;
-    if (P::kVecIn && pole) continue;
-    const double2 S = m.S[r];
-    const size_t n = nb & ~kPoleBit;
-    const double cn = P::kVecIn ? m.coslat[n] : 0.0;
-    V xn[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) xn[c] = vin[n * L + kk[c]];
-    closure_add<OP>(cx, cy, S, pole);
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) P::add(st[c], xn[c], S, pole, cn);
-  }
-  const double al = m.alpha[p], be = P::kVecOut ? m.beta[p] : 0.0;
+  const double al = pr.alpha, be = P::kVecOut ? pr.beta : 0.0;
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
     if (lane + 64 * c < nlev) P::store(out, (size_t)node * L + lane + 64 * c, st[c], al, be, cx, cy, ci);
 }
 
-template <class T, int OP, int NCH>
-__global__ void __launch_bounds__(1024) k_column(DevMesh m, const T *__restrict__ in,
+template <class T, int OP, int NCH, int G>
+__device__ __forceinline__ void column_pos(const DevMesh &m, const T *__restrict__ in,
+                                           T *__restrict__ out, int nlev, int p,
+                                           const PosRec &pr, int lane) {
+  if (NCH > 0) {
+    // G = 6: one load group covers every row of a mesh of degree <= 6 (the
+    // octahedral mesh, pole edge included); G = 8: rows in groups
+    column_node<T, OP, (NCH > 0 ? NCH : 1), G, G == 6>(m, in, out, nlev, pr, lane);
+  } else {
+    // any nlev: chunks of 64 levels one after another
+    for (int k = lane; k < nlev; k += 64) element<T, OP>(m, in, out, nlev, p, pr.node, pr.r0, pr.r1, k);
+  }
+}
+
+// Tiled schedule (cyc == 0): one workgroup per tile / block of positions.
+// Persistent schedule (cyc > 0 workgroups per XCD): the wavefronts of XCD x
+// take positions of its share [V x/8, V (x+1)/8) cyclically, wavefront g at
+// step t computing position lo + g + t * (cyc * waves per block).
+template <class T, int OP, int NCH, int G>
+__global__ void __launch_bounds__(512) k_column(DevMesh m, const T *__restrict__ in,
                                                  T *__restrict__ out, int nlev, int npb,
-                                                 int per_xcd) {
-  int p0, p1;
-  if (!tile_range(m, xcd_tile(blockIdx.x, per_xcd), npb, p0, p1)) return;
+                                                 int per_xcd, int cyc) {
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  for (int p = p0 + wave; p < p1; p += nw) {
-    const int node = __builtin_amdgcn_readfirstlane(m.perm[p]);
-    const int r0 = __builtin_amdgcn_readfirstlane(m.rowp[p]);
-    const int r1 = __builtin_amdgcn_readfirstlane(m.rowp[p + 1]);
-    if (NCH > 0) {
-      column_node<T, OP, (NCH > 0 ? NCH : 1)>(m, in, out, nlev, p, node, r0, r1, lane);
-    } else {
-      // any nlev: chunks of 64 levels one after another
-      for (int k = lane; k < nlev; k += 64) element<T, OP>(m, in, out, nlev, p, node, r0, r1, k);
-    }
+  int p, p1, stride;
+  if (cyc > 0) {
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+    const int lo = (int)((int64_t)m.V * x / 8);
+    p1 = (int)((int64_t)m.V * (x + 1) / 8);
+    p = lo + i * nw + wave;
+    stride = cyc * nw;
+  } else {
+    int p0;
+    if (!tile_range(m, xcd_tile(blockIdx.x, per_xcd), npb, p0, p1)) return;
+    p = p0 + wave;
+    stride = nw;
+  }
+  if (p >= p1) return;
+  PosRec cur = m.pos[p];
+  for (; p < p1; p += stride) {
+    const PosRec nxt = m.pos[min(p + stride, p1 - 1)];  // prefetch
+    column_pos<T, OP, NCH, G>(m, in, out, nlev, p, cur, lane);
+    cur = nxt;
   }
 }
 
@@ -415,16 +451,16 @@ __global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ 
 
   // staging: wavefront w moves nodes w, w+nw, ... of a run; lanes = levels
   V regs[EPT];
+  const int lane_c = min(lane, kc - 1);
   auto fetch = [&](int q) {
     const int4 sg = m.seg[s0 + q];  // ring offset, ring size, first index, length
+    // no branches around the loads: slots past the run re-read its last node
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int t = wave + i * nw;
-      if (t < sg.w && lane_on) {
-        int ii = sg.z + t;
-        if (ii >= sg.y) ii -= sg.y;
-        regs[i] = vin[(size_t)(sg.x + ii) * L + k0 + lane];
-      }
+      const int t = max(0, min(wave + i * nw, sg.w - 1));
+      int ii = sg.z + t;
+      if (ii >= sg.y) ii -= sg.y;
+      regs[i] = vin[(size_t)(sg.x + ii) * L + k0 + lane_c];
     }
   };
   auto deposit = [&](int q) {
@@ -459,10 +495,8 @@ __global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ 
     if (lane_on) {
       const V *bq = buf + (q & 3) * slot_stride;
       for (int p = pr.x + wave; p < pr.y; p += nw) {
-        const int node = __builtin_amdgcn_readfirstlane(m.perm[p]);
-        const int r0 = __builtin_amdgcn_readfirstlane(m.rowp[p]);
-        const int r1 = __builtin_amdgcn_readfirstlane(m.rowp[p + 1]);
-        const int ts = __builtin_amdgcn_readfirstlane(m.selfslot[p]);
+        const PosRec rec = m.pos[p];
+        const int node = rec.node, r0 = rec.r0, r1 = rec.r1, ts = rec.selfslot;
         const double ci = P::kVecIn ? m.coslat[node] : 0.0;
         typename P::St st;
         P::init(st, bq[ts * kc + lane], ci);
@@ -471,34 +505,30 @@ __global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ 
           // all loads of the group first (indices clamped into the row),
           // then the accumulation in row order
           int lr[G];
-          uint32_t nb[G];
           double2 S[G];
           V xn[G];
           double cn[G];
 #pragma unroll
-          for (int j = 0; j < G; ++j) {
-            const int r = min(rb + j, r1 - 1);
-            lr[j] = m.lref[r];
-            nb[j] = (uint32_t)m.nbr[r];
-            S[j] = m.S[r];
+          for (int j = 0; j < G; ++j) {  // whole group, contiguous (arrays padded)
+            lr[j] = m.lref[rb + j];
+            S[j] = m.S[rb + j];
+            cn[j] = P::kVecIn ? m.ncos[rb + j] : 0.0;
           }
 #pragma unroll
           for (int j = 0; j < G; ++j) {
-            const int l = lr[j] < 0 ? (1 << 16) | ts : lr[j];  // pole: placeholder
+            const int l = lr[j] & ~kLrefPole;
             xn[j] = buf[((q + (l >> 16) - 1) & 3) * slot_stride + (l & 0xffff) * kc + lane];
-            cn[j] = P::kVecIn ? m.coslat[nb[j] & ~kPoleBit] : 0.0;
           }
 #pragma unroll
           for (int j = 0; j < G; ++j) {
             if (rb + j >= r1) break;
-            const bool pole = lr[j] < 0;
+            const bool pole = (lr[j] & kLrefPole) != 0;
             if (P::kVecIn && pole) continue;
-            if (pole) xn[j] = vin[(size_t)(nb[j] & ~kPoleBit) * L + k0 + lane];
             closure_add<OP>(cx, cy, S[j], pole);
             P::add(st, xn[j], S[j], pole, cn[j]);
           }
         }
-        const double al = m.alpha[p], be = P::kVecOut ? m.beta[p] : 0.0;
+        const double al = rec.alpha, be = P::kVecOut ? rec.beta : 0.0;
         P::store(out, (size_t)node * L + k0 + lane, st, al, be, cx, cy, ci);
       }
     }
@@ -698,11 +728,15 @@ atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hip
 // ---------------------------------------------------------------------------
 __global__ void k_derive_scales(int V, const double *__restrict__ vol,
                                 const double *__restrict__ cosl, double R,
-                                double *__restrict__ alpha, double *__restrict__ beta) {
+                                double *__restrict__ alpha, double *__restrict__ beta,
+                                PosRec *__restrict__ pos) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < V) {
-    alpha[p] = R / vol[p];
-    beta[p] = (R * cosl[p]) / vol[p];
+    const double a = R / vol[p], b = (R * cosl[p]) / vol[p];
+    alpha[p] = a;
+    beta[p] = b;
+    pos[p].alpha = a;
+    pos[p].beta = b;
   }
 }
 
@@ -711,7 +745,7 @@ atlas_status derive_scales(MeshStore &m, const double *vol_by_pos, const double 
   const int V = m.d.V;
   hipLaunchKernelGGL(k_derive_scales, dim3((V + 255) / 256), dim3(256), 0, 0, V, vol_by_pos,
                      cos_by_pos, radius, const_cast<double *>(m.d.alpha),
-                     const_cast<double *>(m.d.beta));
+                     const_cast<double *>(m.d.beta), const_cast<PosRec *>(m.d.pos));
   ATLASX_HIP(hipGetLastError());
   return ATLAS_OK;
 }
@@ -739,6 +773,19 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 // Levels per chunk of the sweep form: at most 64 (one per lane), split
 // evenly (137 -> 46, 46, 45).
 static int sweep_chunk(int nlev, int want) {
@@ -757,6 +804,8 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
   const dim3 grid(per_xcd * 8), block(sh.block);
   switch (sh.variant) {
     case ATLAS_VARIANT_COLUMN: {
+      if (sh.block > 512 && sh.level_chunk == 0)
+        return fail(ATLAS_EINVAL, "the column form takes at most 512 threads per block");
       if (sh.level_chunk > 0) {
         const int nchunk = (nlev + sh.level_chunk - 1) / sh.level_chunk;
         const int units = ntiles * nchunk;
@@ -766,9 +815,18 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         break;
       }
       const int nch = (nlev + 63) / 64;
+      // persistent grid: blocks_per_cu workgroups on every compute unit
+      const int cyc = sh.blocks_per_cu > 0 ? sh.blocks_per_cu * device_cu_count() / 8 : 0;
+      const dim3 cgrid = cyc > 0 ? dim3(8 * cyc) : grid;
 #define ATLASX_COL(N)                                                                  \
-  hipLaunchKernelGGL((k_column<T, OP, N>), grid, block, 0, st, m, in, out, nlev,       \
-                     sh.nodes_per_block, per_xcd)
+  do {                                                                                 \
+    if (m.maxdeg <= 6)                                                                 \
+      hipLaunchKernelGGL((k_column<T, OP, N, 6>), cgrid, block, 0, st, m, in, out, nlev, \
+                         sh.nodes_per_block, per_xcd, cyc);                            \
+    else                                                                               \
+      hipLaunchKernelGGL((k_column<T, OP, N, 8>), cgrid, block, 0, st, m, in, out, nlev, \
+                         sh.nodes_per_block, per_xcd, cyc);                            \
+  } while (0)
       if (nch == 1) ATLASX_COL(1);
       else if (nch == 2) ATLASX_COL(2);
       else if (nch == 3) ATLASX_COL(3);

@@ -88,7 +88,7 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
     base = _run(P, gm, op, x)
     shapes = []
     for variant in (P.VARIANT_COLUMN, P.VARIANT_FLAT):
-        for block in (64, 256, 1024):
+        for block in (64, 256, 512):
             for npb in (0, 1, 7, 64):
                 shapes.append(P.Launch(variant, block, npb))
     shapes.append(P.Launch(P.VARIANT_FLUX, 256, 0))
@@ -98,6 +98,9 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))
     for kc in (1, 7, 64):
         shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, kc))
+    for block in (64, 256):
+        for bpc in (1, 3, 8):
+            shapes.append(P.Launch(P.VARIANT_COLUMN, block, 0, 0, bpc))
     for sh in shapes:
         got = _run(P, gm, op, x, launch=sh)
         assert torch.equal(got, base), (sh.variant, sh.block_threads, sh.nodes_per_block)
