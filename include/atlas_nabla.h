@@ -52,7 +52,8 @@ typedef enum {
   ATLAS_EDEVICE = -3,  /* a HIP runtime call failed                        */
   ATLAS_EBUSY = -4,    /* resource in use (e.g. freeing a registered mesh) */
   ATLAS_ESTATE = -5,   /* call not valid in the object's current state    */
-  ATLAS_ETIMEOUT = -6  /* a bounded wait expired                           */
+  ATLAS_ETIMEOUT = -6, /* a bounded wait expired                           */
+  ATLAS_ECANCELLED = -7 /* the request was cancelled before it ran         */
 } atlas_status;
 
 typedef enum { ATLAS_F32 = 0, ATLAS_F64 = 1 } atlas_dtype;

@@ -17,7 +17,8 @@ import threading
 import numpy as np
 
 from . import _abi
-from ._abi import (ATLAS_F32, ATLAS_F64, ATLAS_OP_CURL, ATLAS_OP_DIVERGENCE,  # noqa: F401
+from ._abi import (ATLAS_ECANCELLED, ATLAS_ENOMEM, ATLAS_OK,  # noqa: F401
+                   ATLAS_F32, ATLAS_F64, ATLAS_OP_CURL, ATLAS_OP_DIVERGENCE,  # noqa: F401
                    ATLAS_OP_GRADIENT, ATLAS_OP_LAPLACIAN, VARIANT_AUTO, VARIANT_COLUMN,
                    VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP, AtlasError, Launch, Layout, MeshDesc,
                    MeshInfo)
@@ -223,7 +224,156 @@ class Mesh:
                                                         int(dtype_code)))
 
 
-__all__ = ["Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
+def autotune(mesh, op: int, x, out, workspace=None, stream=None):
+    """Time the candidate launch shapes for (mesh, op, dtype, nlev) on these
+    buffers; the mesh remembers the fastest.  Returns (Launch, ms)."""
+    vec_in = op in (ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL)
+    nlev = mesh._nlev_vector(x) if vec_in else mesh._nlev_scalar(x)
+    best = Launch()
+    ms = ctypes.c_float()
+    ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+    _check(lib().atlas_autotune(mesh.handle, int(op), _dev_ptr(x, "x"), nlev, _dtype_code(x),
+                                _dev_ptr(out, "out"), ws, _stream(stream), ctypes.byref(best),
+                                ctypes.byref(ms)))
+    return best, ms.value
+
+
+class Batch:
+    """Many operator applications in one persistent launch (atlas_batch.h).
+    items: list of (mesh, op, x, out) or (mesh, op, x, out, workspace)."""
+
+    def __init__(self, items, *, use_graph=True, autotune=False, block_threads=0,
+                 blocks_per_cu=0, stream=None):
+        if not items:
+            raise ValueError("a batch needs at least one item")
+        self._keep = []
+        arr = (_abi.WorkItem * len(items))()
+        dtype = None
+        for i, it in enumerate(items):
+            mesh, op, x, out = it[:4]
+            ws = it[4] if len(it) > 4 else None
+            vec_in = op in (ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL)
+            nlev = mesh._nlev_vector(x) if vec_in else mesh._nlev_scalar(x)
+            d = _dtype_code(x)
+            if dtype is None:
+                dtype = d
+            elif d != dtype:
+                raise TypeError("all items of a batch share one dtype")
+            arr[i].mesh = mesh.handle
+            arr[i].op = int(op)
+            arr[i].nlev = nlev
+            arr[i].in_ = _dev_ptr(x, "input").value
+            arr[i].out = _dev_ptr(out, "output").value
+            arr[i].workspace = ws.data_ptr() if ws is not None else None
+            self._keep.append((mesh, x, out, ws))
+        cfg = _abi.BatchConfig(dtype, int(use_graph), int(autotune), int(block_threads),
+                               int(blocks_per_cu))
+        self._lib = lib()
+        self._h = ctypes.c_void_p()
+        _check(self._lib.atlas_batch_build(arr, len(items), ctypes.byref(cfg), _stream(stream),
+                                           ctypes.byref(self._h)))
+        info = _abi.BatchInfo()
+        _check(self._lib.atlas_batch_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+
+    def launch(self, stream=None):
+        _check(self._lib.atlas_batch_launch(self._h, _stream(stream)))
+
+    def check(self):
+        """Wait for the last launch."""
+        _check(self._lib.atlas_batch_check(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(self._lib.atlas_batch_free(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server (atlas_serve.h): HBM-budget admission, resident meshes,
+    continuous batching over `nstreams` HIP streams.  With simulate=True no
+    device is touched (launch durations follow bytes / sim_bytes_per_us)."""
+
+    def __init__(self, *, hbm_budget_bytes, nstreams=4, max_batch=64, batch_max_elems=0,
+                 simulate=False, sim_bytes_per_us=1e6, fail_alloc_every=0):
+        cfg = _abi.ServeConfig(int(hbm_budget_bytes), int(nstreams), int(max_batch),
+                               int(batch_max_elems), int(bool(simulate)), float(sim_bytes_per_us),
+                               int(fail_alloc_every))
+        self._lib = lib()
+        self._h = ctypes.c_void_p()
+        self._keep = {}
+        self._meshes = []
+        _check(self._lib.atlas_serve_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self.simulate = bool(simulate)
+
+    def register_mesh(self, mesh) -> int:
+        mid = ctypes.c_int32()
+        _check(self._lib.atlas_serve_register_mesh(self._h, mesh.handle, ctypes.byref(mid)))
+        self._meshes.append(mesh)
+        return mid.value
+
+    def register_sim_mesh(self, nnodes: int) -> int:
+        mid = ctypes.c_int32()
+        _check(self._lib.atlas_serve_register_sim_mesh(self._h, int(nnodes), ctypes.byref(mid)))
+        return mid.value
+
+    def submit(self, mesh_id: int, op: int, x=None, out=None, *, nlev=None, dtype=None) -> int:
+        """Device request: x (and out, or None for a server-owned output) are
+        device tensors [V][nlev] or [V][nlev][2].  Simulation request: x is
+        None and nlev, dtype (ATLAS_F32/ATLAS_F64) are given."""
+        if x is None:
+            req = _abi.Request(int(mesh_id), int(op), int(dtype), int(nlev), None, None)
+        else:
+            vec_in = op in (ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL)
+            lev = x.shape[1] if x.dim() >= 2 else 1
+            if vec_in and (x.dim() != 3 or x.shape[2] != 2):
+                raise ValueError("vector input must be [V][nlev][2]")
+            req = _abi.Request(int(mesh_id), int(op), _dtype_code(x), int(lev),
+                               _dev_ptr(x, "input").value,
+                               _dev_ptr(out, "output").value if out is not None else None)
+        t = ctypes.c_uint64()
+        _check(self._lib.atlas_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (x, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> dict:
+        r = _abi.Result()
+        _check(self._lib.atlas_serve_wait(self._h, int(ticket), int(timeout_us), ctypes.byref(r)))
+        return {"status": r.status, "batch_size": r.batch_size, "out": r.out or 0,
+                "queue_us": r.queue_us, "run_us": r.run_us, "total_us": r.total_us}
+
+    def cancel(self, ticket: int):
+        _check(self._lib.atlas_serve_cancel(self._h, int(ticket)))
+
+    def release(self, ticket: int):
+        _check(self._lib.atlas_serve_release(self._h, int(ticket)))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        s = _abi.ServeStats()
+        _check(self._lib.atlas_serve_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _abi.ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(self._lib.atlas_serve_destroy(self._h))
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Server", "Batch", "autotune", "Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
            "ATLAS_F32", "ATLAS_F64", "ATLAS_OP_GRADIENT", "ATLAS_OP_DIVERGENCE",
            "ATLAS_OP_CURL", "ATLAS_OP_LAPLACIAN", "VARIANT_AUTO", "VARIANT_COLUMN",
            "VARIANT_FLAT", "VARIANT_FLUX", "VARIANT_SWEEP"]

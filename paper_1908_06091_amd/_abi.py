@@ -10,7 +10,9 @@ ATLAS_OP_GRADIENT, ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL, ATLAS_OP_LAPLACIAN = 0, 1
 VARIANT_AUTO, VARIANT_COLUMN, VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP = 0, 1, 2, 3, 4
 
 STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EDEVICE",
-          -4: "ATLAS_EBUSY", -5: "ATLAS_ESTATE", -6: "ATLAS_ETIMEOUT"}
+          -4: "ATLAS_EBUSY", -5: "ATLAS_ESTATE", -6: "ATLAS_ETIMEOUT", -7: "ATLAS_ECANCELLED"}
+ATLAS_OK, ATLAS_EINVAL, ATLAS_ENOMEM, ATLAS_EDEVICE = 0, -1, -2, -3
+ATLAS_EBUSY, ATLAS_ESTATE, ATLAS_ETIMEOUT, ATLAS_ECANCELLED = -4, -5, -6, -7
 
 
 class AtlasError(RuntimeError):
@@ -57,7 +59,52 @@ class Launch(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32)]
 
 
-# name -> (restype, argtypes); every symbol the header declares
+class WorkItem(ctypes.Structure):
+    _fields_ = [("mesh", ctypes.c_void_p), ("op", ctypes.c_int32), ("nlev", ctypes.c_int32),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("nitems", ctypes.c_int32), ("nunits", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("form_column", ctypes.c_int32),
+                ("form_flat", ctypes.c_int32), ("owned_bytes", ctypes.c_size_t)]
+
+
+# name -> (restype, argtypes); every symbol the headers declare
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("nstreams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("batch_max_elems", ctypes.c_int64),
+                ("simulate", ctypes.c_int32), ("sim_bytes_per_us", ctypes.c_double),
+                ("fail_alloc_every", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mesh_id", ctypes.c_int32), ("op", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("nlev", ctypes.c_int32), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("queue_us", ctypes.c_double),
+                ("run_us", ctypes.c_double), ("total_us", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("batched_launches", ctypes.c_uint64), ("inflight_bytes", ctypes.c_size_t),
+                ("peak_inflight_bytes", ctypes.c_size_t)]
+
+
 SIGNATURES = {
     "atlas_last_error": (ctypes.c_char_p, []),
     "atlas_version": (ctypes.c_char_p, []),
@@ -88,8 +135,33 @@ SIGNATURES = {
                                          ctypes.c_void_p]),
     "atlas_bandwidth_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                              ctypes.c_int32, ctypes.c_void_p]),
+    "atlas_batch_build": (ctypes.c_int, [ctypes.POINTER(WorkItem), ctypes.c_int32,
+                                         ctypes.POINTER(BatchConfig), ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_batch_check": (ctypes.c_int, [ctypes.c_void_p]),
+    "atlas_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchInfo)]),
+    "atlas_batch_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "atlas_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Launch),
+                                      ctypes.POINTER(ctypes.c_float)]),
     "atlas_flux_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int,
                                                      ctypes.c_int32, ctypes.c_int]),
+    "atlas_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig),
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_serve_register_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.POINTER(ctypes.c_int32)]),
+    "atlas_serve_register_sim_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                                     ctypes.POINTER(ctypes.c_int32)]),
+    "atlas_serve_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "atlas_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                                        ctypes.POINTER(Result)]),
+    "atlas_serve_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "atlas_serve_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "atlas_serve_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServeStats)]),
+    "atlas_serve_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 

@@ -1,0 +1,378 @@
+// batch.cpp -- batched persistent launch (atlas_batch.h) and the autotuner.
+//
+// A batch is the device-side analogue of applying the Nabla operators
+// (Section 4.7) to every field of a FieldSet (Section 4.6) in one go: one
+// persistent kernel pulls (item, block of nodes, phase) units from per-XCD
+// queues; the launch can be captured once in a hipGraph and replayed.
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <new>
+#include <vector>
+
+#include "atlas_batch.h"
+#include "internal.h"
+
+namespace atlasx {
+
+atlas_status check_call(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
+                        atlas_dtype dt, void *out);
+atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
+                   atlas_dtype dt, void *out, void *workspace, const atlas_launch *shape,
+                   hipStream_t stream);
+
+ItemShape heuristic_shape(int nlev) {
+  if (nlev >= 48) return {FORM_COLUMN, 16};
+  const int npb = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));
+  return {FORM_FLAT, npb};
+}
+
+// Units of a batch: every item's nodes in blocks of its npb, each item's
+// blocks split into 8 contiguous runs, one per queue (XCD); pass 0 holds
+// every unit of phase 0, pass 1 the divergence units of the Laplacians.
+// qbeg[9 * pass + x] is where queue x of that pass starts in `units`.
+void plan_units(const std::vector<BatchItem> &items, const std::vector<ItemShape> &shapes,
+                std::vector<BatchUnit> &units, std::vector<int> &qbeg) {
+  std::vector<std::vector<BatchUnit>> q0(8), q1(8);
+  for (size_t i = 0; i < items.size(); ++i) {
+    const int V = items[i].m.V, npb = std::max(1, shapes[i].npb);
+    const int nu = (V + npb - 1) / npb;
+    for (int x = 0; x < 8; ++x) {
+      const int u0 = (int)((int64_t)nu * x / 8), u1 = (int)((int64_t)nu * (x + 1) / 8);
+      for (int u = u0; u < u1; ++u) {
+        const BatchUnit un{(int)i, u * npb, std::min(V, (u + 1) * npb), 0};
+        q0[x].push_back(un);
+        if (items[i].lapl) q1[x].push_back({(int)i, un.p0, un.p1, 1});
+      }
+    }
+  }
+  units.clear();
+  qbeg.assign(18, 0);
+  for (int pass = 0; pass < 2; ++pass) {
+    auto &q = pass ? q1 : q0;
+    for (int x = 0; x < 8; ++x) {
+      qbeg[9 * pass + x] = (int)units.size();
+      units.insert(units.end(), q[x].begin(), q[x].end());
+    }
+    qbeg[9 * pass + 8] = (int)units.size();
+  }
+}
+
+namespace {
+
+struct Batch {
+  atlas_dtype dtype = ATLAS_F32;
+  int nitems = 0, nunits = 0, grid = 0, block = 256;
+  bool two_pass = false;
+  int form_column = 0, form_flat = 0;
+  BatchItem *d_items = nullptr;
+  BatchUnit *d_units = nullptr;
+  int *d_qbeg = nullptr;  // [18]: queue starts of pass 0, then of pass 1
+  int *d_heads = nullptr; // [16]: queue heads of pass 0, then of pass 1
+  std::vector<void *> owned;  // batch-owned Laplacian workspaces
+  size_t owned_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  hipEvent_t last = nullptr;
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (last) (void)hipEventDestroy(last);
+    for (void *p : owned) (void)hipFree(p);
+    if (d_items) (void)hipFree(d_items);
+    if (d_units) (void)hipFree(d_units);
+    if (d_qbeg) (void)hipFree(d_qbeg);
+    if (d_heads) (void)hipFree(d_heads);
+  }
+};
+
+}  // namespace
+
+// Times one launch shape (median of three after a warm-up) on `st`.
+static float time_shape(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
+                        atlas_dtype dt, void *out, void *ws, const atlas_launch &l,
+                        hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (apply(mesh, op, in, nlev, dt, out, ws, &l, st) != ATLAS_OK) return -1.0f;
+  float best = 1e30f;
+  for (int r = 0; r < 3; ++r) {
+    (void)hipEventRecord(e0, st);
+    if (apply(mesh, op, in, nlev, dt, out, ws, &l, st) != ATLAS_OK) return -1.0f;
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.0f;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms);
+  }
+  return best;
+}
+
+static std::vector<atlas_launch> candidates(const MeshStore &m, int nlev) {
+  std::vector<atlas_launch> c;
+  auto add = [&](int v, int b, int npb, int kc, int bpc) { c.push_back({v, b, npb, kc, bpc}); };
+  if (nlev >= 32) {
+    add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 256, 4, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 128, 0, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 4);
+    if (m.d.sweep_ok) {
+      add(ATLAS_VARIANT_SWEEP, 256, 0, 0, 0);
+      add(ATLAS_VARIANT_SWEEP, 512, 0, 0, 0);
+    }
+  }
+  const int fl = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));
+  add(ATLAS_VARIANT_FLAT, 256, fl, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 256, std::max(1, fl / 4), 0, 0);
+  add(ATLAS_VARIANT_FLAT, 256, 0, 0, 0);
+  if (nlev < 32) add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0);
+  return c;
+}
+
+atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, atlas_dtype dt,
+                      void *out, void *ws, hipStream_t st, atlas_launch *best, float *best_ms) {
+  atlas_status s = check_call(mesh, op, in, nlev, dt, out);
+  if (s != ATLAS_OK) return s;
+  MeshStore &m = *mesh->store;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ATLASX_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ATLAS_EDEVICE, "hipEventCreate failed");
+  }
+  float bt = 1e30f;
+  atlas_launch bl{};
+  for (const atlas_launch &c : candidates(m, nlev)) {
+    const float t = time_shape(mesh, op, in, nlev, dt, out, ws, c, st, e0, e1);
+    if (t >= 0.0f && t < bt) {
+      bt = t;
+      bl = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (bt >= 1e29f) return fail(ATLAS_EDEVICE, "no launch shape ran");
+  {
+    std::lock_guard<std::mutex> g(m.tune_mu);
+    LaunchShape sh;
+    sh.variant = bl.variant;
+    sh.block = bl.block_threads;
+    sh.nodes_per_block = bl.nodes_per_block;
+    sh.level_chunk = bl.level_chunk;
+    sh.blocks_per_cu = bl.blocks_per_cu;
+    m.tuned[TuneKey{(int)op, (int)dt, nlev}] = sh;
+  }
+  if (best) *best = bl;
+  if (best_ms) *best_ms = bt;
+  return ATLAS_OK;
+}
+
+// The form a batch uses for an item class after autotuning: the fastest of
+// the column / flat candidates with their tile sizes.
+static ItemShape tuned_item_shape(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
+                                  atlas_dtype dt, void *out, void *ws, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ItemShape best = heuristic_shape(nlev);
+  if (hipEventCreate(&e0) != hipSuccess) return best;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return best;
+  }
+  float bt = 1e30f;
+  const int fl = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));
+  const ItemShape cands[] = {{FORM_COLUMN, 8}, {FORM_COLUMN, 32}, {FORM_FLAT, fl},
+                             {FORM_FLAT, std::max(1, fl / 4)}};
+  for (const ItemShape &c : cands) {
+    const atlas_launch l{c.form == FORM_COLUMN ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT, 256,
+                         c.npb, 0, 0};
+    const float t = time_shape(mesh, op, in, nlev, dt, out, ws, l, st, e0, e1);
+    if (t >= 0.0f && t < bt) {
+      bt = t;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+}  // namespace atlasx
+
+using namespace atlasx;
+
+struct atlas_batch_s {
+  Batch *b;
+};
+
+extern "C" {
+
+atlas_status atlas_autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
+                            atlas_dtype dtype, void *out, void *workspace, hipStream_t stream,
+                            atlas_launch *best, float *best_ms) {
+  return autotune(mesh, op, in, nlev, dtype, out, workspace, stream, best, best_ms);
+}
+
+atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
+                               const atlas_batch_config *cfg, hipStream_t stream,
+                               atlas_batch_t *out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!items || n < 1) return fail(ATLAS_EINVAL, "a batch needs at least one item");
+  if (n > (1 << 20)) return fail(ATLAS_EINVAL, "too many items");
+  const atlas_batch_config c = cfg ? *cfg : atlas_batch_config{ATLAS_F32, 0, 0, 0, 0};
+  if (c.dtype != ATLAS_F32 && c.dtype != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
+  const int block = c.block_threads ? c.block_threads : 256;
+  if (block < 64 || block > 256 || (block & 63))
+    return fail(ATLAS_EINVAL, "block_threads must be 64, 128, 192 or 256");
+  if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32)
+    return fail(ATLAS_EINVAL, "bad batch configuration");
+  const atlas_dtype dt = (atlas_dtype)c.dtype;
+  const size_t w = dt == ATLAS_F64 ? 8 : 4;
+  // validate every item before allocating anything
+  for (int i = 0; i < n; ++i) {
+    const atlas_work_item &it = items[i];
+    atlas_status s = check_call(it.mesh, (atlas_op)it.op, it.in, it.nlev, dt, it.out);
+    if (s != ATLAS_OK) return s;
+    if (it.op == ATLAS_OP_LAPLACIAN && it.workspace &&
+        ((uintptr_t)it.workspace % (2 * w)) != 0)
+      return fail(ATLAS_EINVAL, "workspace misaligned");
+  }
+  Batch *b = new (std::nothrow) Batch();
+  if (!b) return fail(ATLAS_ENOMEM, "out of host memory");
+  b->dtype = dt;
+  b->nitems = n;
+  b->block = block;
+  auto bail = [&](atlas_status s) {
+    delete b;
+    return s;
+  };
+  std::vector<BatchItem> h_items(n);
+  std::vector<ItemShape> h_shapes(n);
+  std::map<std::tuple<const void *, int, int>, ItemShape> shapes;
+  for (int i = 0; i < n; ++i) {
+    const atlas_work_item &it = items[i];
+    MeshStore &m = *it.mesh->store;
+    BatchItem &bi = h_items[i];
+    std::memset(&bi, 0, sizeof(bi));
+    bi.m = m.d;
+    bi.lapl = it.op == ATLAS_OP_LAPLACIAN ? 1 : 0;
+    bi.op = it.op == ATLAS_OP_DIVERGENCE ? 1 : it.op == ATLAS_OP_CURL ? 2 : 0;
+    bi.nlev = it.nlev;
+    bi.in = it.in;
+    bi.out = it.out;
+    bi.ws = it.workspace;
+    if (bi.lapl && !bi.ws) {
+      void *p = nullptr;
+      const size_t bytes = (size_t)m.d.V * it.nlev * 2 * w;
+      if (hipMalloc(&p, bytes) != hipSuccess) return bail(fail(ATLAS_ENOMEM, "batch workspace"));
+      b->owned.push_back(p);
+      b->owned_bytes += bytes;
+      bi.ws = p;
+    }
+    const auto key = std::make_tuple((const void *)&m, it.op, it.nlev);
+    auto f = shapes.find(key);
+    ItemShape sh;
+    if (f != shapes.end()) {
+      sh = f->second;
+    } else {
+      sh = c.autotune ? tuned_item_shape(it.mesh, (atlas_op)(bi.lapl ? ATLAS_OP_GRADIENT : it.op),
+                                         it.in, it.nlev, dt, bi.lapl ? bi.ws : it.out, nullptr,
+                                         stream)
+                      : heuristic_shape(it.nlev);
+      shapes[key] = sh;
+    }
+    bi.form = sh.form;
+    (sh.form == FORM_COLUMN ? b->form_column : b->form_flat) += 1;
+    h_shapes[i] = sh;
+    b->two_pass = b->two_pass || bi.lapl;
+  }
+  std::vector<BatchUnit> h_units;
+  std::vector<int> qbeg;
+  plan_units(h_items, h_shapes, h_units, qbeg);
+  b->nunits = (int)h_units.size();
+  if (hipMalloc(&b->d_items, sizeof(BatchItem) * n) != hipSuccess ||
+      hipMalloc(&b->d_units, sizeof(BatchUnit) * std::max<size_t>(1, h_units.size())) != hipSuccess ||
+      hipMalloc(&b->d_qbeg, sizeof(int) * 18) != hipSuccess ||
+      hipMalloc(&b->d_heads, sizeof(int) * 16) != hipSuccess)
+    return bail(fail(ATLAS_ENOMEM, "batch tables"));
+  b->owned_bytes += sizeof(BatchItem) * n + sizeof(BatchUnit) * h_units.size() + 4 * (18 + 16);
+  if (hipMemcpy(b->d_items, h_items.data(), sizeof(BatchItem) * n, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->d_units, h_units.data(), sizeof(BatchUnit) * h_units.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_qbeg, qbeg.data(), sizeof(int) * 18, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(ATLAS_EDEVICE, "batch table upload"));
+  const int bpc = c.blocks_per_cu ? c.blocks_per_cu : batch_blocks_per_cu(dt, block);
+  b->grid = std::max(8, (device_cu_count() * bpc + 7) / 8 * 8);
+  if (hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(ATLAS_EDEVICE, "event"));
+  if (c.use_graph) {
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(ATLAS_EDEVICE, "capture stream"));
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bail(fail(ATLAS_EDEVICE, "hipStreamBeginCapture"));
+    atlas_status s = launch_batch(dt, b->d_items, b->d_units, b->d_qbeg, b->d_qbeg + 9,
+                                  b->two_pass, b->d_heads, b->grid, block, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (s != ATLAS_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return bail(s != ATLAS_OK ? s : fail(ATLAS_EDEVICE, "hipStreamEndCapture"));
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+      return bail(fail(ATLAS_EDEVICE, "hipGraphInstantiate"));
+  }
+  atlas_batch_t h = new (std::nothrow) atlas_batch_s{b};
+  if (!h) return bail(fail(ATLAS_ENOMEM, "out of host memory"));
+  *out = h;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_batch_launch(atlas_batch_t batch, hipStream_t stream) {
+  if (!batch || !batch->b) return fail(ATLAS_EINVAL, "batch is NULL");
+  Batch &b = *batch->b;
+  if (b.exec) {
+    ATLASX_HIP(hipGraphLaunch(b.exec, stream));
+  } else {
+    atlas_status s = launch_batch(b.dtype, b.d_items, b.d_units, b.d_qbeg, b.d_qbeg + 9,
+                                  b.two_pass, b.d_heads, b.grid, b.block, stream);
+    if (s != ATLAS_OK) return s;
+  }
+  ATLASX_HIP(hipEventRecord(b.last, stream));
+  return ATLAS_OK;
+}
+
+atlas_status atlas_batch_check(atlas_batch_t batch) {
+  if (!batch || !batch->b) return fail(ATLAS_EINVAL, "batch is NULL");
+  ATLASX_HIP(hipEventSynchronize(batch->b->last));
+  return ATLAS_OK;
+}
+
+atlas_status atlas_batch_get_info(atlas_batch_t batch, atlas_batch_info *info) {
+  if (!batch || !batch->b || !info) return fail(ATLAS_EINVAL, "NULL argument");
+  const Batch &b = *batch->b;
+  info->nitems = b.nitems;
+  info->nunits = b.nunits;
+  info->grid_blocks = b.grid;
+  info->block_threads = b.block;
+  info->graph = b.exec ? 1 : 0;
+  info->form_column = b.form_column;
+  info->form_flat = b.form_flat;
+  info->owned_bytes = b.owned_bytes;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_batch_free(atlas_batch_t batch) {
+  if (!batch) return ATLAS_OK;
+  if (batch->b && batch->b->last) (void)hipEventSynchronize(batch->b->last);
+  delete batch->b;
+  delete batch;
+  return ATLAS_OK;
+}
+
+}  // extern "C"

@@ -13,10 +13,6 @@
 
 #include "internal.h"
 
-struct atlas_mesh_s {
-  atlasx::MeshStore *store;
-};
-
 namespace atlasx {
 
 static thread_local std::string g_last_error;
@@ -294,6 +290,15 @@ namespace atlasx {
 LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
                        atlas_dtype dt) {
   LaunchShape s = default_shape(m, op, nlev, dt);
+  if (!l || l->variant == ATLAS_VARIANT_AUTO) {
+    // an autotuned shape for this (op, dtype, nlev), if any (the Laplacian
+    // runs its two passes with the gradient's shape)
+    MeshStore &ms = const_cast<MeshStore &>(m);
+    std::lock_guard<std::mutex> g(ms.tune_mu);
+    const int key_op = op == ATLAS_OP_LAPLACIAN ? (int)ATLAS_OP_GRADIENT : (int)op;
+    auto it = ms.tuned.find(TuneKey{key_op, (int)dt, nlev});
+    if (it != ms.tuned.end()) s = it->second;
+  }
   if (l && l->variant != ATLAS_VARIANT_AUTO) {
     s.variant = l->variant;
     s.block = l->block_threads;

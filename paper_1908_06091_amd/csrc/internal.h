@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -89,6 +90,57 @@ struct DevMesh {
   const double *ncos = nullptr;      // [I]  cos(lat) of the incidence's neighbour
 };
 
+// ------------------------------------------------------------- kernels
+struct MeshStore;
+
+struct LaunchShape {
+  int variant = ATLAS_VARIANT_COLUMN;
+  int block = 256;
+  int nodes_per_block = 0;  // 0 = the mesh's tiles
+  int level_chunk = 0;      // column form: levels per unit, 0 = all
+  int blocks_per_cu = 0;    // > 0: persistent wave-cyclic grid
+};
+
+// ------------------------------------------------------------- batches
+enum { FORM_COLUMN = 0, FORM_FLAT = 1 };
+
+struct BatchItem {       // device table entry of a batch
+  DevMesh m;
+  int32_t op;            // OP code of a single pass (Laplacian: see lapl)
+  int32_t lapl;          // 1: gradient into ws (phase 0), divergence (phase 1)
+  int32_t nlev;
+  int32_t form;          // FORM_COLUMN / FORM_FLAT
+  int32_t pad[4];
+  const void *in;
+  void *out;
+  void *ws;
+};
+
+struct BatchUnit {
+  int32_t item, p0, p1, phase;
+};
+
+atlas_status launch_batch(atlas_dtype dt, const BatchItem *items, const BatchUnit *units,
+                          const int *qbeg0, const int *qbeg1, bool two_pass, int *heads,
+                          int grid, int block, hipStream_t st);
+int batch_blocks_per_cu(atlas_dtype dt, int block);
+atlas_status launch_fill(int *p, int n, int value, hipStream_t st);
+
+// Tile shape of an item inside a batch: the form and positions per unit.
+struct ItemShape {
+  int form, npb;
+};
+ItemShape heuristic_shape(int nlev);
+void plan_units(const std::vector<BatchItem> &items, const std::vector<ItemShape> &shapes,
+                std::vector<BatchUnit> &units, std::vector<int> &qbeg);
+
+struct TuneKey {
+  int op, dtype, nlev;
+  bool operator<(const TuneKey &o) const {
+    return op != o.op ? op < o.op : dtype != o.dtype ? dtype < o.dtype : nlev < o.nlev;
+  }
+};
+
 struct MeshStore {
   DevMesh d;
   int device = 0;
@@ -102,16 +154,10 @@ struct MeshStore {
   size_t ws_bytes = 0;
   int serve_refs = 0;
   double geometry_bytes = 0.0;
+  // autotuned launch shapes, keyed by (op, dtype, nlev)
+  std::mutex tune_mu;
+  std::map<TuneKey, LaunchShape> tuned;
   ~MeshStore();
-};
-
-// ------------------------------------------------------------- kernels
-struct LaunchShape {
-  int variant = ATLAS_VARIANT_COLUMN;
-  int block = 256;
-  int nodes_per_block = 0;  // 0 = the mesh's tiles
-  int level_chunk = 0;      // column form: levels per unit, 0 = all
-  int blocks_per_cu = 0;    // > 0: persistent wave-cyclic grid
 };
 
 int device_cu_count();
@@ -126,3 +172,8 @@ atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hip
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
 
 }  // namespace atlasx
+
+// the opaque mesh handle of the C ABI
+struct atlas_mesh_s {
+  atlasx::MeshStore *store;
+};

@@ -694,6 +694,104 @@ __global__ void __launch_bounds__(1024) k_gather_flux(DevMesh m, const T *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Batched persistent form.  Workgroup b serves work queue b mod 8 (one per
+// XCD); units are (item, block of positions, phase).  One launch runs one
+// pass: phase 0 (every single operator, and the gradient of every
+// Laplacian into its workspace), then, if any item is a Laplacian, a second
+// launch runs phase 1 (the divergence of that gradient) -- the dependency is
+// the launch order.  A workgroup never waits for another: it takes units
+// from its queue until the queue is drained, then exits.  heads[x] is queue
+// x's next unit.
+// ---------------------------------------------------------------------------
+template <class T, int OP>
+__device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, const T *in, T *out,
+                                              int nlev, int p0, int p1) {
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (form == FORM_COLUMN) {
+    const int nch = (nlev + 63) / 64;
+    for (int p = p0 + wave; p < p1; p += nw) {
+      const PosRec pr = m.pos[p];
+      if (m.maxdeg <= 6 && nch == 1) column_node<T, OP, 1, 6, true>(m, in, out, nlev, pr, lane);
+      else if (m.maxdeg <= 6 && nch == 2) column_node<T, OP, 2, 6, true>(m, in, out, nlev, pr, lane);
+      else if (m.maxdeg <= 6 && nch == 3) column_node<T, OP, 3, 6, true>(m, in, out, nlev, pr, lane);
+      else
+        for (int k = lane; k < nlev; k += 64) element<T, OP>(m, in, out, nlev, p, pr.node, pr.r0, pr.r1, k);
+    }
+  } else {
+    const int nel = (p1 - p0) * nlev;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+      const int pl = e / nlev;
+      const int k = e - pl * nlev;
+      const int p = p0 + pl;
+      element<T, OP>(m, in, out, nlev, p, m.perm[p], m.rowp[p], m.rowp[p + 1], k);
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_batch(const BatchItem *__restrict__ items,
+                                               const BatchUnit *__restrict__ units,
+                                               const int *__restrict__ qbeg, int *heads) {
+  __shared__ int s_u;
+  const int x = blockIdx.x & 7;
+  for (;;) {
+    if (threadIdx.x == 0) s_u = qbeg[x] + atomicAdd(&heads[x], 1);
+    __syncthreads();
+    const int u = s_u;
+    __syncthreads();
+    if (u >= qbeg[x + 1]) break;  // this queue is drained: every wave exits
+    const BatchUnit un = units[u];
+    const BatchItem &it = items[un.item];
+    const int op = it.lapl ? (un.phase ? OP_DIV : OP_GRAD) : it.op;
+    const T *src = static_cast<const T *>(un.phase ? it.ws : it.in);
+    T *dst = static_cast<T *>((it.lapl && un.phase == 0) ? it.ws : it.out);
+    if (op == OP_GRAD) batch_unit_op<T, OP_GRAD>(it.m, it.form, src, dst, it.nlev, un.p0, un.p1);
+    else if (op == OP_DIV) batch_unit_op<T, OP_DIV>(it.m, it.form, src, dst, it.nlev, un.p0, un.p1);
+    else batch_unit_op<T, OP_CURL>(it.m, it.form, src, dst, it.nlev, un.p0, un.p1);
+  }
+}
+
+__global__ void k_fill(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+atlas_status launch_fill(int *p, int n, int value, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, st, p, n, value);
+  ATLASX_HIP(hipGetLastError());
+  return ATLAS_OK;
+}
+
+int batch_blocks_per_cu(atlas_dtype dt, int block) {
+  int n = 0;
+  hipError_t e = dt == ATLAS_F64
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double>, block, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float>, block, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+// One batch = counter reset (a kernel, not a memset, so it can live in a
+// captured graph) + the phase-0 pass + (if any) the phase-1 pass.
+atlas_status launch_batch(atlas_dtype dt, const BatchItem *items, const BatchUnit *units,
+                          const int *qbeg0, const int *qbeg1, bool two_pass, int *heads,
+                          int grid, int block, hipStream_t st) {
+  atlas_status s = launch_fill(heads, 16, 0, st);
+  if (s != ATLAS_OK) return s;
+  for (int pass = 0; pass < (two_pass ? 2 : 1); ++pass) {
+    const int *qb = pass ? qbeg1 : qbeg0;
+    int *hd = heads + 8 * pass;
+    if (dt == ATLAS_F64)
+      hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(block), 0, st, items, units, qb, hd);
+    else
+      hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(block), 0, st, items, units, qb, hd);
+    ATLASX_HIP(hipGetLastError());
+  }
+  return ATLAS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Streaming reference: read n, write 2n (the gradient's byte pattern).
 // ---------------------------------------------------------------------------
 template <class T>

@@ -1,0 +1,112 @@
+"""GPU tests of the batched persistent launch: every item of a batch equals
+the same operator launched alone, bit for bit; graph replays interleaved
+with other work stay identical."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_06091_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def meshes(P):
+    return {N: P.Mesh(N) for N in (8, 16, 24)}
+
+
+OPS = ("grad", "div", "curl", "lapl")
+
+
+def _op_code(P, op):
+    return {"grad": P.ATLAS_OP_GRADIENT, "div": P.ATLAS_OP_DIVERGENCE,
+            "curl": P.ATLAS_OP_CURL, "lapl": P.ATLAS_OP_LAPLACIAN}[op]
+
+
+def _make_items(P, meshes, n, dtype, seed):
+    rng = np.random.default_rng(seed)
+    items = []
+    for i in range(n):
+        N = int(rng.choice(list(meshes)))
+        gm = meshes[N]
+        nlev = int(rng.choice([1, 10, 91, 137]))
+        op = OPS[int(rng.integers(0, 4))]
+        vec_in = op in ("div", "curl")
+        shape = (gm.nnodes, nlev, 2) if vec_in else (gm.nnodes, nlev)
+        x = torch.from_numpy(rng.standard_normal(shape)).to(dtype=dtype, device="cuda")
+        oshape = (gm.nnodes, nlev, 2) if op == "grad" else (gm.nnodes, nlev)
+        out = torch.full(oshape, float("nan"), dtype=dtype, device="cuda")
+        items.append((gm, _op_code(P, op), x, out))
+    return items
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_items_equal_solo(P, meshes, dtype, use_graph, autotune):
+    print(f"batch dtype={dtype} graph={use_graph} autotune={autotune}", flush=True)
+    items = _make_items(P, meshes, 24, dtype, seed=7)
+    b = P.Batch(items, use_graph=use_graph, autotune=autotune)
+    assert b.info.nitems == 24 and b.info.graph == int(use_graph)
+    b.launch()
+    b.check()
+    for gm, op, x, out in items:
+        ref = gm.apply(op, x)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (op, x.shape)
+
+
+def test_graph_replays_with_eager_work_between(P, meshes):
+    items = _make_items(P, meshes, 16, torch.float32, seed=11)
+    b = P.Batch(items, use_graph=True)
+    b.launch()
+    b.check()
+    first = [out.clone() for _, _, _, out in items]
+    gm = meshes[16]
+    y = torch.randn(gm.nnodes, 7, device="cuda")
+    for _ in range(3):
+        for _, _, _, out in items:
+            out.fill_(float("nan"))
+        gm.laplacian(y)           # unrelated eager work between replays
+        torch.cuda.synchronize()
+        b.launch()
+        b.check()
+        for (_, _, _, out), ref in zip(items, first):
+            assert torch.equal(out, ref)
+
+
+def test_laplacian_items_two_passes(P, meshes):
+    """Laplacian items run as gradient then divergence passes of the batch;
+    mixed with other operators they still equal the single operator."""
+    gm = meshes[16]
+    x = torch.randn(gm.nnodes, 10, device="cuda")
+    y = torch.randn(gm.nnodes, 10, 2, device="cuda")
+    o1 = torch.empty_like(x)
+    o2 = torch.empty_like(x)
+    ws = torch.empty(gm.nnodes, 10, 2, device="cuda")
+    b = P.Batch([(gm, P.ATLAS_OP_LAPLACIAN, x, o1, ws), (gm, P.ATLAS_OP_DIVERGENCE, y, o2)],
+                use_graph=False)
+    b.launch()
+    b.check()
+    assert torch.equal(o1, gm.laplacian(x))
+    assert torch.equal(o2, gm.divergence(y))
+
+
+def test_batch_validation(P, meshes):
+    gm = meshes[8]
+    x32 = torch.randn(gm.nnodes, 3, device="cuda")
+    x64 = x32.double()
+    with pytest.raises(TypeError):
+        P.Batch([(gm, P.ATLAS_OP_GRADIENT, x32, torch.empty(gm.nnodes, 3, 2, device="cuda")),
+                 (gm, P.ATLAS_OP_GRADIENT, x64,
+                  torch.empty(gm.nnodes, 3, 2, device="cuda", dtype=torch.float64))])
+    with pytest.raises(P.AtlasError):
+        P.Batch([(gm, 9, x32, torch.empty(gm.nnodes, 3, device="cuda"))])
+    with pytest.raises(P.AtlasError):  # input and output overlap
+        P.Batch([(gm, P.ATLAS_OP_LAPLACIAN, x32, x32)])
