@@ -45,6 +45,11 @@ def parse_args():
     ap.add_argument("--no-extra-ops", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=16,
                     help="levels of the workload the CPU oracle sample covers")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-qps", type=float, default=400.0)
     return ap.parse_args()
 
 
@@ -125,6 +130,196 @@ def cpu_baseline(N, nlev_total, levels, f_host):
         "kind": "oracle",
         "sample": f"O{N} FP64 gradient, all {om.E} edges, first {levels} of {nlev_total} levels "
                   f"({dt:.1f} s)",
+    }, om
+
+
+def accuracy(gm, om, f64, uv64, torch, np, nsample=2000):
+    """Max and RMS error of the FP64 and FP32 paths against the FP64 oracle on
+    sampled nodes (all levels), normwise per output component."""
+    nlev = f64.shape[1]
+    rng = np.random.default_rng(1280)
+    nodes = np.sort(rng.choice(gm.nnodes, size=nsample, replace=False)).astype(np.int64)
+    idx = torch.from_numpy(nodes).to(f64.device)
+    f_h = f64.cpu().numpy()
+    uv_h = uv64.cpu().numpy()
+    refs = {"grad": om.gradient_at(f_h, nlev, nodes), "div": om.divergence_at(uv_h, nlev, nodes),
+            "lapl": om.laplacian_at(f_h, nlev, nodes)}
+    del f_h, uv_h
+    res = {}
+    for dt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
+        f, uv = f64.to(dt), uv64.to(dt)
+        for op, fn, x in (("grad", gm.gradient, f), ("div", gm.divergence, uv),
+                          ("lapl", gm.laplacian, f)):
+            got = fn(x).index_select(0, idx).double().cpu().numpy()
+            ref = refs[op]
+            comps = [(got[..., c], ref[..., c]) for c in range(2)] if op == "grad" else [(got, ref)]
+            emax = max(float(np.abs(g - r).max() / np.abs(r).max()) for g, r in comps)
+            erms = max(float(np.sqrt(((g - r) ** 2).mean() / (r ** 2).mean())) for g, r in comps)
+            res[f"{op}_{tag}"] = {"max_rel": emax, "rms_rel": erms}
+        del f, uv
+        torch.cuda.empty_cache()
+    res["sample"] = f"{nsample} random nodes x {nlev} levels, oracle evaluated per node"
+    return res
+
+
+def batch_bench(P, torch, np, dev):
+    """64 FP32 work items over O80/O160/O320 with nlev in {1,10,91,137} and
+    operators in {grad, div, lapl}, autotuned and captured in a hipGraph:
+    replay time against the same items launched one by one."""
+    import synthetic as sy
+    rng = np.random.default_rng(64)
+    meshes = {N: P.Mesh(N) for N in (80, 160, 320)}
+    lonlat = {N: P.mesh_desc_octahedral(N) for N in meshes}
+    fields = {}
+    items, edges_levels = [], 0
+    for i in range(64):
+        N = int(rng.choice([80, 160, 320]))
+        nlev = int(rng.choice([1, 10, 91, 137]))
+        op = ["grad", "div", "lapl"][int(rng.integers(0, 3))]
+        gm = meshes[N]
+        if N not in fields:
+            co = sy.random_coeffs(16, [sy.seed_rng(4, N, j) for j in range(4)])
+            d = lonlat[N]
+            fields[N] = (torch.from_numpy(sy.synthesize(d["lon"], d["lat"], co)).to(dev),
+                         torch.from_numpy(sy.synthesize_gradient(d["lon"], d["lat"], co)).to(dev))
+        H, G = fields[N]
+        k = torch.arange(nlev, device=dev, dtype=torch.float64)
+        fac = 1.0 + k / 137.0
+        if op == "div":
+            x = (G[(k.long() % 4)].permute(1, 0, 2) * fac[None, :, None]).float().contiguous()
+            out = torch.empty(gm.nnodes, nlev, dtype=torch.float32, device=dev)
+            code = P.ATLAS_OP_DIVERGENCE
+        else:
+            x = (H[(k.long() % 4)].t() * fac[None, :]).float().contiguous()
+            shape = (gm.nnodes, nlev, 2) if op == "grad" else (gm.nnodes, nlev)
+            out = torch.empty(shape, dtype=torch.float32, device=dev)
+            code = P.ATLAS_OP_GRADIENT if op == "grad" else P.ATLAS_OP_LAPLACIAN
+        items.append((gm, code, x, out))
+        edges_levels += gm.nedges * nlev * (2 if op == "lapl" else 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = P.Batch(items, use_graph=True, autotune=True)
+    build_s = time.perf_counter() - t0
+    ms_batch = time_op(lambda: b.launch(), 20, 3, torch)
+    solo = [it[3].clone() for it in items]
+    ms_seq = time_op(lambda: [gm.apply(c, x, out=o) for gm, c, x, o in items], 20, 3, torch)
+    same = all(torch.equal(a, it[3]) for a, it in zip(solo, items))
+    info = b.info
+    b.close()
+    return {"items": 64, "dtype": "f32", "graph": bool(info.graph), "units": info.nunits,
+            "grid_blocks": info.grid_blocks, "form_column": info.form_column,
+            "form_flat": info.form_flat, "build_s_incl_autotune": round(build_s, 2),
+            "ms_batch": round(ms_batch, 4), "ms_one_by_one": round(ms_seq, 4),
+            "speedup": round(ms_seq / ms_batch, 3),
+            "edge_level_per_s": edges_levels / (ms_batch * 1e-3),
+            "bitwise_equal_to_solo": bool(same)}
+
+
+def serve_bench(P, torch, np, dev, gm1280, nreq, qps):
+    """Poisson arrivals of seeded requests over {O48,O160,O320,O640,O1280} x
+    nlev {1,37,137} x {grad,div,curl,lapl} x {FP32,FP64}: the server
+    (admission by HBM budget, continuous batching over 4 streams) against the
+    same arrival schedule served by sequential plain FP64 calls."""
+    import threading
+    grids = (48, 160, 320, 640, 1280)
+    meshes = {N: (gm1280 if N == 1280 else P.Mesh(N)) for N in grids}
+    rng = np.random.default_rng(2000)
+    reqs = []
+    for _ in range(nreq):
+        reqs.append((int(rng.choice(grids)), int(rng.choice([1, 37, 137])),
+                     ["grad", "div", "curl", "lapl"][int(rng.integers(0, 4))],
+                     "f32" if rng.integers(0, 2) else "f64"))
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=nreq))
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    inputs = {}
+
+    def field(N, nlev, vec, dt):
+        key = (N, nlev, vec, dt)
+        if key not in inputs:
+            shape = (meshes[N].nnodes, nlev, 2) if vec else (meshes[N].nnodes, nlev)
+            inputs[key] = torch.randn(shape, generator=g, device=dev,
+                                      dtype=torch.float64 if dt == "f64" else torch.float32)
+        return inputs[key]
+
+    code = {"grad": P.ATLAS_OP_GRADIENT, "div": P.ATLAS_OP_DIVERGENCE,
+            "curl": P.ATLAS_OP_CURL, "lapl": P.ATLAS_OP_LAPLACIAN}
+    for N, nlev, op, dt in reqs:
+        field(N, nlev, op in ("div", "curl"), dt)
+        field(N, nlev, op in ("div", "curl"), "f64")
+    work = sum(meshes[N].nedges * nlev * (2 if op == "lapl" else 1) for N, nlev, op, _ in reqs)
+    torch.cuda.synchronize()
+
+    def pct(lat):
+        lat = np.sort(np.asarray(lat))
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    # sequential plain FP64: one request at a time, in arrival order
+    outs = {}
+    for N, nlev, op, _ in reqs:
+        shape = (meshes[N].nnodes, nlev, 2) if op == "grad" else (meshes[N].nnodes, nlev)
+        outs.setdefault((N, nlev, op), torch.empty(shape, dtype=torch.float64, device=dev))
+    for N, nlev, op, _ in reqs[:20]:  # warm-up
+        meshes[N].apply(code[op], field(N, nlev, op in ("div", "curl"), "f64"),
+                        out=outs[(N, nlev, op)])
+    torch.cuda.synchronize()
+    lat_seq = []
+    t0 = time.perf_counter()
+    for (N, nlev, op, _), ta in zip(reqs, arrivals):
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        meshes[N].apply(code[op], field(N, nlev, op in ("div", "curl"), "f64"),
+                        out=outs[(N, nlev, op)])
+        torch.cuda.synchronize()
+        lat_seq.append((time.perf_counter() - t0 - ta) * 1e6)
+    span_seq = time.perf_counter() - t0
+    del outs
+    torch.cuda.empty_cache()
+
+    # the server: FP32 and FP64 requests as drawn
+    budget = 64 << 30
+    srv = P.Server(hbm_budget_bytes=budget, nstreams=4, max_batch=64)
+    ids = {N: srv.register_mesh(meshes[N]) for N in grids}
+    tickets = [None] * nreq
+    lat_srv, batch_sizes, status = [0.0] * nreq, [0] * nreq, [0] * nreq
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(nreq):
+            ready.acquire()
+            r = srv.wait(tickets[i])
+            lat_srv[i], batch_sizes[i], status[i] = r["total_us"], r["batch_size"], r["status"]
+            srv.release(tickets[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i, ((N, nlev, op, dt), ta) in enumerate(zip(reqs, arrivals)):
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        tickets[i] = srv.submit(ids[N], code[op], field(N, nlev, op in ("div", "curl"), dt))
+        ready.release()
+    th.join()
+    span_srv = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    p50s, p99s = pct(lat_seq)
+    p50v, p99v = pct(lat_srv)
+    return {
+        "requests": nreq, "qps_offered": qps,
+        "mix": "grids O48/O160/O320/O640/O1280, nlev 1/37/137, grad/div/curl/lapl, f32/f64",
+        "server": {"p50_us": round(p50v, 1), "p99_us": round(p99v, 1),
+                   "req_per_s": round(nreq / span_srv, 1), "edge_level_per_s": work / span_srv,
+                   "launches": st["launches"], "batched_launches": st["batched_launches"],
+                   "mean_batch": round(float(np.mean(batch_sizes)), 2),
+                   "failed": int(sum(1 for x in status if x != 0)),
+                   "peak_inflight_GB": round(st["peak_inflight_bytes"] / 1e9, 2),
+                   "hbm_budget_GB": round(budget / 1e9, 2)},
+        "sequential_f64": {"p50_us": round(p50s, 1), "p99_us": round(p99s, 1),
+                           "req_per_s": round(nreq / span_seq, 1),
+                           "edge_level_per_s": work / span_seq},
     }
 
 
@@ -197,9 +392,29 @@ def main():
         traffic = rec["fetch_bytes"] + rec["write_bytes"]
 
     cpu = None
+    om = None
     if not args.no_cpu_baseline:
         f_host = f64[:, :args.cpu_levels].cpu().numpy()
-        cpu = cpu_baseline(N, nlev, args.cpu_levels, np.ascontiguousarray(f_host))
+        cpu, om = cpu_baseline(N, nlev, args.cpu_levels, np.ascontiguousarray(f_host))
+        print(f"# cpu baseline done: {cpu['sample']}", file=sys.stderr, flush=True)
+    acc = None
+    if not args.no_accuracy:
+        if om is None:
+            import oracle
+            om = oracle.Mesh(N)
+        acc = accuracy(gm, om, f64, uv64, torch, np)
+        print("# accuracy done", file=sys.stderr, flush=True)
+    del om
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench(P, torch, np, dev)
+        print("# batch done", file=sys.stderr, flush=True)
+    serving = None
+    if not args.no_serve:
+        del f64, uv64
+        torch.cuda.empty_cache()
+        serving = serve_bench(P, torch, np, dev, gm, args.serve_requests, args.serve_qps)
+        print("# serving done", file=sys.stderr, flush=True)
 
     line = {
         "metric": "edge*level updates/s (gradient, O1280 L137) + % HBM peak",
@@ -224,6 +439,9 @@ def main():
                      "algorithmic_bytes": alg_bytes("grad", 8)},
         "cpu_baseline": cpu,
         "ops": ops,
+        "accuracy_vs_oracle": acc,
+        "batch": batch,
+        "serving": serving,
         "kernel_source_sha": sha,
     }
     print(json.dumps(line), flush=True)

@@ -229,6 +229,14 @@ typedef struct {
                                per wavefront per step, so the set of columns
                                in flight stays small enough for the L2;
                                0 = one workgroup per tile                   */
+  int32_t level_vec;        /* column: most levels per lane (1, 2 or 4), a
+                               lane moving its levels in one access of at
+                               most 16 bytes (each pass takes the largest
+                               width that fits its element: FP64 scalar 2,
+                               FP32 scalar 4, FP32 vector 2, FP64 vector 1);
+                               0 = as wide as fits.  Falls back to 1 for
+                               meshes of degree > 6, columns shorter than
+                               the width or longer than 256 lane vectors. */
 } atlas_launch;
 
 /* Apply `op` with an explicit launch shape (tests, autotuner).  For

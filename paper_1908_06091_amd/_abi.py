@@ -56,7 +56,7 @@ class Layout(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("nodes_per_block", ctypes.c_int32), ("level_chunk", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("level_vec", ctypes.c_int32)]
 
 
 class WorkItem(ctypes.Structure):

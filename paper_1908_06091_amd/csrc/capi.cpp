@@ -109,6 +109,8 @@ atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
     return fail(ATLAS_EINVAL, "level_chunk must be in [0, 64]");
   if (sh.blocks_per_cu < 0 || sh.blocks_per_cu > 32)
     return fail(ATLAS_EINVAL, "blocks_per_cu must be in [0, 32]");
+  if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
+    return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
   size_t need = 0;
   if (op == ATLAS_OP_LAPLACIAN) need += lapl_ws_bytes(m, nlev, dt);
   if (sh.variant == ATLAS_VARIANT_FLUX) need += flux_ws_bytes(m, op, nlev, dt);
@@ -305,6 +307,7 @@ LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, i
     s.nodes_per_block = l->nodes_per_block;
     s.level_chunk = l->level_chunk;
     s.blocks_per_cu = l->blocks_per_cu;
+    s.level_vec = l->level_vec;
   }
   return s;
 }

@@ -99,6 +99,7 @@ struct LaunchShape {
   int nodes_per_block = 0;  // 0 = the mesh's tiles
   int level_chunk = 0;      // column form: levels per unit, 0 = all
   int blocks_per_cu = 0;    // > 0: persistent wave-cyclic grid
+  int level_vec = 0;        // column form: levels per lane, 0 = auto
 };
 
 // ------------------------------------------------------------- batches

@@ -152,6 +152,10 @@ template <> struct Pol<double, OP_GRAD> {
                                                double be, double, double, double) {
     st_out2(out + 2 * idx, al * s.gl, be * s.gt);
   }
+  static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
+    s.gl = use ? t.gl : s.gl;
+    s.gt = use ? t.gt : s.gt;
+  }
 };
 
 // FP64 divergence / curl: sum of sS_lon a_e +- sS_lat b_e with edge
@@ -177,6 +181,9 @@ template <int OP> struct PolDC64 {
                                                double, double, double, double) {
     st_out(out + idx, al * s.acc);
   }
+  static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
+    s.acc = use ? t.acc : s.acc;
+  }
 };
 template <> struct Pol<double, OP_DIV> : PolDC64<OP_DIV> {};
 template <> struct Pol<double, OP_CURL> : PolDC64<OP_CURL> {};
@@ -200,6 +207,12 @@ template <> struct Pol<float, OP_GRAD> {
     st_out2(out + 2 * idx, (float)(al * (s.kx.value() + cx * (double)s.xi)),
             (float)(be * (s.ky.value() + cy * (double)s.xi)));
   }
+  static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
+    s.kx.s = use ? t.kx.s : s.kx.s;
+    s.kx.c = use ? t.kx.c : s.kx.c;
+    s.ky.s = use ? t.ky.s : s.ky.s;
+    s.ky.c = use ? t.ky.c : s.ky.c;
+  }
 };
 
 template <int OP> struct PolDC32 {
@@ -219,6 +232,10 @@ template <int OP> struct PolDC32 {
     const double b_i = ((OP == OP_DIV) ? (double)s.ui.y : (double)s.ui.x) * s.ci;
     const double closure = (OP == OP_DIV) ? cx * a_i + cy * b_i : cx * a_i - cy * b_i;
     st_out(out + idx, (float)(al * (s.ka.value() + closure)));
+  }
+  static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
+    s.ka.s = use ? t.ka.s : s.ka.s;
+    s.ka.c = use ? t.ka.c : s.ka.c;
   }
 };
 template <> struct Pol<float, OP_DIV> : PolDC32<OP_DIV> {};
@@ -413,6 +430,167 @@ __global__ void __launch_bounds__(512) k_column(DevMesh m, const T *__restrict__
     column_pos<T, OP, NCH, G>(m, in, out, nlev, p, cur, lane);
     cur = nxt;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Level-vector column form: as the column form, but every lane owns NV
+// consecutive levels of the column and moves them with one 16-byte access
+// (FP64 scalar columns: 2 levels per lane; FP32 scalar: 4; FP32 vector: 2).
+// A wavefront load instruction then carries 1 KiB instead of 256-512 B, so a
+// node needs 2-3x fewer vector memory instructions -- the address path, not
+// the bytes, is what limits the one-level-per-lane form.  Column starts are
+// only element-aligned (a column of 137 FP64 levels is 1096 B), so these are
+// unaligned 16-byte accesses.  A lane's first level is clamped to
+// nlev - NV: every access stays inside the column, and the lanes at the end
+// recompute and store levels that a neighbouring lane also owns -- the same
+// operation sequence, so the same bits are written twice.
+// ---------------------------------------------------------------------------
+template <class V, int NV> struct LaneVec;
+template <> struct LaneVec<double, 2> {
+  typedef double raw __attribute__((ext_vector_type(2), aligned(8)));
+  static __device__ __forceinline__ double get(const raw &r, int v) { return r[v]; }
+};
+template <> struct LaneVec<float, 2> {
+  typedef float raw __attribute__((ext_vector_type(2), aligned(4)));
+  static __device__ __forceinline__ float get(const raw &r, int v) { return r[v]; }
+};
+template <> struct LaneVec<float, 4> {
+  typedef float raw __attribute__((ext_vector_type(4), aligned(4)));
+  static __device__ __forceinline__ float get(const raw &r, int v) { return r[v]; }
+};
+template <> struct LaneVec<v2f, 2> {
+  typedef float raw __attribute__((ext_vector_type(4), aligned(8)));
+  static __device__ __forceinline__ v2f get(const raw &r, int v) { return v2f{r[2 * v], r[2 * v + 1]}; }
+};
+
+// NV levels per lane are possible for this element type (one access of at
+// most 16 bytes).
+template <class T, int OP, int NV>
+constexpr bool lane_vec_ok() {
+  return NV > 1 && NV * sizeof(typename Pol<T, OP>::V) <= 16;
+}
+
+// One node (rows of at most 6 incidences, one load group), NCH chunks of
+// 64 lanes x NV levels.
+template <class T, int OP, int NV, int NCH>
+__device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict__ in,
+                                          T *__restrict__ out, int nlev, const PosRec &pr,
+                                          int lane) {
+  using P = Pol<T, OP>;
+  using V = typename P::V;
+  using LV = LaneVec<V, NV>;
+  using R = typename LV::raw;
+  const V *vin = reinterpret_cast<const V *>(in);
+  const size_t L = (size_t)nlev;
+  const int node = pr.node, r0 = pr.r0, n = pr.r1 - pr.r0;
+  int s[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) s[c] = min(NV * (lane + 64 * c), nlev - NV);
+  const double ci = P::kVecIn ? m.coslat[node] : 0.0;
+  typename P::St st[NCH][NV];
+  {
+    R xi[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) xi[c] = *reinterpret_cast<const R *>(vin + (size_t)node * L + s[c]);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) P::init(st[c][v], LV::get(xi[c], v), ci);
+  }
+  constexpr int G = 6;
+  uint32_t nb[G];
+  double2 S[G];
+  double cn[G];
+  R xn[G][NCH];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    nb[j] = (uint32_t)m.nbr[r0 + j];
+    S[j] = m.S[r0 + j];
+    cn[j] = P::kVecIn ? m.ncos[r0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const size_t q = nb[j] & ~kPoleBit;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) xn[j][c] = *reinterpret_cast<const R *>(vin + q * L + s[c]);
+  }
+  // Every incidence of the group is accumulated into a candidate state and
+  // kept by a select (not a branch): the loads above then have unconditional
+  // uses and stay one burst, instead of being moved into a branch per
+  // incidence and waited for one at a time.  Padding entries (j >= n) and
+  // pole edges of div/curl leave the state as it was.
+  double cx = 0.0, cy = 0.0;
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const bool pole = (nb[j] & kPoleBit) != 0;
+    const bool use = j < n && !(P::kVecIn && pole);
+    double tx = cx, ty = cy;
+    closure_add<P::kOp>(tx, ty, S[j], pole);
+    cx = use ? tx : cx;
+    cy = use ? ty : cy;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        typename P::St t = st[c][v];
+        P::add(t, LV::get(xn[j][c], v), S[j], pole, cn[j]);
+        P::keep(st[c][v], t, use);
+      }
+  }
+  const double al = pr.alpha, be = P::kVecOut ? pr.beta : 0.0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      P::store(out, (size_t)node * L + s[c] + v, st[c][v], al, be, cx, cy, ci);
+}
+
+// Same schedules as k_column (tiled, or persistent wave-cyclic).  The
+// occupancy hint lets the register allocator keep a node's whole load burst
+// in flight (at the default target it delays part of the burst to save
+// registers, and each delayed load is then waited for on its own).
+template <int NCH> constexpr int colv_waves() { return NCH <= 2 ? 4 : 2; }
+
+template <class T, int OP, int NV, int NCH>
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(colv_waves<NCH>(), colv_waves<NCH>())))
+    k_colv(DevMesh m, const T *__restrict__ in,
+                                               T *__restrict__ out, int nlev, int npb,
+                                               int per_xcd, int cyc) {
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int p, p1, stride;
+  if (cyc > 0) {
+    const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+    const int lo = (int)((int64_t)m.V * x / 8);
+    p1 = (int)((int64_t)m.V * (x + 1) / 8);
+    p = lo + i * nw + wave;
+    stride = cyc * nw;
+  } else {
+    int p0;
+    if (!tile_range(m, xcd_tile(blockIdx.x, per_xcd), npb, p0, p1)) return;
+    p = p0 + wave;
+    stride = nw;
+  }
+  if (p >= p1) return;
+  PosRec cur = m.pos[p];
+  for (; p < p1; p += stride) {
+    const PosRec nxt = m.pos[min(p + stride, p1 - 1)];  // prefetch
+    colv_node<T, OP, NV, NCH>(m, in, out, nlev, cur, lane);
+    cur = nxt;
+  }
+}
+
+// Levels per lane of the level-vector form for (T, OP, nlev): 16 bytes per
+// lane when the column is long enough and the mesh has degree <= 6; 1 means
+// the one-level-per-lane form.
+template <class T, int OP>
+__host__ __device__ inline int auto_level_vec(int nlev, int maxdeg) {
+  const int nv = (int)(16 / sizeof(typename Pol<T, OP>::V));
+  if (nv < 2 || maxdeg > 6 || nlev < nv) return 1;
+  if ((nlev + 64 * nv - 1) / (64 * nv) > 4) return 1;
+  return nv;
 }
 
 // ---------------------------------------------------------------------------
@@ -710,7 +888,22 @@ __device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, const 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (form == FORM_COLUMN) {
+    const int nv = auto_level_vec<T, OP>(nlev, m.maxdeg);
     const int nch = (nlev + 63) / 64;
+    if (nv > 1) {
+      constexpr int NV = (int)(16 / sizeof(typename Pol<T, OP>::V));
+      const int nchv = (nlev + 64 * NV - 1) / (64 * NV);
+      if constexpr (lane_vec_ok<T, OP, NV>()) {
+        for (int p = p0 + wave; p < p1; p += nw) {
+          const PosRec pr = m.pos[p];
+          if (nchv == 1) colv_node<T, OP, NV, 1>(m, in, out, nlev, pr, lane);
+          else if (nchv == 2) colv_node<T, OP, NV, 2>(m, in, out, nlev, pr, lane);
+          else if (nchv == 3) colv_node<T, OP, NV, 3>(m, in, out, nlev, pr, lane);
+          else colv_node<T, OP, NV, 4>(m, in, out, nlev, pr, lane);
+        }
+        return;
+      }
+    }
     for (int p = p0 + wave; p < p1; p += nw) {
       const PosRec pr = m.pos[p];
       if (m.maxdeg <= 6 && nch == 1) column_node<T, OP, 1, 6, true>(m, in, out, nlev, pr, lane);
@@ -916,6 +1109,33 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       // persistent grid: blocks_per_cu workgroups on every compute unit
       const int cyc = sh.blocks_per_cu > 0 ? sh.blocks_per_cu * device_cu_count() / 8 : 0;
       const dim3 cgrid = cyc > 0 ? dim3(8 * cyc) : grid;
+      int nv = sh.level_vec;
+      if (nv == 0) nv = auto_level_vec<T, OP>(nlev, m.maxdeg);
+      if (nv != 1 && nv != 2 && nv != 4)
+        return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
+      nv = min(nv, (int)(16 / sizeof(typename Pol<T, OP>::V)));  // <= 16 bytes per lane
+      const int nchv = (nlev + 64 * nv - 1) / (64 * nv);
+      if (nv > 1 && (nlev < nv || m.maxdeg > 6 || nchv > 4)) nv = 1;  // same results
+      if (nv > 1) {
+        void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
+#define ATLASX_COLV(NV)                                                     \
+  if constexpr (lane_vec_ok<T, OP, NV>()) {                                 \
+    if (nchv == 1) kern = k_colv<T, OP, NV, 1>;                             \
+    else if (nchv == 2) kern = k_colv<T, OP, NV, 2>;                        \
+    else if (nchv == 3) kern = k_colv<T, OP, NV, 3>;                        \
+    else kern = k_colv<T, OP, NV, 4>;                                       \
+  }
+        if (nv == 2) {
+          ATLASX_COLV(2)
+        } else {
+          ATLASX_COLV(4)
+        }
+#undef ATLASX_COLV
+        if (!kern) return fail(ATLAS_EINVAL, "level_vec not available for this dtype and operator");
+        hipLaunchKernelGGL(kern, cgrid, block, 0, st, m, in, out, nlev, sh.nodes_per_block,
+                           per_xcd, cyc);
+        break;
+      }
 #define ATLASX_COL(N)                                                                  \
   do {                                                                                 \
     if (m.maxdeg <= 6)                                                                 \

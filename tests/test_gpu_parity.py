@@ -101,9 +101,15 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
     for block in (64, 256):
         for bpc in (1, 3, 8):
             shapes.append(P.Launch(P.VARIANT_COLUMN, block, 0, 0, bpc))
+    # levels per lane: one, or lane vectors of 2 / 4 levels (capped at 16 B)
+    for lv in (1, 2, 4):
+        shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 0, lv))
+        shapes.append(P.Launch(P.VARIANT_COLUMN, 64, 7, 0, 0, lv))
+        shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 3, lv))
     for sh in shapes:
         got = _run(P, gm, op, x, launch=sh)
-        assert torch.equal(got, base), (sh.variant, sh.block_threads, sh.nodes_per_block)
+        assert torch.equal(got, base), (sh.variant, sh.block_threads, sh.nodes_per_block,
+                                        sh.level_vec)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -183,6 +189,9 @@ def test_invalid_arguments_enqueue_nothing(P):
     # unknown dtype
     assert L.atlas_nabla_gradient(gm.handle, ctypes.c_void_p(x.data_ptr()), 3, 7,
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s)) == -1
+    # levels per lane other than 0, 1, 2, 4
+    with pytest.raises(P.AtlasError):
+        gm.apply(P.ATLAS_OP_GRADIENT, x, out=out, launch=P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 0, 3))
     torch.cuda.synchronize()
     assert torch.all(out == 7.0), "a rejected call must not write anything"
     with pytest.raises(ValueError):
