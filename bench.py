@@ -49,7 +49,8 @@ def parse_args():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-qps", type=float, default=400.0)
+    ap.add_argument("--serve-load", type=str, default="0.5,0.9,1.5",
+                    help="offered rates as multiples of the sequential FP64 service rate")
     return ap.parse_args()
 
 
@@ -206,20 +207,41 @@ def batch_bench(P, torch, np, dev):
     same = all(torch.equal(a, it[3]) for a, it in zip(solo, items))
     info = b.info
     b.close()
+    # each item against the FP64 oracle on its (FP32) inputs, sampled nodes
+    import oracle
+    oms = {N: oracle.Mesh(N) for N in meshes}
+    worst = 0.0
+    for gm, c, x, out in items:
+        N = next(k for k, v in meshes.items() if v is gm)
+        om = oms[N]
+        nodes = np.sort(rng.choice(om.V, size=min(256, om.V), replace=False)).astype(np.int64)
+        xh = x.double().cpu().numpy()
+        nlev = x.shape[1]
+        fn = {P.ATLAS_OP_GRADIENT: om.gradient_at, P.ATLAS_OP_DIVERGENCE: om.divergence_at,
+              P.ATLAS_OP_LAPLACIAN: om.laplacian_at}[c]
+        ref = fn(xh, nlev, nodes)
+        got = out.double().cpu().numpy()[nodes]
+        comps = [(got[..., k], ref[..., k]) for k in range(2)] if ref.ndim == 3 else [(got, ref)]
+        for g_, r_ in comps:
+            worst = max(worst, float(np.abs(g_ - r_).max() / np.abs(r_).max()))
     return {"items": 64, "dtype": "f32", "graph": bool(info.graph), "units": info.nunits,
             "grid_blocks": info.grid_blocks, "form_column": info.form_column,
             "form_flat": info.form_flat, "build_s_incl_autotune": round(build_s, 2),
             "ms_batch": round(ms_batch, 4), "ms_one_by_one": round(ms_seq, 4),
             "speedup": round(ms_seq / ms_batch, 3),
             "edge_level_per_s": edges_levels / (ms_batch * 1e-3),
-            "bitwise_equal_to_solo": bool(same)}
+            "bitwise_equal_to_solo": bool(same),
+            "max_rel_error_vs_oracle": worst,
+            "oracle_sample": "256 random nodes per item, all levels"}
 
 
-def serve_bench(P, torch, np, dev, gm1280, nreq, qps):
+def serve_bench(P, torch, np, dev, gm1280, nreq, qps_factors):
     """Poisson arrivals of seeded requests over {O48,O160,O320,O640,O1280} x
     nlev {1,37,137} x {grad,div,curl,lapl} x {FP32,FP64}: the server
     (admission by HBM budget, continuous batching over 4 streams) against the
-    same arrival schedule served by sequential plain FP64 calls."""
+    same arrival schedule served by sequential plain FP64 calls.  The offered
+    rates are multiples of the sequential FP64 service rate mu_seq, measured
+    first on the same request mix."""
     import threading
     grids = (48, 160, 320, 640, 1280)
     meshes = {N: (gm1280 if N == 1280 else P.Mesh(N)) for N in grids}
@@ -229,7 +251,7 @@ def serve_bench(P, torch, np, dev, gm1280, nreq, qps):
         reqs.append((int(rng.choice(grids)), int(rng.choice([1, 37, 137])),
                      ["grad", "div", "curl", "lapl"][int(rng.integers(0, 4))],
                      "f32" if rng.integers(0, 2) else "f64"))
-    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=nreq))
+    gaps = rng.exponential(1.0, size=nreq)  # unit-rate inter-arrival times
     g = torch.Generator(device=dev)
     g.manual_seed(5)
     inputs = {}
@@ -248,78 +270,97 @@ def serve_bench(P, torch, np, dev, gm1280, nreq, qps):
         field(N, nlev, op in ("div", "curl"), dt)
         field(N, nlev, op in ("div", "curl"), "f64")
     work = sum(meshes[N].nedges * nlev * (2 if op == "lapl" else 1) for N, nlev, op, _ in reqs)
-    torch.cuda.synchronize()
-
-    def pct(lat):
-        lat = np.sort(np.asarray(lat))
-        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
-
-    # sequential plain FP64: one request at a time, in arrival order
     outs = {}
     for N, nlev, op, _ in reqs:
         shape = (meshes[N].nnodes, nlev, 2) if op == "grad" else (meshes[N].nnodes, nlev)
         outs.setdefault((N, nlev, op), torch.empty(shape, dtype=torch.float64, device=dev))
-    for N, nlev, op, _ in reqs[:20]:  # warm-up
-        meshes[N].apply(code[op], field(N, nlev, op in ("div", "curl"), "f64"),
-                        out=outs[(N, nlev, op)])
     torch.cuda.synchronize()
-    lat_seq = []
-    t0 = time.perf_counter()
-    for (N, nlev, op, _), ta in zip(reqs, arrivals):
-        now = time.perf_counter() - t0
-        if now < ta:
-            time.sleep(ta - now)
+
+    def seq_call(i):
+        N, nlev, op, _ = reqs[i]
         meshes[N].apply(code[op], field(N, nlev, op in ("div", "curl"), "f64"),
                         out=outs[(N, nlev, op)])
         torch.cuda.synchronize()
-        lat_seq.append((time.perf_counter() - t0 - ta) * 1e6)
-    span_seq = time.perf_counter() - t0
-    del outs
-    torch.cuda.empty_cache()
 
-    # the server: FP32 and FP64 requests as drawn
-    budget = 64 << 30
-    srv = P.Server(hbm_budget_bytes=budget, nstreams=4, max_batch=64)
-    ids = {N: srv.register_mesh(meshes[N]) for N in grids}
-    tickets = [None] * nreq
-    lat_srv, batch_sizes, status = [0.0] * nreq, [0] * nreq, [0] * nreq
-    ready = threading.Semaphore(0)
-
-    def waiter():
-        for i in range(nreq):
-            ready.acquire()
-            r = srv.wait(tickets[i])
-            lat_srv[i], batch_sizes[i], status[i] = r["total_us"], r["batch_size"], r["status"]
-            srv.release(tickets[i])
-
-    th = threading.Thread(target=waiter)
-    th.start()
+    for i in range(20):  # warm-up
+        seq_call(i)
     t0 = time.perf_counter()
-    for i, ((N, nlev, op, dt), ta) in enumerate(zip(reqs, arrivals)):
-        now = time.perf_counter() - t0
-        if now < ta:
-            time.sleep(ta - now)
-        tickets[i] = srv.submit(ids[N], code[op], field(N, nlev, op in ("div", "curl"), dt))
-        ready.release()
-    th.join()
-    span_srv = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    p50s, p99s = pct(lat_seq)
-    p50v, p99v = pct(lat_srv)
+    for i in range(nreq):
+        seq_call(i)
+    mu_seq = nreq / (time.perf_counter() - t0)
+
+    def pct(lat):
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    def run_sequential(arrivals):
+        lat = []
+        t0 = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            seq_call(i)
+            lat.append((time.perf_counter() - t0 - ta) * 1e6)
+        return lat, time.perf_counter() - t0
+
+    budget = 64 << 30
+
+    def run_server(arrivals):
+        srv = P.Server(hbm_budget_bytes=budget, nstreams=4, max_batch=64)
+        ids = {N: srv.register_mesh(meshes[N]) for N in grids}
+        tickets = [None] * nreq
+        lat, sizes, status = [0.0] * nreq, [0] * nreq, [0] * nreq
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(nreq):
+                ready.acquire()
+                r = srv.wait(tickets[i])
+                lat[i], sizes[i], status[i] = r["total_us"], r["batch_size"], r["status"]
+                srv.release(tickets[i])
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i, ((N, nlev, op, dt), ta) in enumerate(zip(reqs, arrivals)):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            tickets[i] = srv.submit(ids[N], code[op], field(N, nlev, op in ("div", "curl"), dt))
+            ready.release()
+        th.join()
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, span, st, sizes, status
+
+    runs = []
+    for f in qps_factors:
+        qps = f * mu_seq
+        arrivals = np.cumsum(gaps / qps)
+        lat_seq, span_seq = run_sequential(arrivals)
+        lat_srv, span_srv, st, sizes, status = run_server(arrivals)
+        p50s, p99s = pct(lat_seq)
+        p50v, p99v = pct(lat_srv)
+        runs.append({
+            "qps_offered": round(qps, 1), "load_vs_mu_seq": f,
+            "server": {"p50_us": round(p50v, 1), "p99_us": round(p99v, 1),
+                       "req_per_s": round(nreq / span_srv, 1),
+                       "edge_level_per_s": work / span_srv,
+                       "launches": st["launches"], "batched_launches": st["batched_launches"],
+                       "mean_batch": round(float(np.mean(sizes)), 2),
+                       "failed": int(sum(1 for x in status if x != 0)),
+                       "peak_inflight_GB": round(st["peak_inflight_bytes"] / 1e9, 2)},
+            "sequential_f64": {"p50_us": round(p50s, 1), "p99_us": round(p99s, 1),
+                               "req_per_s": round(nreq / span_seq, 1),
+                               "edge_level_per_s": work / span_seq}})
+        print(f"# serving at {f} x mu_seq done", file=sys.stderr, flush=True)
     return {
-        "requests": nreq, "qps_offered": qps,
+        "requests": nreq,
         "mix": "grids O48/O160/O320/O640/O1280, nlev 1/37/137, grad/div/curl/lapl, f32/f64",
-        "server": {"p50_us": round(p50v, 1), "p99_us": round(p99v, 1),
-                   "req_per_s": round(nreq / span_srv, 1), "edge_level_per_s": work / span_srv,
-                   "launches": st["launches"], "batched_launches": st["batched_launches"],
-                   "mean_batch": round(float(np.mean(batch_sizes)), 2),
-                   "failed": int(sum(1 for x in status if x != 0)),
-                   "peak_inflight_GB": round(st["peak_inflight_bytes"] / 1e9, 2),
-                   "hbm_budget_GB": round(budget / 1e9, 2)},
-        "sequential_f64": {"p50_us": round(p50s, 1), "p99_us": round(p99s, 1),
-                           "req_per_s": round(nreq / span_seq, 1),
-                           "edge_level_per_s": work / span_seq},
+        "mu_seq_req_per_s": round(mu_seq, 1),
+        "hbm_budget_GB": round(budget / 1e9, 2), "streams": 4, "max_batch": 64,
+        "runs": runs,
     }
 
 
@@ -413,7 +454,8 @@ def main():
     if not args.no_serve:
         del f64, uv64
         torch.cuda.empty_cache()
-        serving = serve_bench(P, torch, np, dev, gm, args.serve_requests, args.serve_qps)
+        serving = serve_bench(P, torch, np, dev, gm, args.serve_requests,
+                              [float(v) for v in args.serve_load.split(",")])
         print("# serving done", file=sys.stderr, flush=True)
 
     line = {

@@ -91,13 +91,17 @@ typedef struct {
 /* Gaussian latitudes: the 2N roots of the Legendre polynomial P_{2N}(mu),   */
 /* in descending order (north to south).  Section 4.2.3.5.  Newton's method  */
 /* on the three-term recurrence, started from the classical asymptotic      */
-/* guess cos(pi (j + 3/4) / (n + 1/2)).                                      */
+/* guess cos(pi (j + 3/4) / (n + 1/2)), carried out in extended precision   */
+/* (x86 long double, 64-bit significand) and rounded to double once, so     */
+/* that each mu is the double nearest the true root.  A root found in       */
+/* double is only good to a few ulps, and near the poles an ulp of latitude  */
+/* is a relative change of ~2e-13 in cos(lat) and in the polar dual volumes. */
 /* ------------------------------------------------------------------------ */
-static void legendre_pair(int n, double x, double *p_n, double *p_nm1) {
-  double p0 = 1.0, p1 = x;
-  if (n == 0) { *p_n = 1.0; *p_nm1 = 0.0; return; }
+static void legendre_pair(int n, long double x, long double *p_n, long double *p_nm1) {
+  long double p0 = 1.0L, p1 = x;
+  if (n == 0) { *p_n = 1.0L; *p_nm1 = 0.0L; return; }
   for (int k = 2; k <= n; ++k) {
-    double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / (double)k;
+    long double pk = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / (long double)k;
     p0 = p1;
     p1 = pk;
   }
@@ -109,21 +113,21 @@ int orc_gauss_mu(int N, double *mu) {
   if (N < 1 || !mu) return -1;
   const int n = 2 * N;
   for (int j = 0; j < N; ++j) {
-    double x = cos(ORC_PI * (j + 0.75) / (n + 0.5));
+    long double x = cosl(3.14159265358979323846264338327950288L * (j + 0.75L) / (n + 0.5L));
     int converged = 0;
     for (int it = 0; it < 100; ++it) {
-      double p, pm1;
+      long double p, pm1;
       legendre_pair(n, x, &p, &pm1);
-      double dp = n * (x * p - pm1) / (x * x - 1.0); /* P_n'(x) */
-      double dx = p / dp;
+      long double dp = n * (x * p - pm1) / (x * x - 1.0L); /* P_n'(x) */
+      long double dx = p / dp;
       x -= dx;
-      if (fabs(dx) <= 1e-15) {
+      if (fabsl(dx) <= 1e-18L) {
         if (converged) break; /* one extra step after convergence */
         converged = 1;
       }
     }
-    mu[j] = x;          /* northern hemisphere: descending positive roots */
-    mu[n - 1 - j] = -x; /* southern mirror                                */
+    mu[j] = (double)x;          /* northern hemisphere: descending positive roots */
+    mu[n - 1 - j] = -(double)x; /* southern mirror                                */
   }
   return 0;
 }

@@ -75,3 +75,35 @@ def test_workload_sizes():
     N = 1280
     assert 4 * N * N + 36 * N == 6599680
     assert abs(3 * (4 * N * N + 36 * N) - 40 - 19.8e6) < 0.01e6
+
+
+def _mp_legendre_roots(n, count, dps=40):
+    """The `count` largest roots of P_n to `dps` digits (mpmath Newton on the
+    three-term recurrence from the asymptotic guess), each rounded to the
+    nearest double."""
+    import mpmath
+    mpmath.mp.dps = dps
+    out = []
+    for j in range(count):
+        x = mpmath.cos(mpmath.pi * (j + mpmath.mpf(3) / 4) / (n + mpmath.mpf(1) / 2))
+        for _ in range(60):
+            p0, p1 = mpmath.mpf(1), x
+            for k in range(2, n + 1):
+                p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+            dx = p1 / (n * (x * p1 - p0) / (x * x - 1))
+            x -= dx
+            if abs(dx) < mpmath.mpf(10) ** (-dps + 5):
+                break
+        out.append(float(x))  # mpf -> float rounds to nearest
+    return np.array(out)
+
+
+@pytest.mark.parametrize("N,count", [(1, 1), (2, 2), (16, 16), (48, 48), (1280, 8)])
+def test_gauss_mu_correctly_rounded(N, count):
+    """Each latitude is the double nearest the true Legendre root (Sec. 4.2.3.5):
+    compared bit for bit with 40-digit roots for whole small grids and for the
+    polar rings of O1280, where an ulp of latitude is a 2e-13 relative change
+    of cos(lat)."""
+    mu = oracle.gauss_mu(N)
+    ref = _mp_legendre_roots(2 * N, count)
+    np.testing.assert_array_equal(mu[:count], ref)
