@@ -141,6 +141,21 @@ class Mesh:
         except Exception:
             pass
 
+    def volume_integral(self, x, stream=None):
+        """sum_i V_i x[i][k] (scalar [V][nlev]) or sum_i V_i x[i][k][c]
+        (vector [V][nlev][2]) per level, as a float64 device tensor."""
+        torch = _torch()
+        if x.dim() == 3 and x.shape[2] == 2:
+            nlev, ncomp = self._nlev_vector(x), 2
+            out = torch.empty(nlev, 2, dtype=torch.float64, device=x.device)
+        else:
+            nlev, ncomp = self._nlev_scalar(x), 1
+            out = torch.empty(nlev, dtype=torch.float64, device=x.device)
+        _check(self._lib.atlas_diag_volume_integral(self._h, _dev_ptr(x, "x"), nlev, ncomp,
+                                                    _dtype_code(x), _dev_ptr(out, "out"),
+                                                    _stream(stream)))
+        return out
+
     # -- shape helpers ------------------------------------------------------
     def _nlev_scalar(self, t):
         if t.dim() == 1:
@@ -295,6 +310,32 @@ class Batch:
             pass
 
 
+def error_norms(got, ref, stream=None) -> dict:
+    """Error of `got` against `ref` computed on the device (atlas_diag.h):
+    per component (last axis of a [..][2] field, else one component) the
+    max |got - ref|, the RMS of got - ref, max |ref| and RMS of ref, and the
+    normwise ratios max_rel = max|d| / max|ref|, rms_rel = rms(d) / rms(ref)."""
+    torch = _torch()
+    if got.shape != ref.shape:
+        raise ValueError("got and ref must have the same shape")
+    ncomp = 2 if got.dim() == 3 and got.shape[-1] == 2 else 1
+    n = got.numel() // ncomp
+    out = torch.empty(4 * ncomp, dtype=torch.float64, device=got.device)
+    _check(lib().atlas_diag_error_norms(_dev_ptr(got, "got"), _dtype_code(got), _dev_ptr(ref, "ref"),
+                                        _dtype_code(ref), n, ncomp, _dev_ptr(out, "out"),
+                                        _stream(stream)))
+    v = out.cpu().numpy().reshape(ncomp, 4)
+    comps = []
+    for c in range(ncomp):
+        dmax, dss, rmax, rss = (float(t) for t in v[c])
+        comps.append({"max_abs": dmax, "rms": (dss / n) ** 0.5, "ref_max": rmax,
+                      "ref_rms": (rss / n) ** 0.5,
+                      "max_rel": dmax / rmax if rmax > 0 else dmax,
+                      "rms_rel": (dss / rss) ** 0.5 if rss > 0 else dss ** 0.5})
+    return {"components": comps, "max_rel": max(c["max_rel"] for c in comps),
+            "rms_rel": max(c["rms_rel"] for c in comps)}
+
+
 class Server:
     """Request server (atlas_serve.h): HBM-budget admission, resident meshes,
     continuous batching over `nstreams` HIP streams.  With simulate=True no
@@ -373,7 +414,7 @@ class Server:
             pass
 
 
-__all__ = ["Server", "Batch", "autotune", "Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
+__all__ = ["error_norms", "Server", "Batch", "autotune", "Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
            "ATLAS_F32", "ATLAS_F64", "ATLAS_OP_GRADIENT", "ATLAS_OP_DIVERGENCE",
            "ATLAS_OP_CURL", "ATLAS_OP_LAPLACIAN", "VARIANT_AUTO", "VARIANT_COLUMN",
            "VARIANT_FLAT", "VARIANT_FLUX", "VARIANT_SWEEP"]

@@ -148,6 +148,12 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_float)]),
     "atlas_flux_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int,
                                                      ctypes.c_int32, ctypes.c_int]),
+    "atlas_diag_volume_integral": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
+    "atlas_diag_error_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                              ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
     "atlas_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "atlas_serve_register_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,

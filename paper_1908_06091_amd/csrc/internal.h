@@ -88,6 +88,7 @@ struct DevMesh {
   const int32_t *lref = nullptr;     // [I]  ((dq + 1) << 16) | slot, plus
                                      //      kLrefPole for a pole edge
   const double *ncos = nullptr;      // [I]  cos(lat) of the incidence's neighbour
+  const double *vol = nullptr;       // [V]  dual volume V_i (by position; diagnostics)
 };
 
 // ------------------------------------------------------------- kernels

@@ -383,7 +383,8 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
     delete m;
     return st;
   }
-  // the two temporaries are only read by the derivation kernel
+  // the volumes stay (diagnostics); cos by position was only for the scales
+  m->d.vol = vol_d;
   (void)hipDeviceSynchronize();
   // bytes one operator pass reads from the mesh store (column/flat forms):
   // per position perm + rowp + alpha/beta; per incidence nbr + S;
