@@ -55,10 +55,14 @@ def parse_args():
 
 
 def kernel_source_sha():
+    """Identity of what sets the dominant kernel's memory traffic: the kernel
+    source and the default tile layout of the processing order."""
     h = hashlib.sha256()
-    for f in ("nabla_kernels.hip", "mesh_store.cpp"):
-        with open(os.path.join(ROOT, "paper_1908_06091_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1908_06091_amd", "csrc", "nabla_kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1908_06091_amd", "csrc", "internal.h")) as fh:
+        layout = "\n".join(l for l in fh.read().splitlines() if re.search(r"kDefault(Band|Width)", l))
+    h.update(layout.encode())
     return h.hexdigest()[:16]
 
 

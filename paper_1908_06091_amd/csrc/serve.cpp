@@ -10,6 +10,14 @@
 // batch kernel of batch.cpp).  Every launch form computes each output element
 // with the same operation sequence, so a result does not depend on what it
 // was launched with.
+//
+// Device memory for outputs and workspaces comes from a small caching
+// allocator: blocks are hipMalloc'ed once per size class and handed out
+// again only after the work that used them has completed (a workspace when
+// its request's event has fired, a server-owned output when the caller has
+// released it), so reuse needs no stream ordering.  Cached plus used bytes
+// stay within the HBM budget; cached blocks are freed only when a new size
+// would not fit otherwise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +25,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -88,7 +97,10 @@ struct Server {
   int grid_full[2] = {8, 8};  // persistent batch grid per dtype (F32, F64)
   std::vector<MeshEntry> meshes;
   std::vector<Slot> slots;
-  hipMemPool_t pool = nullptr;
+  // caching allocator (scheduler thread and release, under mu)
+  std::multimap<size_t, void *> cache;        // free blocks by size
+  std::map<void *, size_t> block_bytes;       // every block the server holds
+  size_t held_bytes = 0;                      // used + cached
 
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -107,32 +119,63 @@ struct Server {
   }
   void uncharge(size_t b) { st.inflight_bytes -= std::min(b, st.inflight_bytes); }
 
-  // Device allocation on a slot's stream; every cfg.fail_alloc_every-th call
+  static size_t size_class(size_t bytes) {
+    const size_t g = (size_t)2 << 20;  // 2 MiB granules
+    return (bytes + g - 1) / g * g;
+  }
+
+  // Device block of at least `bytes`; every cfg.fail_alloc_every-th call
   // fails on purpose (fault injection for the scheduler's error paths).
-  bool alloc(void **p, size_t bytes, hipStream_t s) {
+  bool alloc(void **p, size_t bytes) {
     ++alloc_count;
     if (cfg.fail_alloc_every > 0 && alloc_count % (uint64_t)cfg.fail_alloc_every == 0) return false;
     if (cfg.simulate) {
       *p = nullptr;
       return true;
     }
-    return hipMallocFromPoolAsync(p, bytes, pool, s) == hipSuccess;
+    const size_t want = size_class(bytes);
+    auto it = cache.lower_bound(want);
+    if (it != cache.end() && it->first <= want + want / 4) {  // close fit
+      *p = it->second;
+      cache.erase(it);
+      return true;
+    }
+    // make room within the budget by dropping cached blocks, largest first
+    while (held_bytes + want > cfg.hbm_budget_bytes && !cache.empty()) {
+      auto last = std::prev(cache.end());
+      (void)hipFree(last->second);
+      held_bytes -= last->first;
+      block_bytes.erase(last->second);
+      cache.erase(last);
+    }
+    void *q = nullptr;
+    if (hipMalloc(&q, want) != hipSuccess) return false;
+    block_bytes[q] = want;
+    held_bytes += want;
+    *p = q;
+    return true;
   }
-  void free_async(void *p, hipStream_t s) {
-    if (p && !cfg.simulate) (void)hipFreeAsync(p, s);
+  // Returns a block whose device work has completed to the cache.
+  void recycle(void *p) {
+    if (!p || cfg.simulate) return;
+    auto it = block_bytes.find(p);
+    if (it != block_bytes.end()) cache.insert({it->second, p});
   }
 
   // A request leaves the device: release what it holds except an output the
   // caller still has to read (released by atlas_serve_release).
+  // Called once the request's device work (if any) has completed.
   void finish(Req &q, int status, Clock::time_point now) {
     q.status = status;
     q.state = DONE;
     q.t_done = now;
+    recycle(q.ws);
+    q.ws = nullptr;
     size_t b = q.in_b + q.ws_b;
     if (!(q.own_out && status == ATLAS_OK)) {
       if (q.out_charged) b += q.out_b;
       q.out_charged = false;
-      if (q.own_out && q.r.out) free_async(q.r.out, slots[std::max(0, q.slot)].stream);
+      if (q.own_out && q.r.out) recycle(q.r.out);
       if (q.own_out) q.r.out = nullptr;
     }
     uncharge(b);
@@ -207,10 +250,10 @@ struct Server {
       Req &q = reqs.at(t);
       q.slot = si;
       bool ok = true;
-      if (!q.r.out && q.own_out) ok = alloc(&q.r.out, q.out_b, s.stream);
-      if (ok && q.ws_b) ok = alloc(&q.ws, q.ws_b, s.stream);
+      if (!q.r.out && q.own_out) ok = alloc(&q.r.out, q.out_b);
+      if (ok && q.ws_b) ok = alloc(&q.ws, q.ws_b);
       if (!ok) {
-        free_async(q.ws, s.stream);
+        recycle(q.ws);  // nothing was enqueued on it
         q.ws = nullptr;
         finish(q, ATLAS_ENOMEM, now);
         continue;
@@ -241,14 +284,12 @@ struct Server {
     } else {
       status = launch_batch_group(s, run);
     }
-    for (uint64_t t : run) {
-      Req &q = reqs.at(t);
-      free_async(q.ws, s.stream);  // stream-ordered after the kernels
-      q.ws = nullptr;
-    }
     if (status == ATLAS_OK && !cfg.simulate && hipEventRecord(s.done, s.stream) != hipSuccess)
       status = ATLAS_EDEVICE;
     if (status != ATLAS_OK) {
+      // part of the group's work may be enqueued: let it drain before the
+      // blocks go back to the cache
+      if (!cfg.simulate) (void)hipStreamSynchronize(s.stream);
       for (uint64_t t : run) finish(reqs.at(t), status, now);
       cv_done.notify_all();
       return;
@@ -368,18 +409,15 @@ atlas_status release_server(Server *sv) {
   for (Slot &s : sv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
   }
-  for (auto &kv : sv->reqs) {
-    Req &q = kv.second;
-    if (q.own_out && q.r.out && q.slot >= 0) sv->free_async(q.r.out, sv->slots[q.slot].stream);
-  }
+  for (auto &kv : sv->block_bytes) (void)hipFree(kv.first);  // used and cached blocks
+  sv->block_bytes.clear();
+  sv->cache.clear();
   for (Slot &s : sv->slots) {
-    if (s.stream) (void)hipStreamSynchronize(s.stream);
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.d_tab) (void)hipFree(s.d_tab);
     if (s.h_tab) (void)hipHostFree(s.h_tab);
   }
-  if (sv->pool) (void)hipMemPoolDestroy(sv->pool);
   for (MeshEntry &e : sv->meshes)
     if (e.mesh && e.mesh->store) e.mesh->store->serve_refs -= 1;
   delete sv;
@@ -409,19 +447,6 @@ atlas_status atlas_serve_create(const atlas_serve_config *cfg, atlas_server_t *o
       delete sv;
       return fail(ATLAS_EDEVICE, "hipGetDevice");
     }
-    hipMemPoolProps props;
-    std::memset(&props, 0, sizeof(props));
-    props.allocType = hipMemAllocationTypePinned;
-    props.handleTypes = hipMemHandleTypeNone;
-    props.location.type = hipMemLocationTypeDevice;
-    props.location.id = sv->device;
-    if (hipMemPoolCreate(&sv->pool, &props) != hipSuccess) {
-      sv->pool = nullptr;
-      release_server(sv);
-      return fail(ATLAS_EDEVICE, "hipMemPoolCreate");
-    }
-    uint64_t keep = UINT64_MAX;  // keep freed blocks for reuse
-    (void)hipMemPoolSetAttribute(sv->pool, hipMemPoolAttrReleaseThreshold, &keep);
     for (int d = 0; d < 2; ++d)
       sv->grid_full[d] = std::max(
           8, (device_cu_count() * batch_blocks_per_cu(d ? ATLAS_F64 : ATLAS_F32, Server::kBlock) +
@@ -595,7 +620,7 @@ atlas_status atlas_serve_release(atlas_server_t srv, uint64_t ticket) {
   if (it == sv.reqs.end()) return fail(ATLAS_EINVAL, "unknown ticket");
   Req &q = it->second;
   if (q.state != DONE) return fail(ATLAS_ESTATE, "request not finished");
-  if (q.own_out && q.r.out && q.slot >= 0) sv.free_async(q.r.out, sv.slots[q.slot].stream);
+  if (q.own_out && q.r.out) sv.recycle(q.r.out);  // the caller has finished reading it
   if (q.out_charged) sv.uncharge(q.out_b);
   sv.reqs.erase(it);
   sv.cv_sched.notify_one();  // budget freed
