@@ -229,14 +229,16 @@ typedef struct {
                                per wavefront per step, so the set of columns
                                in flight stays small enough for the L2;
                                0 = one workgroup per tile                   */
-  int32_t level_vec;        /* column: most levels per lane (1, 2 or 4), a
-                               lane moving its levels in one access of at
-                               most 16 bytes (each pass takes the largest
-                               width that fits its element: FP64 scalar 2,
-                               FP32 scalar 4, FP32 vector 2, FP64 vector 1);
-                               0 = as wide as fits.  Falls back to 1 for
-                               meshes of degree > 6, columns shorter than
-                               the width or longer than 256 lane vectors. */
+  int32_t level_vec;        /* column: levels per lane.  0 = the level-vector
+                               kernel at its widest (each lane moves 16
+                               bytes: FP64 scalar 2 levels, FP32 scalar 4,
+                               FP32 vector 2, FP64 vector 1; lanes past the
+                               column make no memory access); 2 or 4 = that
+                               kernel with at most that many levels; 1 = the
+                               one-level-per-lane kernel.  The level-vector
+                               kernel needs a mesh of degree <= 6 and a
+                               column of 1..256 lane vectors; otherwise the
+                               one-level-per-lane kernel runs.            */
 } atlas_launch;
 
 /* Apply `op` with an explicit launch shape (tests, autotuner).  For

@@ -148,9 +148,15 @@ template <> struct Pol<double, OP_GRAD> {
     if (!pole) s.gl = s.gl + S.x * xe;
     s.gt = s.gt + S.y * xe;
   }
+  using Out = v2d;
+  static __device__ __forceinline__ Out result(const St &s, double al, double be, double, double,
+                                               double) {
+    return Out{al * s.gl, be * s.gt};
+  }
   static __device__ __forceinline__ void store(double *out, size_t idx, const St &s, double al,
-                                               double be, double, double, double) {
-    st_out2(out + 2 * idx, al * s.gl, be * s.gt);
+                                               double be, double cx, double cy, double ci) {
+    const Out r = result(s, al, be, cx, cy, ci);
+    st_out2(out + 2 * idx, r.x, r.y);
   }
   static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
     s.gl = use ? t.gl : s.gl;
@@ -177,9 +183,14 @@ template <int OP> struct PolDC64 {
     const double f = (OP == OP_DIV) ? S.x * ae + S.y * be : S.x * ae - S.y * be;
     s.acc = s.acc + f;
   }
+  using Out = double;
+  static __device__ __forceinline__ Out result(const St &s, double al, double, double, double,
+                                               double) {
+    return al * s.acc;
+  }
   static __device__ __forceinline__ void store(double *out, size_t idx, const St &s, double al,
-                                               double, double, double, double) {
-    st_out(out + idx, al * s.acc);
+                                               double be, double cx, double cy, double ci) {
+    st_out(out + idx, result(s, al, be, cx, cy, ci));
   }
   static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
     s.acc = use ? t.acc : s.acc;
@@ -202,10 +213,16 @@ template <> struct Pol<float, OP_GRAD> {
     if (!pole) s.kx.add(tx);
     s.ky.add(ty);
   }
+  using Out = v2f;
+  static __device__ __forceinline__ Out result(const St &s, double al, double be, double cx,
+                                               double cy, double) {
+    return Out{(float)(al * (s.kx.value() + cx * (double)s.xi)),
+               (float)(be * (s.ky.value() + cy * (double)s.xi))};
+  }
   static __device__ __forceinline__ void store(float *out, size_t idx, const St &s, double al,
-                                               double be, double cx, double cy, double) {
-    st_out2(out + 2 * idx, (float)(al * (s.kx.value() + cx * (double)s.xi)),
-            (float)(be * (s.ky.value() + cy * (double)s.xi)));
+                                               double be, double cx, double cy, double ci) {
+    const Out r = result(s, al, be, cx, cy, ci);
+    st_out2(out + 2 * idx, r.x, r.y);
   }
   static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
     s.kx.s = use ? t.kx.s : s.kx.s;
@@ -226,12 +243,17 @@ template <int OP> struct PolDC32 {
     diff_terms_f32<OP>(S, 0.0f, 0.0f, s.ui, un, s.ci, cn, tx, ty, t);
     s.ka.add(t);
   }
-  static __device__ __forceinline__ void store(float *out, size_t idx, const St &s, double al,
-                                               double, double cx, double cy, double) {
+  using Out = float;
+  static __device__ __forceinline__ Out result(const St &s, double al, double, double cx,
+                                               double cy, double) {
     const double a_i = (OP == OP_DIV) ? (double)s.ui.x : (double)s.ui.y;
     const double b_i = ((OP == OP_DIV) ? (double)s.ui.y : (double)s.ui.x) * s.ci;
     const double closure = (OP == OP_DIV) ? cx * a_i + cy * b_i : cx * a_i - cy * b_i;
-    st_out(out + idx, (float)(al * (s.ka.value() + closure)));
+    return (float)(al * (s.ka.value() + closure));
+  }
+  static __device__ __forceinline__ void store(float *out, size_t idx, const St &s, double al,
+                                               double be, double cx, double cy, double ci) {
+    st_out(out + idx, result(s, al, be, cx, cy, ci));
   }
   static __device__ __forceinline__ void keep(St &s, const St &t, bool use) {
     s.ka.s = use ? t.ka.s : s.ka.s;
@@ -445,6 +467,86 @@ __global__ void __launch_bounds__(512) k_column(DevMesh m, const T *__restrict__
 // recompute and store levels that a neighbouring lane also owns -- the same
 // operation sequence, so the same bits are written twice.
 // ---------------------------------------------------------------------------
+// Buffer accesses.  A column (or a node's output run) is described by a
+// buffer resource whose range is exactly that column; a lane whose offset is
+// out of range makes no memory access at all (loads return 0, stores are
+// dropped).  Lanes past the last lane vector therefore cost no cache
+// traffic, unlike clamped duplicate accesses.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+__device__ i32x4 buf_load16(i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v4i32");
+__device__ i32x2 buf_load8(i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v2i32");
+__device__ void buf_store16(i32x4 v, i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v4i32");
+__device__ void buf_store8(i32x2 v, i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v2i32");
+__device__ void buf_store4(int v, i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.i32");
+
+constexpr int kBufOff = 0x7fffff00;  // an offset outside every range used here
+#ifndef ATLASX_CACHED_STORE
+constexpr int kStoreAux = 2;         // non-temporal (streamed past the caches)
+#else
+constexpr int kStoreAux = 0;
+#endif
+
+// Raw buffer resource (stride 0) over [base, base + bytes); wavefront-uniform.
+__device__ __forceinline__ i32x4 make_rsrc(const void *base, uint32_t bytes) {
+  const uint64_t a = (uint64_t)base;
+  i32x4 r;
+  r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  r.y = __builtin_amdgcn_readfirstlane((int)((uint32_t)(a >> 32) & 0xffffu));
+  r.z = __builtin_amdgcn_readfirstlane((int)bytes);
+  r.w = 0x00020000;
+  return r;
+}
+
+// Read-only mesh data seen through the constant address space: the compiler
+// may then serve wavefront-uniform reads with scalar loads even where the
+// kernel also writes through buffer stores (which it cannot prove disjoint
+// from a generic pointer).
+#define ATLASX_CST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const ATLASX_CST T *cst(const T *p) {
+  return (const ATLASX_CST T *)p;
+}
+
+// Structures read field by field through the constant address space.
+__device__ __forceinline__ double2 cst_double2(const double2 *p, size_t i) {
+  const ATLASX_CST double *d = cst(reinterpret_cast<const double *>(p));
+  double2 r;
+  r.x = d[2 * i];
+  r.y = d[2 * i + 1];
+  return r;
+}
+__device__ __forceinline__ PosRec cst_pos(const PosRec *p, size_t i) {
+  const ATLASX_CST PosRec *q = cst(p) + i;
+  PosRec r;
+  r.node = q->node;
+  r.r0 = q->r0;
+  r.r1 = q->r1;
+  r.selfslot = q->selfslot;
+  r.alpha = q->alpha;
+  r.beta = q->beta;
+  return r;
+}
+
+template <class R>
+__device__ __forceinline__ R buf_load(const i32x4 &rsrc, int voff) {
+  static_assert(sizeof(R) == 16 || sizeof(R) == 8, "lane vectors are 8 or 16 bytes");
+  R r;
+  if constexpr (sizeof(R) == 16) {
+    const i32x4 v = buf_load16(rsrc, voff, 0, 0);
+    __builtin_memcpy(&r, &v, 16);
+  } else {
+    const i32x2 v = buf_load8(rsrc, voff, 0, 0);
+    __builtin_memcpy(&r, &v, 8);
+  }
+  return r;
+}
+
 template <class V, int NV> struct LaneVec;
 template <> struct LaneVec<double, 2> {
   typedef double raw __attribute__((ext_vector_type(2), aligned(8)));
@@ -458,16 +560,22 @@ template <> struct LaneVec<float, 4> {
   typedef float raw __attribute__((ext_vector_type(4), aligned(4)));
   static __device__ __forceinline__ float get(const raw &r, int v) { return r[v]; }
 };
+template <> struct LaneVec<v2d, 1> {
+  typedef double raw __attribute__((ext_vector_type(2), aligned(16)));
+  static __device__ __forceinline__ v2d get(const raw &r, int) { return v2d{r[0], r[1]}; }
+};
 template <> struct LaneVec<v2f, 2> {
   typedef float raw __attribute__((ext_vector_type(4), aligned(8)));
   static __device__ __forceinline__ v2f get(const raw &r, int v) { return v2f{r[2 * v], r[2 * v + 1]}; }
 };
 
-// NV levels per lane are possible for this element type (one access of at
-// most 16 bytes).
+// The level-vector form exists for this element type and width: NV levels
+// make one access of at most 16 bytes (one level per lane only for the
+// 16-byte FP64 vector elements).
 template <class T, int OP, int NV>
 constexpr bool lane_vec_ok() {
-  return NV > 1 && NV * sizeof(typename Pol<T, OP>::V) <= 16;
+  return NV * sizeof(typename Pol<T, OP>::V) <= 16 &&
+         (NV > 1 || sizeof(typename Pol<T, OP>::V) == 16);
 }
 
 // One node (rows of at most 6 incidences, one load group), NCH chunks of
@@ -480,18 +588,28 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
   using V = typename P::V;
   using LV = LaneVec<V, NV>;
   using R = typename LV::raw;
+  using Out = typename P::Out;
   const V *vin = reinterpret_cast<const V *>(in);
   const size_t L = (size_t)nlev;
+  const uint32_t col_bytes = (uint32_t)(L * sizeof(V));
   const int node = pr.node, r0 = pr.r0, n = pr.r1 - pr.r0;
-  int s[NCH];
+  // lane vector c of this lane starts at level s[c]; the last vector is
+  // clamped inside the column, lanes past it get an out-of-range offset
+  const int nvec = (nlev + NV - 1) / NV;
+  int s[NCH], off[NCH];
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) s[c] = min(NV * (lane + 64 * c), nlev - NV);
-  const double ci = P::kVecIn ? m.coslat[node] : 0.0;
+  for (int c = 0; c < NCH; ++c) {
+    const int idx = lane + 64 * c;
+    s[c] = min(NV * idx, nlev - NV);
+    off[c] = idx < nvec ? s[c] * (int)sizeof(V) : kBufOff;
+  }
+  const double ci = P::kVecIn ? cst(m.coslat)[node] : 0.0;
   typename P::St st[NCH][NV];
   {
+    const i32x4 rs = make_rsrc(vin + (size_t)node * L, col_bytes);
     R xi[NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) xi[c] = *reinterpret_cast<const R *>(vin + (size_t)node * L + s[c]);
+    for (int c = 0; c < NCH; ++c) xi[c] = buf_load<R>(rs, off[c]);
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -504,15 +622,16 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
   R xn[G][NCH];
 #pragma unroll
   for (int j = 0; j < G; ++j) {
-    nb[j] = (uint32_t)m.nbr[r0 + j];
-    S[j] = m.S[r0 + j];
-    cn[j] = P::kVecIn ? m.ncos[r0 + j] : 0.0;
+    nb[j] = (uint32_t)cst(m.nbr)[r0 + j];
+    S[j] = cst_double2(m.S, r0 + j);
+    cn[j] = P::kVecIn ? cst(m.ncos)[r0 + j] : 0.0;
   }
 #pragma unroll
   for (int j = 0; j < G; ++j) {
     const size_t q = nb[j] & ~kPoleBit;
+    const i32x4 rs = make_rsrc(vin + q * L, col_bytes);
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) xn[j][c] = *reinterpret_cast<const R *>(vin + q * L + s[c]);
+    for (int c = 0; c < NCH; ++c) xn[j][c] = buf_load<R>(rs, off[c]);
   }
   // Every incidence of the group is accumulated into a candidate state and
   // kept by a select (not a branch): the loads above then have unconditional
@@ -537,12 +656,34 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
         P::keep(st[c][v], t, use);
       }
   }
+  // A lane's NV results are contiguous in the output run of the node:
+  // written in 16-byte pieces (8 / 4 bytes for a shorter run).
   const double al = pr.alpha, be = P::kVecOut ? pr.beta : 0.0;
+  const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
+                             (uint32_t)(L * sizeof(Out)));
+  constexpr int W = NV * (int)sizeof(Out) / 4;  // 32-bit words per lane vector
 #pragma unroll
-  for (int c = 0; c < NCH; ++c)
+  for (int c = 0; c < NCH; ++c) {
+    int w[W];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      P::store(out, (size_t)node * L + s[c] + v, st[c][v], al, be, cx, cy, ci);
+    for (int v = 0; v < NV; ++v) {
+      const Out r = P::result(st[c][v], al, be, cx, cy, ci);
+      __builtin_memcpy(&w[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
+    }
+    const int ob = off[c] == kBufOff ? kBufOff : s[c] * (int)sizeof(Out);
+#pragma unroll
+    for (int k = 0; k < W; k += 4) {
+      if constexpr (W - 0 >= 4) {
+        if (k + 4 <= W) buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, ro, ob + 4 * k, 0, kStoreAux);
+      }
+    }
+    if constexpr (W % 4 == 2) buf_store8(i32x2{w[W - 2], w[W - 1]}, ro, ob + 4 * (W - 2), 0, kStoreAux);
+    if constexpr (W % 4 == 1) buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
+    if constexpr (W % 4 == 3) {
+      buf_store8(i32x2{w[W - 3], w[W - 2]}, ro, ob + 4 * (W - 3), 0, kStoreAux);
+      buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
+    }
+  }
 }
 
 // Same schedules as k_column (tiled, or persistent wave-cyclic).  The
@@ -574,22 +715,24 @@ __global__ void __launch_bounds__(512)
     stride = nw;
   }
   if (p >= p1) return;
-  PosRec cur = m.pos[p];
+  PosRec cur = cst_pos(m.pos, p);
   for (; p < p1; p += stride) {
-    const PosRec nxt = m.pos[min(p + stride, p1 - 1)];  // prefetch
+    const PosRec nxt = cst_pos(m.pos, min(p + stride, p1 - 1));  // prefetch
     colv_node<T, OP, NV, NCH>(m, in, out, nlev, cur, lane);
     cur = nxt;
   }
 }
 
-// Levels per lane of the level-vector form for (T, OP, nlev): 16 bytes per
-// lane when the column is long enough and the mesh has degree <= 6; 1 means
-// the one-level-per-lane form.
+// Levels per lane of the level-vector form for (T, OP, nlev): as many as
+// fill 16 bytes (FP64 scalar 2, FP32 scalar 4, FP32 vector 2, FP64 vector
+// 1), or `want` if smaller; 0 when the form does not apply (mesh degree
+// above 6, a column shorter than one lane vector or longer than 256 of them)
+// and the one-level-per-lane column kernel runs instead.
 template <class T, int OP>
-__host__ __device__ inline int auto_level_vec(int nlev, int maxdeg) {
-  const int nv = (int)(16 / sizeof(typename Pol<T, OP>::V));
-  if (nv < 2 || maxdeg > 6 || nlev < nv) return 1;
-  if ((nlev + 64 * nv - 1) / (64 * nv) > 4) return 1;
+__host__ __device__ inline int auto_level_vec(int nlev, int maxdeg, int want = 4) {
+  const int nv = min(want, (int)(16 / sizeof(typename Pol<T, OP>::V)));
+  if (maxdeg > 6 || nlev < nv) return 0;
+  if ((nlev + 64 * nv - 1) / (64 * nv) > 4) return 0;
   return nv;
 }
 
@@ -890,7 +1033,7 @@ __device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, const 
   if (form == FORM_COLUMN) {
     const int nv = auto_level_vec<T, OP>(nlev, m.maxdeg);
     const int nch = (nlev + 63) / 64;
-    if (nv > 1) {
+    if (nv > 0) {
       constexpr int NV = (int)(16 / sizeof(typename Pol<T, OP>::V));
       const int nchv = (nlev + 64 * NV - 1) / (64 * NV);
       if constexpr (lane_vec_ok<T, OP, NV>()) {
@@ -1109,14 +1252,15 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       // persistent grid: blocks_per_cu workgroups on every compute unit
       const int cyc = sh.blocks_per_cu > 0 ? sh.blocks_per_cu * device_cu_count() / 8 : 0;
       const dim3 cgrid = cyc > 0 ? dim3(8 * cyc) : grid;
-      int nv = sh.level_vec;
-      if (nv == 0) nv = auto_level_vec<T, OP>(nlev, m.maxdeg);
-      if (nv != 1 && nv != 2 && nv != 4)
+      // level_vec: 0 = widest lane vector, 2 / 4 = at most that many levels
+      // per lane, 1 = the one-level-per-lane kernel
+      if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
         return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
-      nv = min(nv, (int)(16 / sizeof(typename Pol<T, OP>::V)));  // <= 16 bytes per lane
-      const int nchv = (nlev + 64 * nv - 1) / (64 * nv);
-      if (nv > 1 && (nlev < nv || m.maxdeg > 6 || nchv > 4)) nv = 1;  // same results
-      if (nv > 1) {
+      const int nv = sh.level_vec == 1 ? 0
+                                       : auto_level_vec<T, OP>(nlev, m.maxdeg,
+                                                               sh.level_vec ? sh.level_vec : 4);
+      if (nv > 0) {
+        const int nchv = (nlev + 64 * nv - 1) / (64 * nv);
         void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
 #define ATLASX_COLV(NV)                                                     \
   if constexpr (lane_vec_ok<T, OP, NV>()) {                                 \
@@ -1125,7 +1269,9 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
     else if (nchv == 3) kern = k_colv<T, OP, NV, 3>;                        \
     else kern = k_colv<T, OP, NV, 4>;                                       \
   }
-        if (nv == 2) {
+        if (nv == 1) {
+          ATLASX_COLV(1)
+        } else if (nv == 2) {
           ATLASX_COLV(2)
         } else {
           ATLASX_COLV(4)
