@@ -862,6 +862,177 @@ __global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ 
 // Flat form: lanes over flattened (position, level) pairs of the tile --
 // full lanes for short columns (nlev = 1 .. 40).
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Level-vector sweep form.  As the parallel sweep above, but every LDS entry
+// and every lane holds a lane vector of NV levels (16 bytes), a workgroup
+// covers `vpc` lane vectors of every column (a level chunk), columns are
+// staged into LDS with range-checked buffer loads (one pass over each
+// column per chunk, coalesced over the run), and each position's result is
+// written with buffer stores (lanes past the chunk make no access).  Per
+// node and chunk: about one staging load instruction and NV result stores
+// against the column form's seven column loads.
+// ---------------------------------------------------------------------------
+template <class T, int OP, int NV, int EPT>
+__global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__ in,
+                                                T *__restrict__ out, int nlev, int vpc,
+                                                int ntiles, int per_xcd) {
+  using P = Pol<T, OP>;
+  using V = typename P::V;
+  using LV = LaneVec<V, NV>;
+  using R = typename LV::raw;
+  using Out = typename P::Out;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R *buf = reinterpret_cast<R *>(smem_raw);
+  const int u = xcd_tile(blockIdx.x, per_xcd);
+  const int c = u / ntiles;
+  const int tile = u - c * ntiles;
+  const int nvec = (nlev + NV - 1) / NV;
+  const int v0 = c * vpc;
+  if (v0 >= nvec) return;
+  const int nvc = min(vpc, nvec - v0);  // lane vectors in this chunk
+  const int s0 = cst(m.tile_seg)[tile];
+  const int nseg = cst(m.tile_seg)[tile + 1] - s0;
+  const int slot_stride = m.segmax * vpc;  // lane vectors per LDS slot
+  const V *vin = reinterpret_cast<const V *>(in);
+  const size_t L = (size_t)nlev;
+  const uint32_t col_bytes = (uint32_t)(L * sizeof(V));
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  // first level of lane vector k of this chunk (the last one clamped inside
+  // the column)
+  auto first = [&](int k) { return min(NV * (v0 + k), nlev - NV); };
+
+  // staging: thread i moves items i, i + blockDim, ... of the run, item =
+  // (node t of the run, lane vector k)
+  R regs[EPT];
+  int seg_len = 0;
+  auto fetch = [&](int q) {
+    int4 sg;
+    sg.x = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q)];
+    sg.y = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q) + 1];
+    sg.z = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q) + 2];
+    sg.w = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q) + 3];
+    seg_len = sg.w;
+    // the ring's columns are contiguous: one resource over the whole ring
+    const i32x4 rs = make_rsrc(vin + (size_t)sg.x * L, (uint32_t)sg.y * col_bytes);
+    const int items = sg.w * nvc;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = threadIdx.x + e * (int)blockDim.x;
+      const int t = i / nvc, k = i - t * nvc;
+      int ii = sg.z + t;
+      if (ii >= sg.y) ii -= sg.y;
+      const int off = i < items ? ii * (int)col_bytes + first(k) * (int)sizeof(V) : kBufOff;
+      regs[e] = buf_load<R>(rs, off);
+    }
+  };
+  auto deposit = [&](int q) {
+    R *b = buf + (q & 3) * slot_stride;
+    const int items = seg_len * nvc;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = threadIdx.x + e * (int)blockDim.x;
+      if (i < items) {
+        const int t = i / nvc, k = i - t * nvc;
+        b[t * vpc + k] = regs[e];
+      }
+    }
+  };
+
+  // first and last parallel with positions of this tile
+  int qa = nseg, qb = -1;
+  for (int q = 0; q < nseg; ++q) {
+    const int lo = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q)];
+    const int hi = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q) + 1];
+    if (hi > lo) {
+      qa = min(qa, q);
+      qb = q;
+    }
+  }
+  if (qb < 0) return;
+  for (int q = 0; q <= min(nseg - 1, qa + 1); ++q) {
+    fetch(q);
+    deposit(q);
+  }
+  __syncthreads();
+  const int kc = min(lane, nvc - 1);  // lanes past the chunk read a valid entry
+  const int s_l = first(kc);
+  const int ob_valid = lane < nvc;
+  for (int q = qa; q <= qb; ++q) {
+    const bool pf = q + 2 < nseg;
+    if (pf) fetch(q + 2);
+    const int p_lo = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q)];
+    const int p_hi = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q) + 1];
+    const R *bq = buf + (q & 3) * slot_stride;
+    for (int p = p_lo + wave; p < p_hi; p += nw) {
+      const PosRec rec = cst_pos(m.pos, p);
+      const int node = rec.node, r0 = rec.r0, n = rec.r1 - rec.r0;
+      const double ci = P::kVecIn ? cst(m.coslat)[node] : 0.0;
+      typename P::St st[NV];
+      {
+        const R xi = bq[rec.selfslot * vpc + kc];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P::init(st[v], LV::get(xi, v), ci);
+      }
+      constexpr int G = 6;
+      int lr[G];
+      double2 S[G];
+      double cn[G];
+      R xn[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        lr[j] = cst(m.lref)[r0 + j];
+        S[j] = cst_double2(m.S, r0 + j);
+        cn[j] = P::kVecIn ? cst(m.ncos)[r0 + j] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int l = lr[j] & ~kLrefPole;
+        xn[j] = buf[((q + ((l >> 16) & 3) - 1) & 3) * slot_stride + (l & 0xffff) * vpc + kc];
+      }
+      double cx = 0.0, cy = 0.0;
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const bool pole = (lr[j] & kLrefPole) != 0;
+        const bool use = j < n && !(P::kVecIn && pole);
+        double tx = cx, ty = cy;
+        closure_add<P::kOp>(tx, ty, S[j], pole);
+        cx = use ? tx : cx;
+        cy = use ? ty : cy;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          typename P::St t = st[v];
+          P::add(t, LV::get(xn[j], v), S[j], pole, cn[j]);
+          P::keep(st[v], t, use);
+        }
+      }
+      const double al = rec.alpha, be = P::kVecOut ? rec.beta : 0.0;
+      const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
+                                 (uint32_t)(L * sizeof(Out)));
+      constexpr int W = NV * (int)sizeof(Out) / 4;
+      int w[W];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const Out r = P::result(st[v], al, be, cx, cy, ci);
+        __builtin_memcpy(&w[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
+      }
+      const int ob = ob_valid ? s_l * (int)sizeof(Out) : kBufOff;
+#pragma unroll
+      for (int k = 0; k + 4 <= W; k += 4)
+        buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, ro, ob + 4 * k, 0, kStoreAux);
+      if constexpr (W % 4 == 2) buf_store8(i32x2{w[W - 2], w[W - 1]}, ro, ob + 4 * (W - 2), 0, kStoreAux);
+      if constexpr (W % 4 == 1) buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
+      if constexpr (W % 4 == 3) {
+        buf_store8(i32x2{w[W - 3], w[W - 2]}, ro, ob + 4 * (W - 3), 0, kStoreAux);
+        buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
+      }
+    }
+    if (pf) deposit(q + 2);
+    __syncthreads();
+  }
+}
+
 template <class T, int OP>
 __global__ void __launch_bounds__(1024) k_flat(DevMesh m, const T *__restrict__ in,
                                                T *__restrict__ out, int nlev, int npb,
@@ -1321,6 +1492,56 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       // the chunk shrinks until a parallel's run fits the staging registers
       // (16 elements per thread) and four runs fit in LDS
       if (sh.block > 512) return fail(ATLAS_EINVAL, "the sweep form takes at most 512 threads");
+      if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
+        return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
+      const int nv = sh.level_vec == 1 ? 0
+                                       : auto_level_vec<T, OP>(nlev, m.maxdeg,
+                                                               sh.level_vec ? sh.level_vec : 4);
+      if (nv > 0) {
+        // level chunk: vpc lane vectors per workgroup pass, at most 64, split
+        // evenly; it shrinks until four runs fit the LDS budget (two
+        // workgroups per compute unit) and a run fits the staging registers
+        const int nvec = (nlev + nv - 1) / nv;
+        int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + nv - 1) / nv) : 64;
+        vpc = min(vpc, nvec);
+        {
+          const int nchunk = (nvec + vpc - 1) / vpc;
+          vpc = (nvec + nchunk - 1) / nchunk;
+        }
+        const size_t seg = (size_t)max(1, m.segmax);
+        const size_t budget = kMaxLds / 2;
+        while (vpc > 1 && (4 * seg * vpc * 16 > budget ||
+                           (int)((seg * vpc + sh.block - 1) / sh.block) > 16))
+          vpc = (vpc + 1) / 2;
+        const int ept = (int)((seg * vpc + sh.block - 1) / sh.block);
+        if (4 * seg * vpc * 16 > kMaxLds || ept > 16)
+          return fail(ATLAS_EINVAL, "sweep tile too large for LDS or the block size");
+        const int nchunk = (nvec + vpc - 1) / vpc;
+        const size_t lds = 4 * seg * vpc * 16;
+        const int units = m.ntiles * nchunk;
+        const int per = (units + 7) / 8;
+        void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
+#define ATLASX_SWV(NV)                                              \
+  if constexpr (lane_vec_ok<T, OP, NV>()) {                         \
+    if (ept <= 4) kern = k_sweepv<T, OP, NV, 4>;                    \
+    else if (ept <= 8) kern = k_sweepv<T, OP, NV, 8>;               \
+    else kern = k_sweepv<T, OP, NV, 16>;                            \
+  }
+        if (nv == 1) {
+          ATLASX_SWV(1)
+        } else if (nv == 2) {
+          ATLASX_SWV(2)
+        } else {
+          ATLASX_SWV(4)
+        }
+#undef ATLASX_SWV
+        if (!kern) return fail(ATLAS_EINVAL, "level_vec not available for this dtype and operator");
+        ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(per * 8), block, lds, st, m, in, out, nlev, vpc, m.ntiles,
+                           per);
+        break;
+      }
       // wavefront w stages nodes w, w + nw, ... of a run: EPT >= segmax / nw;
       // four runs of kc levels must fit in LDS (the chunk shrinks if needed)
       const size_t vbytes = sizeof(T) * (OP == OP_GRAD ? 1 : 2);
