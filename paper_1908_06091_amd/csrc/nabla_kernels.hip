@@ -1365,14 +1365,21 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
   return slots * (size_t)nlev * w * (grad ? 2 : 1);
 }
 
+// Built-in shape (the autotuner can replace it per mesh and class).  Long
+// columns: the column form over blocks of 16 consecutive positions (a run of
+// one parallel, so the neighbour columns of consecutive blocks overlap in
+// L2), lane vectors except for the FP32 gradient, whose compensated sums
+// make it arithmetic-bound: there one level per lane keeps more lanes busy
+// (the Laplacian's two passes share one shape; its divergence pass gains
+// more from lane vectors than its gradient pass loses).
+// Short columns: the flat form over the mesh's tiles.
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   (void)m;
-  (void)op;
-  (void)dt;
   LaunchShape s;
   s.variant = nlev >= 48 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
   s.block = 256;
-  s.nodes_per_block = 0;
+  s.nodes_per_block = s.variant == ATLAS_VARIANT_COLUMN ? 16 : 0;
+  s.level_vec = (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) ? 1 : 0;
   return s;
 }
 
