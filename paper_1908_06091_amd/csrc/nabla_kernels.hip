@@ -868,21 +868,31 @@ __global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ 
 // covers `vpc` lane vectors of every column (a level chunk), columns are
 // staged into LDS with range-checked buffer loads (one pass over each
 // column per chunk, coalesced over the run), and each position's result is
-// written with buffer stores (lanes past the chunk make no access).  Per
-// node and chunk: about one staging load instruction and NV result stores
-// against the column form's seven column loads.
+// written with buffer stores (lanes past the chunk make no access).  The
+// geometry of the positions is staged into LDS as well, one step ahead (the
+// position records of run q+2 and the incidence rows of run q+1 while run
+// q is computed), so a position needs no dependent scalar loads: per step
+// the chain is one LDS read of its record and rows, one of its neighbours.
 // ---------------------------------------------------------------------------
+constexpr int kSweepEpt = 4;   // staged lane vectors per thread and run
+constexpr int kGeoWords = 11;  // 16-byte words of staged rows per position:
+                               // S[6] (6), lref[8] (2), ncos[6] (3)
+
 template <class T, int OP, int NV, int EPT>
-__global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__ in,
-                                                T *__restrict__ out, int nlev, int vpc,
-                                                int ntiles, int per_xcd) {
+__global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict__ in,
+                                                 T *__restrict__ out, int nlev, int vpc,
+                                                 int ntiles, int per_xcd) {
   using P = Pol<T, OP>;
   using V = typename P::V;
   using LV = LaneVec<V, NV>;
   using R = typename LV::raw;
   using Out = typename P::Out;
+  constexpr int WPP = P::kVecIn ? kGeoWords : 8;  // rows words staged per position
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R *buf = reinterpret_cast<R *>(smem_raw);
+  const int segmax = m.segmax;
+  R *buf = reinterpret_cast<R *>(smem_raw);                        // [4][segmax][vpc]
+  i32x4 *gpos = reinterpret_cast<i32x4 *>(buf + 4 * segmax * vpc);  // [4][segmax][2]
+  i32x4 *grow = gpos + 4 * segmax * 2;                              // [4][segmax][kGeoWords]
   const int u = xcd_tile(blockIdx.x, per_xcd);
   const int c = u / ntiles;
   const int tile = u - c * ntiles;
@@ -892,37 +902,34 @@ __global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__
   const int nvc = min(vpc, nvec - v0);  // lane vectors in this chunk
   const int s0 = cst(m.tile_seg)[tile];
   const int nseg = cst(m.tile_seg)[tile + 1] - s0;
-  const int slot_stride = m.segmax * vpc;  // lane vectors per LDS slot
+  const int slot_stride = segmax * vpc;  // lane vectors per LDS slot
   const V *vin = reinterpret_cast<const V *>(in);
   const size_t L = (size_t)nlev;
   const uint32_t col_bytes = (uint32_t)(L * sizeof(V));
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // first level of lane vector k of this chunk (the last one clamped inside
-  // the column)
+  const int *segi = reinterpret_cast<const int *>(m.seg);
+  const int *segp = reinterpret_cast<const int *>(m.seg_pos);
   auto first = [&](int k) { return min(NV * (v0 + k), nlev - NV); };
+  auto run_lo = [&](int q) { return cst(segp)[2 * (s0 + q)]; };
+  auto run_hi = [&](int q) { return cst(segp)[2 * (s0 + q) + 1]; };
 
-  // staging: thread i moves items i, i + blockDim, ... of the run, item =
-  // (node t of the run, lane vector k)
+  // ---- columns: item = (node t of the segment, lane vector k)
   R regs[EPT];
   int seg_len = 0;
   auto fetch = [&](int q) {
-    int4 sg;
-    sg.x = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q)];
-    sg.y = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q) + 1];
-    sg.z = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q) + 2];
-    sg.w = cst(reinterpret_cast<const int *>(m.seg))[4 * (s0 + q) + 3];
-    seg_len = sg.w;
-    // the ring's columns are contiguous: one resource over the whole ring
-    const i32x4 rs = make_rsrc(vin + (size_t)sg.x * L, (uint32_t)sg.y * col_bytes);
-    const int items = sg.w * nvc;
+    const int rb = cst(segi)[4 * (s0 + q)], nx = cst(segi)[4 * (s0 + q) + 1];
+    const int lo = cst(segi)[4 * (s0 + q) + 2];
+    seg_len = cst(segi)[4 * (s0 + q) + 3];
+    const i32x4 rs = make_rsrc(vin + (size_t)rb * L, (uint32_t)nx * col_bytes);
+    const int items = seg_len * nvc;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int i = threadIdx.x + e * (int)blockDim.x;
       const int t = i / nvc, k = i - t * nvc;
-      int ii = sg.z + t;
-      if (ii >= sg.y) ii -= sg.y;
+      int ii = lo + t;
+      if (ii >= nx) ii -= nx;
       const int off = i < items ? ii * (int)col_bytes + first(k) * (int)sizeof(V) : kBufOff;
       regs[e] = buf_load<R>(rs, off);
     }
@@ -939,13 +946,49 @@ __global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__
       }
     }
   };
+  // ---- position records of run q (2 words each) and rows of run q (WPP
+  // words each, at the record's first incidence); a thread moves at most one
+  // word of each kind per step (the dispatch guarantees the block is large
+  // enough)
+  i32x4 preg = {0, 0, 0, 0}, rreg = {0, 0, 0, 0};
+  int pitem = -1, ritem = -1;
+  auto fetch_pos = [&](int q) {
+    const int plo = run_lo(q), n = run_hi(q) - plo;
+    pitem = (int)threadIdx.x < 2 * n ? (int)threadIdx.x : -1;
+    if (pitem >= 0) {
+      const i32x4 *src = reinterpret_cast<const i32x4 *>(m.pos + plo + (pitem >> 1)) + (pitem & 1);
+      preg = *src;
+    }
+  };
+  auto deposit_pos = [&](int q) {
+    if (pitem >= 0) gpos[((q & 3) * segmax) * 2 + pitem] = preg;
+  };
+  auto fetch_rows = [&](int q) {
+    const int n = run_hi(q) - run_lo(q);
+    ritem = (int)threadIdx.x < WPP * n ? (int)threadIdx.x : -1;
+    if (ritem >= 0) {
+      const int t = ritem / WPP, w = ritem - t * WPP;
+      const int r0 = gpos[((q & 3) * segmax + t) * 2].y;  // staged record: node, r0, r1, slot
+      const unsigned char *src;
+      if (w < 6) src = reinterpret_cast<const unsigned char *>(m.S + r0 + w);
+      else if (w < 8) src = reinterpret_cast<const unsigned char *>(m.lref + r0) + 16 * (w - 6);
+      else src = reinterpret_cast<const unsigned char *>(m.ncos + r0) + 16 * (w - 8);
+      i32x4 v;
+      __builtin_memcpy(&v, src, 16);
+      rreg = v;
+    }
+  };
+  auto deposit_rows = [&](int q) {
+    if (ritem >= 0) {
+      const int t = ritem / WPP, w = ritem - t * WPP;
+      grow[((q & 3) * segmax + t) * kGeoWords + w] = rreg;
+    }
+  };
 
   // first and last parallel with positions of this tile
   int qa = nseg, qb = -1;
   for (int q = 0; q < nseg; ++q) {
-    const int lo = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q)];
-    const int hi = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q) + 1];
-    if (hi > lo) {
+    if (run_hi(q) > run_lo(q)) {
       qa = min(qa, q);
       qb = q;
     }
@@ -955,37 +998,75 @@ __global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__
     fetch(q);
     deposit(q);
   }
+  fetch_pos(qa);
+  deposit_pos(qa);
+  if (qa + 1 < nseg) {
+    fetch_pos(qa + 1);
+    deposit_pos(qa + 1);
+  }
   __syncthreads();
+  fetch_rows(qa);
+  deposit_rows(qa);
+  __syncthreads();
+
   const int kc = min(lane, nvc - 1);  // lanes past the chunk read a valid entry
   const int s_l = first(kc);
-  const int ob_valid = lane < nvc;
+  const bool lane_on = lane < nvc;
   for (int q = qa; q <= qb; ++q) {
     const bool pf = q + 2 < nseg;
-    if (pf) fetch(q + 2);
-    const int p_lo = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q)];
-    const int p_hi = cst(reinterpret_cast<const int *>(m.seg_pos))[2 * (s0 + q) + 1];
+    if (pf) {
+      fetch(q + 2);
+      fetch_pos(q + 2);
+    }
+    const bool rf = q + 1 < nseg;
+    if (rf) fetch_rows(q + 1);
+    const int plo = run_lo(q), phi = run_hi(q);
     const R *bq = buf + (q & 3) * slot_stride;
-    for (int p = p_lo + wave; p < p_hi; p += nw) {
-      const PosRec rec = cst_pos(m.pos, p);
-      const int node = rec.node, r0 = rec.r0, n = rec.r1 - rec.r0;
+    const i32x4 *gp = gpos + (q & 3) * segmax * 2;
+    const i32x4 *gr = grow + (q & 3) * segmax * kGeoWords;
+    for (int p = plo + wave; p < phi; p += nw) {
+      const int t = p - plo;
+      const i32x4 w0 = gp[2 * t], w1 = gp[2 * t + 1];
+      const int node = w0.x, n = w0.z - w0.y, selfslot = w0.w;
+      double al, be;
+      {
+        const int a2[2] = {w1.x, w1.y}, b2[2] = {w1.z, w1.w};
+        __builtin_memcpy(&al, a2, 8);
+        __builtin_memcpy(&be, b2, 8);
+      }
+      if (!P::kVecOut) be = 0.0;
       const double ci = P::kVecIn ? cst(m.coslat)[node] : 0.0;
+      constexpr int G = 6;
+      double2 S[G];
+      int lr[8];
+      double cn[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const i32x4 v = gr[t * kGeoWords + j];
+        __builtin_memcpy(&S[j], &v, 16);
+      }
+      {
+        const i32x4 a = gr[t * kGeoWords + 6], b = gr[t * kGeoWords + 7];
+        lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
+        lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
+      }
+      if (P::kVecIn) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const i32x4 v = gr[t * kGeoWords + 8 + k];
+          __builtin_memcpy(&cn[2 * k], &v, 16);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < G; ++j) cn[j] = 0.0;
+      }
       typename P::St st[NV];
       {
-        const R xi = bq[rec.selfslot * vpc + kc];
+        const R xi = bq[selfslot * vpc + kc];
 #pragma unroll
         for (int v = 0; v < NV; ++v) P::init(st[v], LV::get(xi, v), ci);
       }
-      constexpr int G = 6;
-      int lr[G];
-      double2 S[G];
-      double cn[G];
       R xn[G];
-#pragma unroll
-      for (int j = 0; j < G; ++j) {
-        lr[j] = cst(m.lref)[r0 + j];
-        S[j] = cst_double2(m.S, r0 + j);
-        cn[j] = P::kVecIn ? cst(m.ncos)[r0 + j] : 0.0;
-      }
 #pragma unroll
       for (int j = 0; j < G; ++j) {
         const int l = lr[j] & ~kLrefPole;
@@ -1002,12 +1083,11 @@ __global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__
         cy = use ? ty : cy;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          typename P::St t = st[v];
-          P::add(t, LV::get(xn[j], v), S[j], pole, cn[j]);
-          P::keep(st[v], t, use);
+          typename P::St tt = st[v];
+          P::add(tt, LV::get(xn[j], v), S[j], pole, cn[j]);
+          P::keep(st[v], tt, use);
         }
       }
-      const double al = rec.alpha, be = P::kVecOut ? rec.beta : 0.0;
       const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
                                  (uint32_t)(L * sizeof(Out)));
       constexpr int W = NV * (int)sizeof(Out) / 4;
@@ -1017,7 +1097,7 @@ __global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__
         const Out r = P::result(st[v], al, be, cx, cy, ci);
         __builtin_memcpy(&w[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
       }
-      const int ob = ob_valid ? s_l * (int)sizeof(Out) : kBufOff;
+      const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
 #pragma unroll
       for (int k = 0; k + 4 <= W; k += 4)
         buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, ro, ob + 4 * k, 0, kStoreAux);
@@ -1028,7 +1108,11 @@ __global__ void __launch_bounds__(512) k_sweepv(DevMesh m, const T *__restrict__
         buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
       }
     }
-    if (pf) deposit(q + 2);
+    if (pf) {
+      deposit(q + 2);
+      deposit_pos(q + 2);
+    }
+    if (rf) deposit_rows(q + 1);
     __syncthreads();
   }
 }
@@ -1498,12 +1582,17 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         return fail(ATLAS_EINVAL, "the sweep form runs on the mesh's tiles (nodes_per_block = 0)");
       // the chunk shrinks until a parallel's run fits the staging registers
       // (16 elements per thread) and four runs fit in LDS
-      if (sh.block > 512) return fail(ATLAS_EINVAL, "the sweep form takes at most 512 threads");
       if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
         return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
-      const int nv = sh.level_vec == 1 ? 0
-                                       : auto_level_vec<T, OP>(nlev, m.maxdeg,
-                                                               sh.level_vec ? sh.level_vec : 4);
+      // the level-vector sweep stages each position's geometry with one
+      // thread per 16-byte word: it needs a block of segmax * kGeoWords
+      // threads, else the one-level-per-lane sweep runs (same results)
+      int nv = sh.level_vec == 1 ? 0
+                                 : auto_level_vec<T, OP>(nlev, m.maxdeg,
+                                                         sh.level_vec ? sh.level_vec : 4);
+      if (sh.block < max(1, m.segmax) * kGeoWords) nv = 0;
+      if (nv == 0 && sh.block > 512)
+        return fail(ATLAS_EINVAL, "the one-level-per-lane sweep takes at most 512 threads");
       if (nv > 0) {
         // level chunk: vpc lane vectors per workgroup pass, at most 64, split
         // evenly; it shrinks until four runs fit the LDS budget (two
@@ -1516,24 +1605,24 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
           vpc = (nvec + nchunk - 1) / nchunk;
         }
         const size_t seg = (size_t)max(1, m.segmax);
-        const size_t budget = kMaxLds / 2;
-        while (vpc > 1 && (4 * seg * vpc * 16 > budget ||
-                           (int)((seg * vpc + sh.block - 1) / sh.block) > 16))
+        // geometry staged per run: 2 record words and up to kGeoWords row
+        // words per position, one of each kind per thread
+        const size_t geo = 4 * seg * (2 + kGeoWords) * 16;
+        const size_t budget = sh.block > 512 ? kMaxLds : kMaxLds / 2;
+        // (staging: at most kSweepEpt lane vectors per thread and run)
+        while (vpc > 1 && (4 * seg * vpc * 16 + geo > budget ||
+                           (int)((seg * vpc + sh.block - 1) / sh.block) > kSweepEpt))
           vpc = (vpc + 1) / 2;
         const int ept = (int)((seg * vpc + sh.block - 1) / sh.block);
-        if (4 * seg * vpc * 16 > kMaxLds || ept > 16)
+        if (4 * seg * vpc * 16 + geo > kMaxLds || ept > kSweepEpt)
           return fail(ATLAS_EINVAL, "sweep tile too large for LDS or the block size");
         const int nchunk = (nvec + vpc - 1) / vpc;
-        const size_t lds = 4 * seg * vpc * 16;
+        const size_t lds = 4 * seg * vpc * 16 + geo;
         const int units = m.ntiles * nchunk;
         const int per = (units + 7) / 8;
         void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
 #define ATLASX_SWV(NV)                                              \
-  if constexpr (lane_vec_ok<T, OP, NV>()) {                         \
-    if (ept <= 4) kern = k_sweepv<T, OP, NV, 4>;                    \
-    else if (ept <= 8) kern = k_sweepv<T, OP, NV, 8>;               \
-    else kern = k_sweepv<T, OP, NV, 16>;                            \
-  }
+  if constexpr (lane_vec_ok<T, OP, NV>()) kern = k_sweepv<T, OP, NV, kSweepEpt>;
         if (nv == 1) {
           ATLASX_SWV(1)
         } else if (nv == 2) {

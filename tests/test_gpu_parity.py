@@ -93,10 +93,11 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
                 shapes.append(P.Launch(variant, block, npb))
     shapes.append(P.Launch(P.VARIANT_FLUX, 256, 0))
     shapes.append(P.Launch(P.VARIANT_FLUX, 64, 0))
-    for block in (64, 256, 512):
+    for block in (64, 256, 512, 1024):
         for kc in (0, 1, 5, 32):
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))      # lane vectors
-            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 1))  # one level per lane
+            if block <= 512:
+                shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 1))  # one level per lane
     for kc in (1, 7, 64):
         shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, kc))
     for block in (64, 256):
