@@ -746,7 +746,7 @@ __host__ __device__ inline int auto_level_vec(int nlev, int maxdeg, int want = 4
 // neighbour comes from LDS.  One wavefront per position, lanes over levels.
 // ---------------------------------------------------------------------------
 template <class T, int OP, int EPT>
-__global__ void __launch_bounds__(512) k_sweep(DevMesh m, const T *__restrict__ in,
+__global__ void __launch_bounds__(1024) k_sweep(DevMesh m, const T *__restrict__ in,
                                                T *__restrict__ out, int nlev, int kcmax,
                                                int ntiles, int per_xcd) {
   using P = Pol<T, OP>;
@@ -1591,8 +1591,6 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
                                  : auto_level_vec<T, OP>(nlev, m.maxdeg,
                                                          sh.level_vec ? sh.level_vec : 4);
       if (sh.block < max(1, m.segmax) * kGeoWords) nv = 0;
-      if (nv == 0 && sh.block > 512)
-        return fail(ATLAS_EINVAL, "the one-level-per-lane sweep takes at most 512 threads");
       if (nv > 0) {
         // level chunk: vpc lane vectors per workgroup pass, at most 64, split
         // evenly; it shrinks until four runs fit the LDS budget (two
