@@ -878,11 +878,10 @@ constexpr int kSweepEpt = 4;   // staged lane vectors per thread and run
 constexpr int kGeoWords = 11;  // 16-byte words of staged rows per position:
                                // S[6] (6), lref[8] (2), ncos[6] (3)
 
-template <class T, int OP, int NV, int KP>
+template <class T, int OP, int NV, int EPT>
 __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict__ in,
                                                  T *__restrict__ out, int nlev, int vpc,
                                                  int ntiles, int per_xcd) {
-  constexpr int EPT = kSweepEpt;
   using P = Pol<T, OP>;
   using V = typename P::V;
   using LV = LaneVec<V, NV>;
@@ -1013,29 +1012,20 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
   const int kc = min(lane, nvc - 1);  // lanes past the chunk read a valid entry
   const int s_l = first(kc);
   const bool lane_on = lane < nvc;
-  // Each step: (1) the loads for later steps are issued first (the rows
-  // of run q+1 need an LDS read, so they go before the column loads), (2)
-  // every wavefront computes exactly KP positions of run q (positions past
-  // the run recompute a valid one and store nothing), so the number of
-  // stores issued after the loads is a compile-time constant and (3) the
-  // deposit waits for the loads without waiting for those stores.
   for (int q = qa; q <= qb; ++q) {
     const bool pf = q + 2 < nseg;
-    const bool rf = q + 1 < nseg;
-    if (rf) fetch_rows(q + 1);
     if (pf) {
       fetch(q + 2);
       fetch_pos(q + 2);
     }
+    const bool rf = q + 1 < nseg;
+    if (rf) fetch_rows(q + 1);
     const int plo = run_lo(q), phi = run_hi(q);
     const R *bq = buf + (q & 3) * slot_stride;
     const i32x4 *gp = gpos + (q & 3) * segmax * 2;
     const i32x4 *gr = grow + (q & 3) * segmax * kGeoWords;
-#pragma unroll
-    for (int kp = 0; kp < KP; ++kp) {
-      const int p = plo + wave + kp * nw;
-      const bool pos_on = p < phi;
-      const int t = min(p, max(phi - 1, plo)) - plo;
+    for (int p = plo + wave; p < phi; p += nw) {
+      const int t = p - plo;
       const i32x4 w0 = gp[2 * t], w1 = gp[2 * t + 1];
       const int node = w0.x, n = w0.z - w0.y, selfslot = w0.w;
       double al, be;
@@ -1107,7 +1097,7 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
         const Out r = P::result(st[v], al, be, cx, cy, ci);
         __builtin_memcpy(&w[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
       }
-      const int ob = (lane_on && pos_on) ? s_l * (int)sizeof(Out) : kBufOff;
+      const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
 #pragma unroll
       for (int k = 0; k + 4 <= W; k += 4)
         buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, ro, ob + 4 * k, 0, kStoreAux);
@@ -1596,14 +1586,11 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
       // the level-vector sweep stages each position's geometry with one
       // thread per 16-byte word: it needs a block of segmax * kGeoWords
-      // threads and at most 4 positions of a run per wavefront, else the
-      // one-level-per-lane sweep runs (same results)
+      // threads, else the one-level-per-lane sweep runs (same results)
       int nv = sh.level_vec == 1 ? 0
                                  : auto_level_vec<T, OP>(nlev, m.maxdeg,
                                                          sh.level_vec ? sh.level_vec : 4);
-      if (sh.block < max(1, m.segmax) * kGeoWords ||
-          max(1, m.segmax) > 4 * (sh.block >> 6))
-        nv = 0;
+      if (sh.block < max(1, m.segmax) * kGeoWords) nv = 0;
       if (nv > 0) {
         // level chunk: vpc lane vectors per workgroup pass, at most 64, split
         // evenly; it shrinks until four runs fit the LDS budget (two
@@ -1632,14 +1619,8 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         const int units = m.ntiles * nchunk;
         const int per = (units + 7) / 8;
         void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
-        const int kp = (m.segmax + (sh.block >> 6) - 1) / (sh.block >> 6);
-#define ATLASX_SWV(NV)                                                  \
-  if constexpr (lane_vec_ok<T, OP, NV>()) {                             \
-    if (kp <= 1) kern = k_sweepv<T, OP, NV, 1>;                         \
-    else if (kp <= 2) kern = k_sweepv<T, OP, NV, 2>;                    \
-    else if (kp <= 3) kern = k_sweepv<T, OP, NV, 3>;                    \
-    else if (kp <= 4) kern = k_sweepv<T, OP, NV, 4>;                    \
-  }
+#define ATLASX_SWV(NV)                                              \
+  if constexpr (lane_vec_ok<T, OP, NV>()) kern = k_sweepv<T, OP, NV, kSweepEpt>;
         if (nv == 1) {
           ATLASX_SWV(1)
         } else if (nv == 2) {
