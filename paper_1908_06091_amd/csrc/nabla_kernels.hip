@@ -1452,18 +1452,27 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
 // Built-in shape (the autotuner can replace it per mesh and class).  Long
 // columns: the column form over blocks of 16 consecutive positions (a run of
 // one parallel, so the neighbour columns of consecutive blocks overlap in
-// L2), lane vectors except for the FP32 gradient, whose compensated sums
+// L2) -- the level-vector sweep for the FP64 gradient --, lane vectors
+// except for the FP32 gradient, whose compensated sums
 // make it arithmetic-bound: there one level per lane keeps more lanes busy
 // (the Laplacian's two passes share one shape; its divergence pass gains
 // more from lane vectors than its gradient pass loses).
 // Short columns: the flat form over the mesh's tiles.
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
-  (void)m;
   LaunchShape s;
   s.variant = nlev >= 48 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
   s.block = 256;
   s.nodes_per_block = s.variant == ATLAS_VARIANT_COLUMN ? 16 : 0;
   s.level_vec = (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) ? 1 : 0;
+  // FP64 gradient of long columns: the level-vector sweep with 12
+  // wavefronts per workgroup, where the mesh has a sweep plan
+  if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && nlev >= 48 && m.d.sweep_ok &&
+      max(1, m.d.segmax) * kGeoWords <= 768) {
+    s.variant = ATLAS_VARIANT_SWEEP;
+    s.block = 768;
+    s.nodes_per_block = 0;
+    s.level_vec = 0;
+  }
   return s;
 }
 
