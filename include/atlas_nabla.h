@@ -229,16 +229,19 @@ typedef struct {
                                per wavefront per step, so the set of columns
                                in flight stays small enough for the L2;
                                0 = one workgroup per tile                   */
-  int32_t level_vec;        /* column: levels per lane.  0 = the level-vector
-                               kernel at its widest (each lane moves 16
-                               bytes: FP64 scalar 2 levels, FP32 scalar 4,
-                               FP32 vector 2, FP64 vector 1; lanes past the
-                               column make no memory access); 2 or 4 = that
-                               kernel with at most that many levels; 1 = the
-                               one-level-per-lane kernel.  The level-vector
-                               kernel needs a mesh of degree <= 6 and a
-                               column of 1..256 lane vectors; otherwise the
-                               one-level-per-lane kernel runs.            */
+  int32_t level_vec;        /* column and sweep forms: levels per lane.  0 =
+                               the level-vector kernels with the width (1..4
+                               levels, at most 32 bytes per lane) that
+                               needs the fewest level slots per lane, then
+                               the fewest loads (at 137 levels: 3 for FP64
+                               and FP32 scalars and FP32 vectors, 1 for FP64
+                               vectors); 2..4 = that width (capped at 32
+                               bytes); 1 = the one-level-per-lane kernels.
+                               Lanes past the column make no memory access.
+                               The level-vector kernels need a mesh of
+                               degree 4..6 and at most 256 lane vectors per
+                               column; otherwise the one-level-per-lane
+                               kernels run.                                */
 } atlas_launch;
 
 /* Apply `op` with an explicit launch shape (tests, autotuner).  For

@@ -109,8 +109,8 @@ atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
     return fail(ATLAS_EINVAL, "level_chunk must be in [0, 64]");
   if (sh.blocks_per_cu < 0 || sh.blocks_per_cu > 32)
     return fail(ATLAS_EINVAL, "blocks_per_cu must be in [0, 32]");
-  if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
-    return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
+  if (sh.level_vec < 0 || sh.level_vec > 4)
+    return fail(ATLAS_EINVAL, "level_vec must be in [0, 4]");
   size_t need = 0;
   if (op == ATLAS_OP_LAPLACIAN) need += lapl_ws_bytes(m, nlev, dt);
   if (sh.variant == ATLAS_VARIANT_FLUX) need += flux_ws_bytes(m, op, nlev, dt);

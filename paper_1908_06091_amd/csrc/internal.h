@@ -79,6 +79,7 @@ struct DevMesh {
   // parallel-sweep plan: per tile, the parallels it touches (its own and
   // one above / below), each as a segment of consecutive nodes
   int32_t maxdeg = 0;                // longest incidence row
+  int32_t mindeg = 0;                // fewest mesh (non-pole) incidences of a row
   int32_t sweep_ok = 0;              // plan valid for this mesh
   int32_t segmax = 0;                // longest segment (nodes)
   const int32_t *tile_seg = nullptr; // [ntiles+1] segment range of a tile

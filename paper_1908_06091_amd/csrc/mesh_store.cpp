@@ -277,9 +277,10 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   nbr.reserve(2 * E + 2 * NP);
   inc_edge.reserve(2 * E + 2 * NP);
   S.reserve(2 * E + 2 * NP);
-  int32_t maxdeg = 0;
+  int32_t maxdeg = 0, mindeg = INT32_MAX;
   for (int64_t p = 0; p < V; ++p) {
     const int32_t i = perm[p];
+    mindeg = std::min<int32_t>(mindeg, (int32_t)(d->node2edge_ptr[i + 1] - d->node2edge_ptr[i]));
     for (int64_t r = d->node2edge_ptr[i]; r < d->node2edge_ptr[i + 1]; ++r) {
       const int32_t e = d->node2edge[r];
       const int8_t s = d->node2edge_sign[r];
@@ -340,6 +341,7 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->nrings = nrings;
   m->max_degree = maxdeg;
   m->d.maxdeg = maxdeg;
+  m->d.mindeg = V > 0 ? mindeg : 0;
   m->d.sweep_ok = sweep_ok ? 1 : 0;
   m->d.segmax = sp.segmax;
   const double *vol_d = nullptr, *cos_pd = nullptr;

@@ -533,50 +533,90 @@ __device__ __forceinline__ PosRec cst_pos(const PosRec *p, size_t i) {
   return r;
 }
 
+typedef int i32x3 __attribute__((ext_vector_type(3)));
+__device__ int buf_load4(i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.i32");
+__device__ i32x3 buf_load12(i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v3i32");
+__device__ void buf_store12(i32x3 v, i32x4 rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v3i32");
+
+// A lane vector of 4..32 bytes, in 16-, 8- and 4-byte pieces.
 template <class R>
 __device__ __forceinline__ R buf_load(const i32x4 &rsrc, int voff) {
-  static_assert(sizeof(R) == 16 || sizeof(R) == 8, "lane vectors are 8 or 16 bytes");
-  R r;
-  if constexpr (sizeof(R) == 16) {
-    const i32x4 v = buf_load16(rsrc, voff, 0, 0);
-    __builtin_memcpy(&r, &v, 16);
-  } else {
-    const i32x2 v = buf_load8(rsrc, voff, 0, 0);
-    __builtin_memcpy(&r, &v, 8);
+  constexpr int B = (int)sizeof(R);
+  static_assert(B % 4 == 0 && B <= 32, "lane vectors are 4..32 bytes");
+  int w[B / 4];
+  int at = 0;
+#pragma unroll
+  for (; at + 16 <= B; at += 16) {
+    const i32x4 v = buf_load16(rsrc, voff + at, 0, 0);
+    w[at / 4] = v.x; w[at / 4 + 1] = v.y; w[at / 4 + 2] = v.z; w[at / 4 + 3] = v.w;
   }
+  if constexpr (B % 16 == 12) {
+    const i32x3 v = buf_load12(rsrc, voff + (B / 16) * 16, 0, 0);
+    w[(B / 16) * 4] = v.x;
+    w[(B / 16) * 4 + 1] = v.y;
+    w[(B / 16) * 4 + 2] = v.z;
+  } else {
+    if constexpr (B % 16 >= 8) {
+      const i32x2 v = buf_load8(rsrc, voff + (B / 16) * 16, 0, 0);
+      w[(B / 16) * 4] = v.x;
+      w[(B / 16) * 4 + 1] = v.y;
+    }
+    if constexpr (B % 8 == 4) w[B / 4 - 1] = buf_load4(rsrc, voff + B - 4, 0, 0);
+  }
+  R r;
+  __builtin_memcpy(&r, w, B);
   return r;
 }
 
-template <class V, int NV> struct LaneVec;
-template <> struct LaneVec<double, 2> {
-  typedef double raw __attribute__((ext_vector_type(2), aligned(8)));
-  static __device__ __forceinline__ double get(const raw &r, int v) { return r[v]; }
-};
-template <> struct LaneVec<float, 2> {
-  typedef float raw __attribute__((ext_vector_type(2), aligned(4)));
-  static __device__ __forceinline__ float get(const raw &r, int v) { return r[v]; }
-};
-template <> struct LaneVec<float, 4> {
-  typedef float raw __attribute__((ext_vector_type(4), aligned(4)));
-  static __device__ __forceinline__ float get(const raw &r, int v) { return r[v]; }
-};
-template <> struct LaneVec<v2d, 1> {
-  typedef double raw __attribute__((ext_vector_type(2), aligned(16)));
-  static __device__ __forceinline__ v2d get(const raw &r, int) { return v2d{r[0], r[1]}; }
-};
-template <> struct LaneVec<v2f, 2> {
-  typedef float raw __attribute__((ext_vector_type(4), aligned(8)));
-  static __device__ __forceinline__ v2f get(const raw &r, int v) { return v2f{r[2 * v], r[2 * v + 1]}; }
+// Stores `W` 32-bit words of one lane at byte offset `ob`, in 16-, 8- and
+// 4-byte pieces (non-temporal).
+template <int W>
+__device__ __forceinline__ void buf_store_words(const int (&w)[W], const i32x4 &rsrc, int ob) {
+#pragma unroll
+  for (int k = 0; k + 4 <= W; k += 4)
+    buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, rsrc, ob + 4 * k, 0, kStoreAux);
+  if constexpr (W % 4 == 3) {
+    buf_store12(i32x3{w[W - 3], w[W - 2], w[W - 1]}, rsrc, ob + 4 * (W - 3), 0, kStoreAux);
+  } else {
+    if constexpr (W % 4 >= 2)
+      buf_store8(i32x2{w[(W / 4) * 4], w[(W / 4) * 4 + 1]}, rsrc, ob + 16 * (W / 4), 0, kStoreAux);
+    if constexpr (W % 2 == 1) buf_store4(w[W - 1], rsrc, ob + 4 * (W - 1), 0, kStoreAux);
+  }
+}
+
+// A lane vector: NV consecutive levels of one column, NV * sizeof(V) bytes.
+template <class V> struct ElemOf { using E = V; static constexpr int C = 1; };
+template <> struct ElemOf<v2d> { using E = double; static constexpr int C = 2; };
+template <> struct ElemOf<v2f> { using E = float; static constexpr int C = 2; };
+
+template <class V, int NV> struct LaneVec {
+  using E = typename ElemOf<V>::E;
+  static constexpr int C = ElemOf<V>::C;
+  struct raw {
+    E e[NV * C];
+  };
+  static __device__ __forceinline__ V get(const raw &r, int v) {
+    if constexpr (C == 1) {
+      return r.e[v];
+    } else {
+      return V{r.e[2 * v], r.e[2 * v + 1]};
+    }
+  }
 };
 
 // The level-vector form exists for this element type and width: NV levels
-// make one access of at most 16 bytes (one level per lane only for the
-// 16-byte FP64 vector elements).
+// of at most 32 bytes per lane.
 template <class T, int OP, int NV>
 constexpr bool lane_vec_ok() {
-  return NV * sizeof(typename Pol<T, OP>::V) <= 16 &&
-         (NV > 1 || sizeof(typename Pol<T, OP>::V) == 16);
+  return NV >= 1 && NV <= 4 && NV * sizeof(typename Pol<T, OP>::V) <= 32;
 }
+
+// Incidences every row of a mesh has besides its pole edge (the octahedral
+// meshes: at least 4); below it the level-vector kernels need no select.
+constexpr int kMinRow = 4;
 
 // One node (rows of at most 6 incidences, one load group), NCH chunks of
 // 64 lanes x NV levels.
@@ -642,6 +682,14 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
 #pragma unroll
   for (int j = 0; j < G; ++j) {
     const bool pole = (nb[j] & kPoleBit) != 0;
+    if (j < kMinRow) {  // present in every row, never the pole edge
+      closure_add<P::kOp>(cx, cy, S[j], false);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P::add(st[c][v], LV::get(xn[j][c], v), S[j], false, cn[j]);
+      continue;
+    }
     const bool use = j < n && !(P::kVecIn && pole);
     double tx = cx, ty = cy;
     closure_add<P::kOp>(tx, ty, S[j], pole);
@@ -671,18 +719,7 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
       __builtin_memcpy(&w[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
     }
     const int ob = off[c] == kBufOff ? kBufOff : s[c] * (int)sizeof(Out);
-#pragma unroll
-    for (int k = 0; k < W; k += 4) {
-      if constexpr (W - 0 >= 4) {
-        if (k + 4 <= W) buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, ro, ob + 4 * k, 0, kStoreAux);
-      }
-    }
-    if constexpr (W % 4 == 2) buf_store8(i32x2{w[W - 2], w[W - 1]}, ro, ob + 4 * (W - 2), 0, kStoreAux);
-    if constexpr (W % 4 == 1) buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
-    if constexpr (W % 4 == 3) {
-      buf_store8(i32x2{w[W - 3], w[W - 2]}, ro, ob + 4 * (W - 3), 0, kStoreAux);
-      buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
-    }
+    buf_store_words<W>(w, ro, ob);
   }
 }
 
@@ -723,17 +760,32 @@ __global__ void __launch_bounds__(512)
   }
 }
 
-// Levels per lane of the level-vector form for (T, OP, nlev): as many as
-// fill 16 bytes (FP64 scalar 2, FP32 scalar 4, FP32 vector 2, FP64 vector
-// 1), or `want` if smaller; 0 when the form does not apply (mesh degree
-// above 6, a column shorter than one lane vector or longer than 256 of them)
-// and the one-level-per-lane column kernel runs instead.
+// Levels per lane of the level-vector form for (T, OP, nlev): the width
+// (1..4 levels, at most 32 bytes per lane) that needs the fewest level slots
+// per lane (NV x chunks of 64 lanes) -- the arithmetic runs once per slot --
+// then the fewest load instructions per column; `want` > 0 forces a width.
+// 0 when the form does not apply (mesh degree above 6 or a row shorter than
+// kMinRow, no width fitting the column, more than 4 chunks) and the
+// one-level-per-lane column kernel runs instead.
 template <class T, int OP>
-__host__ __device__ inline int auto_level_vec(int nlev, int maxdeg, int want = 4) {
-  const int nv = min(want, (int)(16 / sizeof(typename Pol<T, OP>::V)));
-  if (maxdeg > 6 || nlev < nv) return 0;
-  if ((nlev + 64 * nv - 1) / (64 * nv) > 4) return 0;
-  return nv;
+__host__ __device__ inline int auto_level_vec(int nlev, int maxdeg, int mindeg, int want = 0) {
+  if (maxdeg > 6 || mindeg < kMinRow) return 0;
+  const int vb = (int)sizeof(typename Pol<T, OP>::V);
+  int best = 0, best_slots = 1 << 30, best_loads = 1 << 30;
+  for (int nv = 1; nv <= 4; ++nv) {
+    if (nv * vb > 32 || nlev < nv || (want > 0 && nv != want)) continue;
+    const int nch = ((nlev + nv - 1) / nv + 63) / 64;
+    if (nch > 4) continue;
+    const int bytes = nv * vb;
+    const int pieces = bytes / 16 + ((bytes % 16) ? 1 : 0);  // 16/12/8/4-byte accesses
+    const int slots = nv * nch, loads = nch * pieces;
+    if (slots < best_slots || (slots == best_slots && loads < best_loads)) {
+      best = nv;
+      best_slots = slots;
+      best_loads = loads;
+    }
+  }
+  return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -915,36 +967,37 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
   auto run_lo = [&](int q) { return cst(segp)[2 * (s0 + q)]; };
   auto run_hi = [&](int q) { return cst(segp)[2 * (s0 + q) + 1]; };
 
-  // ---- columns: item = (node t of the segment, lane vector k)
+  // ---- columns: item = (node t of the segment, lane vector k); a thread's
+  // items are the same every step (computed once)
   R regs[EPT];
+  int it_t[EPT], it_off[EPT], it_lds[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = threadIdx.x + e * (int)blockDim.x;
+    const int t = i / nvc, k = i - t * nvc;
+    it_t[e] = t;
+    it_off[e] = first(k) * (int)sizeof(V);
+    it_lds[e] = t * vpc + k;
+  }
   int seg_len = 0;
   auto fetch = [&](int q) {
     const int rb = cst(segi)[4 * (s0 + q)], nx = cst(segi)[4 * (s0 + q) + 1];
     const int lo = cst(segi)[4 * (s0 + q) + 2];
     seg_len = cst(segi)[4 * (s0 + q) + 3];
     const i32x4 rs = make_rsrc(vin + (size_t)rb * L, (uint32_t)nx * col_bytes);
-    const int items = seg_len * nvc;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int i = threadIdx.x + e * (int)blockDim.x;
-      const int t = i / nvc, k = i - t * nvc;
-      int ii = lo + t;
+      int ii = lo + it_t[e];
       if (ii >= nx) ii -= nx;
-      const int off = i < items ? ii * (int)col_bytes + first(k) * (int)sizeof(V) : kBufOff;
+      const int off = it_t[e] < seg_len ? ii * (int)col_bytes + it_off[e] : kBufOff;
       regs[e] = buf_load<R>(rs, off);
     }
   };
   auto deposit = [&](int q) {
     R *b = buf + (q & 3) * slot_stride;
-    const int items = seg_len * nvc;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int i = threadIdx.x + e * (int)blockDim.x;
-      if (i < items) {
-        const int t = i / nvc, k = i - t * nvc;
-        b[t * vpc + k] = regs[e];
-      }
-    }
+    for (int e = 0; e < EPT; ++e)
+      if (it_t[e] < seg_len) b[it_lds[e]] = regs[e];
   };
   // ---- position records of run q (2 words each) and rows of run q (WPP
   // words each, at the record's first incidence); a thread moves at most one
@@ -1076,6 +1129,12 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
 #pragma unroll
       for (int j = 0; j < G; ++j) {
         const bool pole = (lr[j] & kLrefPole) != 0;
+        if (j < kMinRow) {  // present in every row, never the pole edge
+          closure_add<P::kOp>(cx, cy, S[j], false);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) P::add(st[v], LV::get(xn[j], v), S[j], false, cn[j]);
+          continue;
+        }
         const bool use = j < n && !(P::kVecIn && pole);
         double tx = cx, ty = cy;
         closure_add<P::kOp>(tx, ty, S[j], pole);
@@ -1098,15 +1157,7 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
         __builtin_memcpy(&w[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
       }
       const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
-#pragma unroll
-      for (int k = 0; k + 4 <= W; k += 4)
-        buf_store16(i32x4{w[k], w[k + 1], w[k + 2], w[k + 3]}, ro, ob + 4 * k, 0, kStoreAux);
-      if constexpr (W % 4 == 2) buf_store8(i32x2{w[W - 2], w[W - 1]}, ro, ob + 4 * (W - 2), 0, kStoreAux);
-      if constexpr (W % 4 == 1) buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
-      if constexpr (W % 4 == 3) {
-        buf_store8(i32x2{w[W - 3], w[W - 2]}, ro, ob + 4 * (W - 3), 0, kStoreAux);
-        buf_store4(w[W - 1], ro, ob + 4 * (W - 1), 0, kStoreAux);
-      }
+      buf_store_words<W>(w, ro, ob);
     }
     if (pf) {
       deposit(q + 2);
@@ -1286,20 +1337,23 @@ __device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, const 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (form == FORM_COLUMN) {
-    const int nv = auto_level_vec<T, OP>(nlev, m.maxdeg);
+    const int nv = auto_level_vec<T, OP>(nlev, m.maxdeg, m.mindeg);
     const int nch = (nlev + 63) / 64;
     if (nv > 0) {
+      // batch items use the 16-byte width (fewer kernel variants per batch)
       constexpr int NV = (int)(16 / sizeof(typename Pol<T, OP>::V));
       const int nchv = (nlev + 64 * NV - 1) / (64 * NV);
       if constexpr (lane_vec_ok<T, OP, NV>()) {
-        for (int p = p0 + wave; p < p1; p += nw) {
-          const PosRec pr = m.pos[p];
-          if (nchv == 1) colv_node<T, OP, NV, 1>(m, in, out, nlev, pr, lane);
-          else if (nchv == 2) colv_node<T, OP, NV, 2>(m, in, out, nlev, pr, lane);
-          else if (nchv == 3) colv_node<T, OP, NV, 3>(m, in, out, nlev, pr, lane);
-          else colv_node<T, OP, NV, 4>(m, in, out, nlev, pr, lane);
+        if (nlev >= NV && nchv <= 4) {
+          for (int p = p0 + wave; p < p1; p += nw) {
+            const PosRec pr = m.pos[p];
+            if (nchv == 1) colv_node<T, OP, NV, 1>(m, in, out, nlev, pr, lane);
+            else if (nchv == 2) colv_node<T, OP, NV, 2>(m, in, out, nlev, pr, lane);
+            else if (nchv == 3) colv_node<T, OP, NV, 3>(m, in, out, nlev, pr, lane);
+            else colv_node<T, OP, NV, 4>(m, in, out, nlev, pr, lane);
+          }
+          return;
         }
-        return;
       }
     }
     for (int p = p0 + wave; p < p1; p += nw) {
@@ -1525,11 +1579,11 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       const dim3 cgrid = cyc > 0 ? dim3(8 * cyc) : grid;
       // level_vec: 0 = widest lane vector, 2 / 4 = at most that many levels
       // per lane, 1 = the one-level-per-lane kernel
-      if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
-        return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
+      if (sh.level_vec < 0 || sh.level_vec > 4)
+        return fail(ATLAS_EINVAL, "level_vec must be in [0, 4]");
       const int nv = sh.level_vec == 1 ? 0
-                                       : auto_level_vec<T, OP>(nlev, m.maxdeg,
-                                                               sh.level_vec ? sh.level_vec : 4);
+                                       : auto_level_vec<T, OP>(nlev, m.maxdeg, m.mindeg,
+                                                               sh.level_vec);
       if (nv > 0) {
         const int nchv = (nlev + 64 * nv - 1) / (64 * nv);
         void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
@@ -1544,6 +1598,8 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
           ATLASX_COLV(1)
         } else if (nv == 2) {
           ATLASX_COLV(2)
+        } else if (nv == 3) {
+          ATLASX_COLV(3)
         } else {
           ATLASX_COLV(4)
         }
@@ -1591,14 +1647,13 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         return fail(ATLAS_EINVAL, "the sweep form runs on the mesh's tiles (nodes_per_block = 0)");
       // the chunk shrinks until a parallel's run fits the staging registers
       // (16 elements per thread) and four runs fit in LDS
-      if (sh.level_vec != 0 && sh.level_vec != 1 && sh.level_vec != 2 && sh.level_vec != 4)
-        return fail(ATLAS_EINVAL, "level_vec must be 0, 1, 2 or 4");
+      if (sh.level_vec < 0 || sh.level_vec > 4)
+        return fail(ATLAS_EINVAL, "level_vec must be in [0, 4]");
       // the level-vector sweep stages each position's geometry with one
       // thread per 16-byte word: it needs a block of segmax * kGeoWords
       // threads, else the one-level-per-lane sweep runs (same results)
       int nv = sh.level_vec == 1 ? 0
-                                 : auto_level_vec<T, OP>(nlev, m.maxdeg,
-                                                         sh.level_vec ? sh.level_vec : 4);
+                                 : auto_level_vec<T, OP>(nlev, m.maxdeg, m.mindeg, sh.level_vec);
       if (sh.block < max(1, m.segmax) * kGeoWords) nv = 0;
       if (nv > 0) {
         // level chunk: vpc lane vectors per workgroup pass, at most 64, split
@@ -1612,19 +1667,20 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
           vpc = (nvec + nchunk - 1) / nchunk;
         }
         const size_t seg = (size_t)max(1, m.segmax);
+        const size_t rb = (size_t)nv * sizeof(typename Pol<T, OP>::V);  // lane-vector bytes
         // geometry staged per run: 2 record words and up to kGeoWords row
         // words per position, one of each kind per thread
         const size_t geo = 4 * seg * (2 + kGeoWords) * 16;
         const size_t budget = sh.block > 512 ? kMaxLds : kMaxLds / 2;
         // (staging: at most kSweepEpt lane vectors per thread and run)
-        while (vpc > 1 && (4 * seg * vpc * 16 + geo > budget ||
+        while (vpc > 1 && (4 * seg * vpc * rb + geo > budget ||
                            (int)((seg * vpc + sh.block - 1) / sh.block) > kSweepEpt))
           vpc = (vpc + 1) / 2;
         const int ept = (int)((seg * vpc + sh.block - 1) / sh.block);
-        if (4 * seg * vpc * 16 + geo > kMaxLds || ept > kSweepEpt)
+        if (4 * seg * vpc * rb + geo > kMaxLds || ept > kSweepEpt)
           return fail(ATLAS_EINVAL, "sweep tile too large for LDS or the block size");
         const int nchunk = (nvec + vpc - 1) / vpc;
-        const size_t lds = 4 * seg * vpc * 16 + geo;
+        const size_t lds = 4 * seg * vpc * rb + geo;
         const int units = m.ntiles * nchunk;
         const int per = (units + 7) / 8;
         void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
@@ -1634,6 +1690,8 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
           ATLASX_SWV(1)
         } else if (nv == 2) {
           ATLASX_SWV(2)
+        } else if (nv == 3) {
+          ATLASX_SWV(3)
         } else {
           ATLASX_SWV(4)
         }

@@ -96,6 +96,7 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
     for block in (64, 256, 512, 1024):
         for kc in (0, 1, 5, 32):
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))      # lane vectors
+            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 3))
             if block <= 512:
                 shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 1))  # one level per lane
     for kc in (1, 7, 64):
@@ -104,7 +105,7 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
         for bpc in (1, 3, 8):
             shapes.append(P.Launch(P.VARIANT_COLUMN, block, 0, 0, bpc))
     # levels per lane: one, or lane vectors of 2 / 4 levels (capped at 16 B)
-    for lv in (1, 2, 4):
+    for lv in (1, 2, 3, 4):
         shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 0, lv))
         shapes.append(P.Launch(P.VARIANT_COLUMN, 64, 7, 0, 0, lv))
         shapes.append(P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 3, lv))
@@ -191,9 +192,9 @@ def test_invalid_arguments_enqueue_nothing(P):
     # unknown dtype
     assert L.atlas_nabla_gradient(gm.handle, ctypes.c_void_p(x.data_ptr()), 3, 7,
                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s)) == -1
-    # levels per lane other than 0, 1, 2, 4
+    # levels per lane outside [0, 4]
     with pytest.raises(P.AtlasError):
-        gm.apply(P.ATLAS_OP_GRADIENT, x, out=out, launch=P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 0, 3))
+        gm.apply(P.ATLAS_OP_GRADIENT, x, out=out, launch=P.Launch(P.VARIANT_COLUMN, 256, 0, 0, 0, 5))
     torch.cuda.synchronize()
     assert torch.all(out == 7.0), "a rejected call must not write anything"
     with pytest.raises(ValueError):
