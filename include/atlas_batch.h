@@ -77,7 +77,11 @@ atlas_status atlas_batch_free(atlas_batch_t batch);
 /* Autotuner for the single operators: times the candidate launch shapes
  * (column / flat / sweep forms, block sizes, tile sizes) for this
  * (mesh, op, dtype, nlev) on the given buffers, remembers the fastest in
- * the mesh (later calls with the same key use it) and returns it.
+ * the mesh (later calls with the same key use it) and returns it.  The
+ * Laplacian is tuned pass by pass (gradient into `workspace`, or an
+ * internal one when NULL, then its divergence into `out`): later Laplacian
+ * calls run each pass with its own tuned shape; *best is the gradient
+ * pass's shape, *best_ms the sum of both passes.
  * Errors: as atlas_nabla_apply. */
 atlas_status atlas_autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
                             atlas_dtype dtype, void *out, void *workspace,

@@ -113,30 +113,33 @@ static float time_shape(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev
 
 static std::vector<atlas_launch> candidates(const MeshStore &m, int nlev) {
   std::vector<atlas_launch> c;
-  auto add = [&](int v, int b, int npb, int kc, int bpc) { c.push_back({v, b, npb, kc, bpc}); };
+  auto add = [&](int v, int b, int npb, int kc, int bpc, int lv) {
+    c.push_back({v, b, npb, kc, bpc, lv});
+  };
   if (nlev >= 32) {
-    add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 0);
-    add(ATLAS_VARIANT_COLUMN, 256, 4, 0, 0);
-    add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0);
-    add(ATLAS_VARIANT_COLUMN, 128, 0, 0, 0);
-    add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 4);
+    for (int lv : {0, 1, 2, 3}) add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0, lv);
+    add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 128, 16, 0, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 256, 4, 0, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 4, 0);
     if (m.d.sweep_ok) {
-      add(ATLAS_VARIANT_SWEEP, 256, 0, 0, 0);
-      add(ATLAS_VARIANT_SWEEP, 512, 0, 0, 0);
+      for (int b : {512, 768, 1024}) add(ATLAS_VARIANT_SWEEP, b, 0, 0, 0, 0);
+      add(ATLAS_VARIANT_SWEEP, 768, 0, 0, 0, 2);
     }
   }
   const int fl = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));
-  add(ATLAS_VARIANT_FLAT, 256, fl, 0, 0);
-  add(ATLAS_VARIANT_FLAT, 256, std::max(1, fl / 4), 0, 0);
-  add(ATLAS_VARIANT_FLAT, 256, 0, 0, 0);
-  if (nlev < 32) add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 256, fl, 0, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 256, std::max(1, fl / 4), 0, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 256, 0, 0, 0, 0);
+  if (nlev < 32) add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0, 0);
   return c;
 }
 
-atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, atlas_dtype dt,
-                      void *out, void *ws, hipStream_t st, atlas_launch *best, float *best_ms) {
-  atlas_status s = check_call(mesh, op, in, nlev, dt, out);
-  if (s != ATLAS_OK) return s;
+// Times every candidate for one operator on the given buffers and remembers
+// the fastest in the mesh.
+static atlas_status tune_one(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
+                             atlas_dtype dt, void *out, hipStream_t st, atlas_launch *best,
+                             float *best_ms) {
   MeshStore &m = *mesh->store;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ATLASX_HIP(hipEventCreate(&e0));
@@ -147,7 +150,7 @@ atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, 
   float bt = 1e30f;
   atlas_launch bl{};
   for (const atlas_launch &c : candidates(m, nlev)) {
-    const float t = time_shape(mesh, op, in, nlev, dt, out, ws, c, st, e0, e1);
+    const float t = time_shape(mesh, op, in, nlev, dt, out, nullptr, c, st, e0, e1);
     if (t >= 0.0f && t < bt) {
       bt = t;
       bl = c;
@@ -164,8 +167,42 @@ atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, 
     sh.nodes_per_block = bl.nodes_per_block;
     sh.level_chunk = bl.level_chunk;
     sh.blocks_per_cu = bl.blocks_per_cu;
+    sh.level_vec = bl.level_vec;
     m.tuned[TuneKey{(int)op, (int)dt, nlev}] = sh;
   }
+  *best = bl;
+  *best_ms = bt;
+  return ATLAS_OK;
+}
+
+// The Laplacian is tuned pass by pass (gradient into the workspace, then
+// its divergence); it then runs each pass with that pass's tuned shape.
+atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, atlas_dtype dt,
+                      void *out, void *ws, hipStream_t st, atlas_launch *best, float *best_ms) {
+  atlas_status s = check_call(mesh, op, in, nlev, dt, out);
+  if (s != ATLAS_OK) return s;
+  atlas_launch bl{};
+  float bt = 0.0f;
+  if (op != ATLAS_OP_LAPLACIAN) {
+    s = tune_one(mesh, op, in, nlev, dt, out, st, &bl, &bt);
+  } else {
+    const size_t bytes = (size_t)mesh->store->d.V * nlev * 2 * (dt == ATLAS_F64 ? 8 : 4);
+    void *grad = ws, *owned = nullptr;
+    if (!grad) {
+      if (hipMalloc(&owned, bytes) != hipSuccess) return fail(ATLAS_ENOMEM, "autotune workspace");
+      grad = owned;
+    }
+    atlas_launch bd{};
+    float td = 0.0f;
+    s = tune_one(mesh, ATLAS_OP_GRADIENT, in, nlev, dt, grad, st, &bl, &bt);
+    if (s == ATLAS_OK) s = tune_one(mesh, ATLAS_OP_DIVERGENCE, grad, nlev, dt, out, st, &bd, &td);
+    bt += td;
+    if (owned) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(owned);
+    }
+  }
+  if (s != ATLAS_OK) return s;
   if (best) *best = bl;
   if (best_ms) *best_ms = bt;
   return ATLAS_OK;
@@ -188,7 +225,7 @@ static ItemShape tuned_item_shape(atlas_mesh_t mesh, atlas_op op, const void *in
                              {FORM_FLAT, std::max(1, fl / 4)}};
   for (const ItemShape &c : cands) {
     const atlas_launch l{c.form == FORM_COLUMN ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT, 256,
-                         c.npb, 0, 0};
+                         c.npb, 0, 0, 0};
     const float t = time_shape(mesh, op, in, nlev, dt, out, ws, l, st, e0, e1);
     if (t >= 0.0f && t < bt) {
       bt = t;

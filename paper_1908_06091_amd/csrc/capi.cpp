@@ -292,16 +292,16 @@ namespace atlasx {
 LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
                        atlas_dtype dt) {
   LaunchShape s = default_shape(m, op, nlev, dt);
-  if (!l || l->variant == ATLAS_VARIANT_AUTO) {
+  if ((!l || l->variant == ATLAS_VARIANT_AUTO) && op != ATLAS_OP_LAPLACIAN) {
     // an autotuned shape for this (op, dtype, nlev), if any (the Laplacian
-    // runs its two passes with the gradient's shape)
+    // takes each pass's own shape, tuned or built in)
     MeshStore &ms = const_cast<MeshStore &>(m);
     std::lock_guard<std::mutex> g(ms.tune_mu);
-    const int key_op = op == ATLAS_OP_LAPLACIAN ? (int)ATLAS_OP_GRADIENT : (int)op;
-    auto it = ms.tuned.find(TuneKey{key_op, (int)dt, nlev});
+    auto it = ms.tuned.find(TuneKey{(int)op, (int)dt, nlev});
     if (it != ms.tuned.end()) s = it->second;
   }
   if (l && l->variant != ATLAS_VARIANT_AUTO) {
+    s.per_pass = 0;  // an explicit shape serves both Laplacian passes
     s.variant = l->variant;
     s.block = l->block_threads;
     s.nodes_per_block = l->nodes_per_block;

@@ -102,6 +102,7 @@ struct LaunchShape {
   int level_chunk = 0;      // column form: levels per unit, 0 = all
   int blocks_per_cu = 0;    // > 0: persistent wave-cyclic grid
   int level_vec = 0;        // column form: levels per lane, 0 = auto
+  int per_pass = 0;         // Laplacian: each pass takes its built-in shape
 };
 
 // ------------------------------------------------------------- batches

@@ -760,17 +760,20 @@ __global__ void __launch_bounds__(512)
   }
 }
 
-// Levels per lane of the level-vector form for (T, OP, nlev): the width
-// (1..4 levels, at most 32 bytes per lane) that needs the fewest level slots
-// per lane (NV x chunks of 64 lanes) -- the arithmetic runs once per slot --
-// then the fewest load instructions per column; `want` > 0 forces a width.
-// 0 when the form does not apply (mesh degree above 6 or a row shorter than
-// kMinRow, no width fitting the column, more than 4 chunks) and the
-// one-level-per-lane column kernel runs instead.
+// Levels per lane of the level-vector form for (T, OP, nlev).  FP64 (bound
+// by memory traffic): 16-byte lanes.  FP32 (its compensated sums make the
+// arithmetic the larger cost): the width (1..4 levels, at most 32 bytes per
+// lane) that needs the fewest level slots per lane (NV x chunks of 64
+// lanes; the arithmetic runs once per slot), then the fewest load
+// instructions per column.  `want` > 0 forces a width.  0 when the form
+// does not apply (mesh degree above 6 or a row shorter than kMinRow, no
+// width fitting the column, more than 4 chunks) and the one-level-per-lane
+// column kernel runs instead.
 template <class T, int OP>
 __host__ __device__ inline int auto_level_vec(int nlev, int maxdeg, int mindeg, int want = 0) {
   if (maxdeg > 6 || mindeg < kMinRow) return 0;
   const int vb = (int)sizeof(typename Pol<T, OP>::V);
+  if (want == 0 && sizeof(T) == 8) want = 16 / vb;
   int best = 0, best_slots = 1 << 30, best_loads = 1 << 30;
   for (int nv = 1; nv <= 4; ++nv) {
     if (nv * vb > 32 || nlev < nv || (want > 0 && nv != want)) continue;
@@ -1503,29 +1506,31 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
   return slots * (size_t)nlev * w * (grad ? 2 : 1);
 }
 
-// Built-in shape (the autotuner can replace it per mesh and class).  Long
-// columns: the column form over blocks of 16 consecutive positions (a run of
-// one parallel, so the neighbour columns of consecutive blocks overlap in
-// L2) -- the level-vector sweep for the FP64 gradient --, lane vectors
-// except for the FP32 gradient, whose compensated sums
-// make it arithmetic-bound: there one level per lane keeps more lanes busy
-// (the Laplacian's two passes share one shape; its divergence pass gains
-// more from lane vectors than its gradient pass loses).
-// Short columns: the flat form over the mesh's tiles.
+// Built-in shape (the autotuner can replace it per mesh and class), from
+// measurements at O1280, 137 levels.  Long columns: the column form over
+// blocks of 16 consecutive positions (a run of one parallel, so the
+// neighbour columns of consecutive blocks overlap in L2) with the automatic
+// lane-vector width, except: the FP64 gradient runs the level-vector sweep
+// (768 threads), the FP32 gradient one level per lane (its compensated sums
+// keep every lane busy that way).  The Laplacian takes each pass's own
+// shape.  Short columns: the flat form over the mesh's tiles.
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   LaunchShape s;
   s.variant = nlev >= 48 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
   s.block = 256;
   s.nodes_per_block = s.variant == ATLAS_VARIANT_COLUMN ? 16 : 0;
-  s.level_vec = (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) ? 1 : 0;
-  // FP64 gradient of long columns: the level-vector sweep with 12
-  // wavefronts per workgroup, where the mesh has a sweep plan
-  if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && nlev >= 48 && m.d.sweep_ok &&
+  s.level_vec = 0;
+  if (op == ATLAS_OP_LAPLACIAN) {
+    s.per_pass = 1;
+    return s;
+  }
+  if (nlev < 48) return s;
+  if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) s.level_vec = 1;
+  if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && m.d.sweep_ok &&
       max(1, m.d.segmax) * kGeoWords <= 768) {
     s.variant = ATLAS_VARIANT_SWEEP;
     s.block = 768;
     s.nodes_per_block = 0;
-    s.level_vec = 0;
   }
   return s;
 }
@@ -1745,6 +1750,15 @@ static atlas_status launch_dtype(const MeshStore &ms, atlas_op op, const void *i
   }
 }
 
+// Shape of one Laplacian pass: the autotuned one for that operator, else the
+// built-in one.
+static LaunchShape pass_shape(const MeshStore &ms, atlas_op op, int nlev, atlas_dtype dt) {
+  MeshStore &m = const_cast<MeshStore &>(ms);
+  std::lock_guard<std::mutex> g(m.tune_mu);
+  auto it = m.tuned.find(TuneKey{(int)op, (int)dt, nlev});
+  return it != m.tuned.end() ? it->second : default_shape(ms, op, nlev, dt);
+}
+
 // Laplacian: gradient into the workspace [V][nlev][2], then its divergence;
 // the flux form needs its flux buffer behind the gradient.
 atlas_status launch_op(const MeshStore &ms, atlas_op op, atlas_dtype dt, const void *in,
@@ -1753,9 +1767,11 @@ atlas_status launch_op(const MeshStore &ms, atlas_op op, atlas_dtype dt, const v
     const size_t w = dt == ATLAS_F64 ? 8 : 4;
     char *grad = static_cast<char *>(ws);
     void *flux = grad + (size_t)ms.d.V * nlev * 2 * w;
-    atlas_status s = launch_op(ms, ATLAS_OP_GRADIENT, dt, in, nlev, grad, flux, sh, st);
+    const LaunchShape sg = sh.per_pass ? pass_shape(ms, ATLAS_OP_GRADIENT, nlev, dt) : sh;
+    const LaunchShape sd = sh.per_pass ? pass_shape(ms, ATLAS_OP_DIVERGENCE, nlev, dt) : sh;
+    atlas_status s = launch_op(ms, ATLAS_OP_GRADIENT, dt, in, nlev, grad, flux, sg, st);
     if (s != ATLAS_OK) return s;
-    return launch_op(ms, ATLAS_OP_DIVERGENCE, dt, grad, nlev, out, flux, sh, st);
+    return launch_op(ms, ATLAS_OP_DIVERGENCE, dt, grad, nlev, out, flux, sd, st);
   }
   if (dt == ATLAS_F64) return launch_dtype<double>(ms, op, in, nlev, out, ws, sh, st);
   return launch_dtype<float>(ms, op, in, nlev, out, ws, sh, st);

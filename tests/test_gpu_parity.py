@@ -224,3 +224,26 @@ def test_mesh_upload_from_description(P):
     bad["node2edge_sign"] = -bad["node2edge_sign"]
     with pytest.raises(P.AtlasError):
         P.Mesh(desc=bad)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("op", OPS)
+def test_autotune_keeps_results(P, op, dtype):
+    """The autotuner times the candidate shapes, remembers the fastest in the
+    mesh, and later calls with that shape give the same bits as before."""
+    N, nlev = 24, 137
+    gm = P.Mesh(N)
+    rng = np.random.default_rng(5)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    shape = (gm.nnodes, nlev, 2) if op in ("div", "curl") else (gm.nnodes, nlev)
+    x = torch.from_numpy(rng.standard_normal(shape)).to(dtype=tdt, device="cuda")
+    before = _run(P, gm, op, x).clone()
+    out = torch.empty_like(before)
+    code = {"grad": P.ATLAS_OP_GRADIENT, "div": P.ATLAS_OP_DIVERGENCE,
+            "curl": P.ATLAS_OP_CURL, "lapl": P.ATLAS_OP_LAPLACIAN}[op]
+    best, ms = P.autotune(gm, code, x, out)
+    assert ms > 0 and best.variant in (P.VARIANT_COLUMN, P.VARIANT_FLAT, P.VARIANT_SWEEP)
+    after = _run(P, gm, op, x)
+    torch.cuda.synchronize()
+    assert torch.equal(after, before)
+    assert torch.equal(out, before)
