@@ -13,7 +13,10 @@
  * Footprint of a request while in the server: its input, its output and, for
  * the Laplacian, its [V][nlev][2] workspace.  A request whose footprint alone
  * exceeds the budget is rejected at submit with ATLAS_ENOMEM.  A server-owned
- * output stays in the footprint until atlas_serve_release.
+ * output stays in the footprint until atlas_serve_release.  Server-owned
+ * outputs and workspaces are ranges of one arena reserved at creation, so
+ * serving makes no device allocation; a request whose ranges do not fit the
+ * arena yet waits at the head of the queue, as one over the budget does.
  *
  * Ordering: the server launches on streams of its own that do not wait for
  * any other stream.  A request's input and caller-owned output must be ready
@@ -36,7 +39,10 @@ extern "C" {
 typedef struct atlas_server_s *atlas_server_t;
 
 typedef struct {
-  size_t hbm_budget_bytes;  /* bound on the summed footprint in flight      */
+  size_t hbm_budget_bytes;  /* bound on the summed footprint in flight; a
+                               device server reserves this much device memory
+                               at creation as the arena its outputs and
+                               workspaces are carved from                    */
   int32_t nstreams;         /* launch slots (1..16)                          */
   int32_t max_batch;        /* most requests merged into one launch (>= 1)   */
   int64_t batch_max_elems;  /* requests with nnodes*nlev above this launch
@@ -76,6 +82,10 @@ typedef struct {
   size_t inflight_bytes, peak_inflight_bytes;
 } atlas_serve_stats;
 
+/* Starts a server on the current device (a simulation server touches no
+ * device).  Errors: ATLAS_EINVAL (a config field out of range), ATLAS_ENOMEM
+ * (the budget's arena or the batch tables cannot be allocated),
+ * ATLAS_EDEVICE. */
 atlas_status atlas_serve_create(const atlas_serve_config *cfg, atlas_server_t *out);
 
 /* Make a resident mesh known to the server (the server keeps it from being
@@ -112,7 +122,10 @@ atlas_status atlas_serve_release(atlas_server_t srv, uint64_t ticket);
 
 atlas_status atlas_serve_get_stats(atlas_server_t srv, atlas_serve_stats *st);
 
-/* Drain every admitted request, stop the scheduler, free server memory. */
+/* Drain every admitted request, cancel queued ones that cannot be admitted
+ * any more (their footprint waits for releases), stop the scheduler, free
+ * server memory (the arena included: server-owned outputs not yet released
+ * become invalid). */
 atlas_status atlas_serve_destroy(atlas_server_t srv);
 
 #ifdef __cplusplus

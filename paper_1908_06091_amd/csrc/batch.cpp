@@ -24,10 +24,12 @@ atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
                    atlas_dtype dt, void *out, void *workspace, const atlas_launch *shape,
                    hipStream_t stream);
 
-ItemShape heuristic_shape(int nlev) {
-  if (nlev >= 48) return {FORM_COLUMN, 16};
+// Untuned batch shape of an item (op: the OP code of its first pass); the
+// column form's lane width follows the single-launch default.
+ItemShape heuristic_shape(int op, atlas_dtype dt, int nlev) {
+  if (nlev >= 48) return {FORM_COLUMN, 16, (dt == ATLAS_F32 && op == 0) ? 1 : 0};
   const int npb = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));
-  return {FORM_FLAT, npb};
+  return {FORM_FLAT, npb, 0};
 }
 
 // Units of a batch: every item's nodes in blocks of its npb, each item's
@@ -209,11 +211,13 @@ atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, 
 }
 
 // The form a batch uses for an item class after autotuning: the fastest of
-// the column / flat candidates with their tile sizes.
+// the column / flat candidates with their tile sizes and, for the column
+// form, the automatic lane width or one level per lane.
 static ItemShape tuned_item_shape(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
                                   atlas_dtype dt, void *out, void *ws, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ItemShape best = heuristic_shape(nlev);
+  const int opc = op == ATLAS_OP_DIVERGENCE ? 1 : op == ATLAS_OP_CURL ? 2 : 0;
+  ItemShape best = heuristic_shape(opc, dt, nlev);
   if (hipEventCreate(&e0) != hipSuccess) return best;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
@@ -221,11 +225,12 @@ static ItemShape tuned_item_shape(atlas_mesh_t mesh, atlas_op op, const void *in
   }
   float bt = 1e30f;
   const int fl = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));
-  const ItemShape cands[] = {{FORM_COLUMN, 8}, {FORM_COLUMN, 32}, {FORM_FLAT, fl},
-                             {FORM_FLAT, std::max(1, fl / 4)}};
+  const ItemShape cands[] = {{FORM_COLUMN, 8, 0},  {FORM_COLUMN, 32, 0},
+                             {FORM_COLUMN, 8, 1},  {FORM_COLUMN, 32, 1},
+                             {FORM_FLAT, fl, 0},   {FORM_FLAT, std::max(1, fl / 4), 0}};
   for (const ItemShape &c : cands) {
     const atlas_launch l{c.form == FORM_COLUMN ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT, 256,
-                         c.npb, 0, 0, 0};
+                         c.npb, 0, 0, c.level_vec};
     const float t = time_shape(mesh, op, in, nlev, dt, out, ws, l, st, e0, e1);
     if (t >= 0.0f && t < bt) {
       bt = t;
@@ -319,10 +324,11 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
       sh = c.autotune ? tuned_item_shape(it.mesh, (atlas_op)(bi.lapl ? ATLAS_OP_GRADIENT : it.op),
                                          it.in, it.nlev, dt, bi.lapl ? bi.ws : it.out, nullptr,
                                          stream)
-                      : heuristic_shape(it.nlev);
+                      : heuristic_shape(bi.lapl ? 0 : bi.op, dt, it.nlev);
       shapes[key] = sh;
     }
     bi.form = sh.form;
+    bi.level_vec = sh.level_vec;
     (sh.form == FORM_COLUMN ? b->form_column : b->form_flat) += 1;
     h_shapes[i] = sh;
     b->two_pass = b->two_pass || bi.lapl;

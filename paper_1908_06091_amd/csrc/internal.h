@@ -114,7 +114,9 @@ struct BatchItem {       // device table entry of a batch
   int32_t lapl;          // 1: gradient into ws (phase 0), divergence (phase 1)
   int32_t nlev;
   int32_t form;          // FORM_COLUMN / FORM_FLAT
-  int32_t pad[4];
+  int32_t level_vec;     // column form, phase 0: as atlas_launch::level_vec
+  int32_t level_vec1;    // column form, phase 1 (divergence of a Laplacian)
+  int32_t pad[2];
   const void *in;
   void *out;
   void *ws;
@@ -132,9 +134,9 @@ atlas_status launch_fill(int *p, int n, int value, hipStream_t st);
 
 // Tile shape of an item inside a batch: the form and positions per unit.
 struct ItemShape {
-  int form, npb;
+  int form, npb, level_vec;
 };
-ItemShape heuristic_shape(int nlev);
+ItemShape heuristic_shape(int op, atlas_dtype dt, int nlev);
 void plan_units(const std::vector<BatchItem> &items, const std::vector<ItemShape> &shapes,
                 std::vector<BatchUnit> &units, std::vector<int> &qbeg);
 

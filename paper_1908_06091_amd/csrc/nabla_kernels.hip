@@ -932,6 +932,8 @@ __global__ void __launch_bounds__(1024) k_sweep(DevMesh m, const T *__restrict__
 constexpr int kSweepEpt = 4;   // staged lane vectors per thread and run
 constexpr int kGeoWords = 11;  // 16-byte words of staged rows per position:
                                // S[6] (6), lref[8] (2), ncos[6] (3)
+constexpr int kSweepMinTiles = 1024;  // tiles below which the default stays
+                                      // with the column form
 
 template <class T, int OP, int NV, int EPT>
 __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict__ in,
@@ -1333,32 +1335,54 @@ __global__ void __launch_bounds__(1024) k_gather_flux(DevMesh m, const T *__rest
 // from its queue until the queue is drained, then exits.  heads[x] is queue
 // x's next unit.
 // ---------------------------------------------------------------------------
+// Lane vectors wider than 16 bytes: the batch kernel takes them one per
+// lane only (two would not fit its register budget).
+template <class T, int OP, int NV>
+__host__ __device__ constexpr bool batch_wide() {
+  return NV * sizeof(typename Pol<T, OP>::V) > 16;
+}
+
+// Column-form positions p0 + wave, p0 + wave + nw, ... below p1 with lane
+// vectors of NV levels and nchv (1 or 2; 1 if wide) vectors per lane; false
+// if that width does not exist for this dtype and operator.
+template <class T, int OP, int NV>
+__device__ __forceinline__ bool batch_colv(const DevMesh &m, const T *in, T *out, int nlev,
+                                           int nchv, int p0, int p1, int wave, int nw, int lane) {
+  if constexpr (lane_vec_ok<T, OP, NV>()) {
+    for (int p = p0 + wave; p < p1; p += nw) {
+      const PosRec pr = m.pos[p];
+      if (batch_wide<T, OP, NV>() || nchv == 1) colv_node<T, OP, NV, 1>(m, in, out, nlev, pr, lane);
+      else colv_node<T, OP, NV, 2>(m, in, out, nlev, pr, lane);
+    }
+    return true;
+  }
+  return false;
+}
+
 template <class T, int OP>
-__device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, const T *in, T *out,
-                                              int nlev, int p0, int p1) {
+__device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, int level_vec,
+                                              const T *in, T *out, int nlev, int p0, int p1) {
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (form == FORM_COLUMN) {
-    const int nv = auto_level_vec<T, OP>(nlev, m.maxdeg, m.mindeg);
-    const int nch = (nlev + 63) / 64;
+    // lane vectors as in the single-launch column form, up to two per lane
+    // (one if wider than 16 bytes: the batch kernel's registers are sized
+    // for that); wider columns and level_vec 1 take one level per lane
+    const int nv = level_vec == 1 ? 0 : auto_level_vec<T, OP>(nlev, m.maxdeg, m.mindeg, level_vec);
     if (nv > 0) {
-      // batch items use the 16-byte width (fewer kernel variants per batch)
-      constexpr int NV = (int)(16 / sizeof(typename Pol<T, OP>::V));
-      const int nchv = (nlev + 64 * NV - 1) / (64 * NV);
-      if constexpr (lane_vec_ok<T, OP, NV>()) {
-        if (nlev >= NV && nchv <= 4) {
-          for (int p = p0 + wave; p < p1; p += nw) {
-            const PosRec pr = m.pos[p];
-            if (nchv == 1) colv_node<T, OP, NV, 1>(m, in, out, nlev, pr, lane);
-            else if (nchv == 2) colv_node<T, OP, NV, 2>(m, in, out, nlev, pr, lane);
-            else if (nchv == 3) colv_node<T, OP, NV, 3>(m, in, out, nlev, pr, lane);
-            else colv_node<T, OP, NV, 4>(m, in, out, nlev, pr, lane);
-          }
-          return;
-        }
+      const int nchv = ((nlev + nv - 1) / nv + 63) / 64;
+      const bool wide = nv * (int)sizeof(typename Pol<T, OP>::V) > 16;
+      bool done = false;
+      if (nchv <= (wide ? 1 : 2)) {
+        if (nv == 1) done = batch_colv<T, OP, 1>(m, in, out, nlev, nchv, p0, p1, wave, nw, lane);
+        else if (nv == 2) done = batch_colv<T, OP, 2>(m, in, out, nlev, nchv, p0, p1, wave, nw, lane);
+        else if (nv == 3) done = batch_colv<T, OP, 3>(m, in, out, nlev, nchv, p0, p1, wave, nw, lane);
+        else done = batch_colv<T, OP, 4>(m, in, out, nlev, nchv, p0, p1, wave, nw, lane);
       }
+      if (done) return;
     }
+    const int nch = (nlev + 63) / 64;
     for (int p = p0 + wave; p < p1; p += nw) {
       const PosRec pr = m.pos[p];
       if (m.maxdeg <= 6 && nch == 1) column_node<T, OP, 1, 6, true>(m, in, out, nlev, pr, lane);
@@ -1378,8 +1402,13 @@ __device__ __forceinline__ void batch_unit_op(const DevMesh &m, int form, const 
   }
 }
 
+// waves per SIMD the batch kernel is compiled for (FP64: three, so the
+// one-level-per-lane column paths keep their registers)
 template <class T>
-__global__ void __launch_bounds__(256) k_batch(const BatchItem *__restrict__ items,
+constexpr int batch_waves() { return sizeof(T) == 8 ? 3 : 4; }
+
+template <class T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves<T>()))) k_batch(const BatchItem *__restrict__ items,
                                                const BatchUnit *__restrict__ units,
                                                const int *__restrict__ qbeg, int *heads) {
   __shared__ int s_u;
@@ -1395,9 +1424,13 @@ __global__ void __launch_bounds__(256) k_batch(const BatchItem *__restrict__ ite
     const int op = it.lapl ? (un.phase ? OP_DIV : OP_GRAD) : it.op;
     const T *src = static_cast<const T *>(un.phase ? it.ws : it.in);
     T *dst = static_cast<T *>((it.lapl && un.phase == 0) ? it.ws : it.out);
-    if (op == OP_GRAD) batch_unit_op<T, OP_GRAD>(it.m, it.form, src, dst, it.nlev, un.p0, un.p1);
-    else if (op == OP_DIV) batch_unit_op<T, OP_DIV>(it.m, it.form, src, dst, it.nlev, un.p0, un.p1);
-    else batch_unit_op<T, OP_CURL>(it.m, it.form, src, dst, it.nlev, un.p0, un.p1);
+    const int lv = un.phase ? it.level_vec1 : it.level_vec;
+    if (op == OP_GRAD)
+      batch_unit_op<T, OP_GRAD>(it.m, it.form, lv, src, dst, it.nlev, un.p0, un.p1);
+    else if (op == OP_DIV)
+      batch_unit_op<T, OP_DIV>(it.m, it.form, lv, src, dst, it.nlev, un.p0, un.p1);
+    else
+      batch_unit_op<T, OP_CURL>(it.m, it.form, lv, src, dst, it.nlev, un.p0, un.p1);
   }
 }
 
@@ -1526,8 +1559,10 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   }
   if (nlev < 48) return s;
   if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) s.level_vec = 1;
+  // the sweep runs one workgroup per tile and level chunk, each walking its
+  // band's parallels in turn: only a mesh of many tiles fills the chip
   if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && m.d.sweep_ok &&
-      max(1, m.d.segmax) * kGeoWords <= 768) {
+      m.d.ntiles >= kSweepMinTiles && max(1, m.d.segmax) * kGeoWords <= 768) {
     s.variant = ATLAS_VARIANT_SWEEP;
     s.block = 768;
     s.nodes_per_block = 0;

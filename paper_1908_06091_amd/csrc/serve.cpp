@@ -11,13 +11,14 @@
 // with the same operation sequence, so a result does not depend on what it
 // was launched with.
 //
-// Device memory for outputs and workspaces comes from a small caching
-// allocator: blocks are hipMalloc'ed once per size class and handed out
-// again only after the work that used them has completed (a workspace when
-// its request's event has fired, a server-owned output when the caller has
-// released it), so reuse needs no stream ordering.  Cached plus used bytes
-// stay within the HBM budget; cached blocks are freed only when a new size
-// would not fit otherwise.
+// Device memory for outputs and workspaces comes from one arena of the HBM
+// budget, reserved at creation: a request's ranges are carved out when it is
+// admitted and handed back only after the work that used them has completed
+// (a workspace when its request's event has fired, a server-owned output
+// when the caller has released it), so reuse needs no stream ordering and
+// the steady state makes no hipMalloc or hipFree call (hipFree waits for the
+// whole device).  A request whose ranges do not fit the arena yet (it is
+// fragmented) waits at the head of the queue like one over the budget.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,6 +57,7 @@ struct Req {
   MeshStore *m = nullptr;  // NULL on a simulation server
   int64_t V = 0;
   size_t in_b = 0, out_b = 0, ws_b = 0;
+  size_t out_off = SIZE_MAX, ws_off = SIZE_MAX;  // arena ranges (SIZE_MAX: none)
   bool own_out = false;
   bool out_charged = false;  // out_b still counted in flight (a server-owned
                              // output stays counted until it is released)
@@ -88,6 +90,52 @@ struct MeshEntry {
 constexpr size_t kTabAlign = 256;
 size_t align_up(size_t x) { return (x + kTabAlign - 1) / kTabAlign * kTabAlign; }
 
+// Offsets into one device range: best fit over a free list kept sorted by
+// offset, neighbours merged when a range comes back.  Sizes are rounded to
+// kAlign so every range starts aligned.
+struct Arena {
+  static constexpr size_t kAlign = 4096;
+  char *base = nullptr;  // NULL on a simulation server (offsets only)
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+
+  static size_t round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+  void init(char *b, size_t bytes) {  // bytes: a multiple of kAlign
+    base = b;
+    size = bytes;
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool take(size_t bytes, size_t *off) {
+    const size_t b = round(bytes);
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= b && (best == free_.end() || it->second < best->second)) best = it;
+    if (best == free_.end()) return false;
+    *off = best->first;
+    const size_t rest = best->second - b, at = best->first + b;
+    free_.erase(best);
+    if (rest) free_[at] = rest;
+    return true;
+  }
+  void give(size_t off, size_t bytes) {
+    size_t b = round(bytes);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + b == next->first) {
+      b += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += b;
+        return;
+      }
+    }
+    free_[off] = b;
+  }
+};
+
 }  // namespace
 
 struct Server {
@@ -97,10 +145,7 @@ struct Server {
   int grid_full[2] = {8, 8};  // persistent batch grid per dtype (F32, F64)
   std::vector<MeshEntry> meshes;
   std::vector<Slot> slots;
-  // caching allocator (scheduler thread and release, under mu)
-  std::multimap<size_t, void *> cache;        // free blocks by size
-  std::map<void *, size_t> block_bytes;       // every block the server holds
-  size_t held_bytes = 0;                      // used + cached
+  Arena arena;  // outputs and workspaces (under mu)
 
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -109,6 +154,7 @@ struct Server {
   std::deque<uint64_t> admitted;  // admitted, not launched (arrival order)
   uint64_t next_ticket = 1;
   uint64_t alloc_count = 0;
+  uint64_t wake_gen = 0;  // bumped by every call that can unblock admission
   bool stopping = false;
   atlas_serve_stats st{};
   std::thread thread;
@@ -119,47 +165,40 @@ struct Server {
   }
   void uncharge(size_t b) { st.inflight_bytes -= std::min(b, st.inflight_bytes); }
 
-  static size_t size_class(size_t bytes) {
-    const size_t g = (size_t)2 << 20;  // 2 MiB granules
-    return (bytes + g - 1) / g * g;
+  // Carves a request's server-owned output and workspace out of the arena.
+  // Returns 1 when placed, 0 when a range does not fit yet (nothing is
+  // kept), -1 on an injected failure (every cfg.fail_alloc_every-th
+  // allocation fails on purpose: fault injection for the error paths).
+  int place(Req &q) {
+    const size_t need[2] = {q.own_out ? q.out_b : 0, q.ws_b};
+    size_t off[2] = {SIZE_MAX, SIZE_MAX};
+    for (int i = 0; i < 2; ++i) {
+      if (!need[i]) continue;
+      ++alloc_count;
+      const bool injected =
+          cfg.fail_alloc_every > 0 && alloc_count % (uint64_t)cfg.fail_alloc_every == 0;
+      if (injected || !arena.take(need[i], &off[i])) {
+        if (i == 1 && off[0] != SIZE_MAX) arena.give(off[0], need[0]);
+        return injected ? -1 : 0;
+      }
+    }
+    q.out_off = off[0];
+    q.ws_off = off[1];
+    if (arena.base) {
+      if (off[0] != SIZE_MAX) q.r.out = arena.base + off[0];
+      if (off[1] != SIZE_MAX) q.ws = arena.base + off[1];
+    }
+    return 1;
   }
-
-  // Device block of at least `bytes`; every cfg.fail_alloc_every-th call
-  // fails on purpose (fault injection for the scheduler's error paths).
-  bool alloc(void **p, size_t bytes) {
-    ++alloc_count;
-    if (cfg.fail_alloc_every > 0 && alloc_count % (uint64_t)cfg.fail_alloc_every == 0) return false;
-    if (cfg.simulate) {
-      *p = nullptr;
-      return true;
-    }
-    const size_t want = size_class(bytes);
-    auto it = cache.lower_bound(want);
-    if (it != cache.end() && it->first <= want + want / 4) {  // close fit
-      *p = it->second;
-      cache.erase(it);
-      return true;
-    }
-    // make room within the budget by dropping cached blocks, largest first
-    while (held_bytes + want > cfg.hbm_budget_bytes && !cache.empty()) {
-      auto last = std::prev(cache.end());
-      (void)hipFree(last->second);
-      held_bytes -= last->first;
-      block_bytes.erase(last->second);
-      cache.erase(last);
-    }
-    void *q = nullptr;
-    if (hipMalloc(&q, want) != hipSuccess) return false;
-    block_bytes[q] = want;
-    held_bytes += want;
-    *p = q;
-    return true;
+  void give_out(Req &q) {
+    if (q.out_off != SIZE_MAX) arena.give(q.out_off, q.out_b);
+    q.out_off = SIZE_MAX;
+    if (q.own_out) q.r.out = nullptr;
   }
-  // Returns a block whose device work has completed to the cache.
-  void recycle(void *p) {
-    if (!p || cfg.simulate) return;
-    auto it = block_bytes.find(p);
-    if (it != block_bytes.end()) cache.insert({it->second, p});
+  void give_ws(Req &q) {
+    if (q.ws_off != SIZE_MAX) arena.give(q.ws_off, q.ws_b);
+    q.ws_off = SIZE_MAX;
+    q.ws = nullptr;
   }
 
   // A request leaves the device: release what it holds except an output the
@@ -169,14 +208,12 @@ struct Server {
     q.status = status;
     q.state = DONE;
     q.t_done = now;
-    recycle(q.ws);
-    q.ws = nullptr;
+    give_ws(q);
     size_t b = q.in_b + q.ws_b;
     if (!(q.own_out && status == ATLAS_OK)) {
       if (q.out_charged) b += q.out_b;
       q.out_charged = false;
-      if (q.own_out && q.r.out) recycle(q.r.out);
-      if (q.own_out) q.r.out = nullptr;
+      give_out(q);
     }
     uncharge(b);
     if (status == ATLAS_OK) ++st.completed;
@@ -205,15 +242,25 @@ struct Server {
     }
   }
 
-  void admit() {
+  // Admits queued requests in arrival order while they fit the budget and
+  // their ranges fit the arena; an injected allocation failure finishes its
+  // request with ATLAS_ENOMEM.
+  void admit(Clock::time_point now) {
     while (!queue.empty()) {
       Req &q = reqs.at(queue.front());
       if (st.inflight_bytes + q.footprint() > cfg.hbm_budget_bytes) break;
+      const int placed = place(q);
+      if (placed == 0) break;
       charge(q.footprint());
       q.out_charged = true;
+      queue.pop_front();
+      if (placed < 0) {
+        finish(q, ATLAS_ENOMEM, now);
+        cv_done.notify_all();
+        continue;
+      }
       q.state = ADMITTED;
       admitted.push_back(q.ticket);
-      queue.pop_front();
     }
   }
 
@@ -241,29 +288,11 @@ struct Server {
     return g;
   }
 
-  // Enqueues one group on slot `si`.  Requests whose allocation fails are
-  // finished with ATLAS_ENOMEM; the rest run.
-  void launch(int si, std::vector<uint64_t> group, Clock::time_point now) {
+  // Enqueues one group of admitted requests (their memory placed) on slot
+  // `si`.
+  void launch(int si, std::vector<uint64_t> run, Clock::time_point now) {
     Slot &s = slots[si];
-    std::vector<uint64_t> run;
-    for (uint64_t t : group) {
-      Req &q = reqs.at(t);
-      q.slot = si;
-      bool ok = true;
-      if (!q.r.out && q.own_out) ok = alloc(&q.r.out, q.out_b);
-      if (ok && q.ws_b) ok = alloc(&q.ws, q.ws_b);
-      if (!ok) {
-        recycle(q.ws);  // nothing was enqueued on it
-        q.ws = nullptr;
-        finish(q, ATLAS_ENOMEM, now);
-        continue;
-      }
-      run.push_back(t);
-    }
-    if (run.empty()) {
-      cv_done.notify_all();
-      return;
-    }
+    for (uint64_t t : run) reqs.at(t).slot = si;
     const int n = (int)run.size();
     int status = ATLAS_OK;
     if (cfg.simulate) {
@@ -287,8 +316,8 @@ struct Server {
     if (status == ATLAS_OK && !cfg.simulate && hipEventRecord(s.done, s.stream) != hipSuccess)
       status = ATLAS_EDEVICE;
     if (status != ATLAS_OK) {
-      // part of the group's work may be enqueued: let it drain before the
-      // blocks go back to the cache
+      // part of the group's work may be enqueued: let it drain before its
+      // ranges go back to the arena
       if (!cfg.simulate) (void)hipStreamSynchronize(s.stream);
       for (uint64_t t : run) finish(reqs.at(t), status, now);
       cv_done.notify_all();
@@ -325,8 +354,9 @@ struct Server {
       bi.in = q.r.in;
       bi.out = q.r.out;
       bi.ws = q.ws;
-      shapes[i] = heuristic_shape(q.r.nlev);
+      shapes[i] = heuristic_shape(bi.op, dt, q.r.nlev);
       bi.form = shapes[i].form;
+      bi.level_vec = shapes[i].level_vec;
       two_pass = two_pass || bi.lapl;
     }
     std::vector<BatchUnit> units;
@@ -371,13 +401,26 @@ struct Server {
     for (;;) {
       Clock::time_point now = Clock::now();
       poll(now);
-      admit();
+      admit(now);
       for (int si = 0; si < (int)slots.size() && !admitted.empty(); ++si) {
         if (slots[si].busy) continue;
         launch(si, next_group(), Clock::now());
       }
       const bool busy = any_busy();
-      if (stopping && queue.empty() && admitted.empty() && !busy) break;
+      if (stopping && admitted.empty() && !busy) {
+        // a request still queued now can only wait for releases that a
+        // caller destroying the server will not make: cancel it
+        for (uint64_t t : queue) {
+          Req &q = reqs.at(t);
+          q.status = ATLAS_ECANCELLED;
+          q.state = DONE;
+          q.t_done = Clock::now();
+          ++st.cancelled;
+        }
+        queue.clear();
+        cv_done.notify_all();
+        break;
+      }
       if (busy) {
         Clock::time_point until = Clock::now() + std::chrono::microseconds(20);
         if (cfg.simulate) {
@@ -387,9 +430,11 @@ struct Server {
         }
         cv_sched.wait_until(lk, until);
       } else {
-        cv_sched.wait(lk, [&] {
-          return stopping || !queue.empty() || !admitted.empty();
-        });
+        // idle: every slot is free, so nothing is admitted-but-unlaunched;
+        // a queued request left over does not fit until a submit, cancel,
+        // release or destroy changes the picture
+        const uint64_t gen = wake_gen;
+        cv_sched.wait(lk, [&] { return stopping || wake_gen != gen; });
       }
     }
   }
@@ -409,9 +454,8 @@ atlas_status release_server(Server *sv) {
   for (Slot &s : sv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
   }
-  for (auto &kv : sv->block_bytes) (void)hipFree(kv.first);  // used and cached blocks
-  sv->block_bytes.clear();
-  sv->cache.clear();
+  if (sv->arena.base) (void)hipFree(sv->arena.base);
+  sv->arena.base = nullptr;
   for (Slot &s : sv->slots) {
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -433,7 +477,8 @@ atlas_status atlas_serve_create(const atlas_serve_config *cfg, atlas_server_t *o
   if (cfg->nstreams < 1 || cfg->nstreams > 16) return fail(ATLAS_EINVAL, "nstreams must be in [1, 16]");
   if (cfg->max_batch < 1 || cfg->max_batch > 4096) return fail(ATLAS_EINVAL, "max_batch must be in [1, 4096]");
   if (cfg->batch_max_elems < 0) return fail(ATLAS_EINVAL, "batch_max_elems must be >= 0");
-  if (cfg->hbm_budget_bytes == 0) return fail(ATLAS_EINVAL, "hbm_budget_bytes must be > 0");
+  if (cfg->hbm_budget_bytes == 0 || cfg->hbm_budget_bytes > ((size_t)1 << 50))
+    return fail(ATLAS_EINVAL, "hbm_budget_bytes must be in (0, 2^50]");
   if (cfg->simulate && !(cfg->sim_bytes_per_us > 0))
     return fail(ATLAS_EINVAL, "sim_bytes_per_us must be > 0");
   if (cfg->fail_alloc_every < 0) return fail(ATLAS_EINVAL, "fail_alloc_every must be >= 0");
@@ -442,11 +487,22 @@ atlas_status atlas_serve_create(const atlas_serve_config *cfg, atlas_server_t *o
   sv->cfg = *cfg;
   if (sv->cfg.batch_max_elems == 0) sv->cfg.batch_max_elems = (int64_t)1 << 22;
   sv->slots.resize(cfg->nstreams);
+  // the budget plus one alignment granule for each of a request's two
+  // ranges: every admissible request fits an empty arena
+  const size_t arena_bytes = Arena::round(cfg->hbm_budget_bytes) + 2 * Arena::kAlign;
+  if (cfg->simulate) sv->arena.init(nullptr, arena_bytes);
   if (!cfg->simulate) {
     if (hipGetDevice(&sv->device) != hipSuccess) {
       delete sv;
       return fail(ATLAS_EDEVICE, "hipGetDevice");
     }
+    void *base = nullptr;
+    if (hipMalloc(&base, arena_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      delete sv;
+      return fail(ATLAS_ENOMEM, "cannot reserve the HBM budget on the device");
+    }
+    sv->arena.init(static_cast<char *>(base), arena_bytes);
     for (int d = 0; d < 2; ++d)
       sv->grid_full[d] = std::max(
           8, (device_cu_count() * batch_blocks_per_cu(d ? ATLAS_F64 : ATLAS_F32, Server::kBlock) +
@@ -554,6 +610,7 @@ atlas_status atlas_serve_submit(atlas_server_t srv, const atlas_request *req, ui
   sv.reqs.emplace(q.ticket, q);
   sv.queue.push_back(q.ticket);
   *ticket = q.ticket;
+  ++sv.wake_gen;
   sv.cv_sched.notify_one();
   return ATLAS_OK;
 }
@@ -608,6 +665,7 @@ atlas_status atlas_serve_cancel(atlas_server_t srv, uint64_t ticket) {
     return fail(ATLAS_ESTATE, "request already launched");
   }
   sv.cv_done.notify_all();
+  ++sv.wake_gen;
   sv.cv_sched.notify_one();
   return ATLAS_OK;
 }
@@ -620,9 +678,10 @@ atlas_status atlas_serve_release(atlas_server_t srv, uint64_t ticket) {
   if (it == sv.reqs.end()) return fail(ATLAS_EINVAL, "unknown ticket");
   Req &q = it->second;
   if (q.state != DONE) return fail(ATLAS_ESTATE, "request not finished");
-  if (q.own_out && q.r.out) sv.recycle(q.r.out);  // the caller has finished reading it
+  sv.give_out(q);  // the caller has finished reading it
   if (q.out_charged) sv.uncharge(q.out_b);
   sv.reqs.erase(it);
+  ++sv.wake_gen;
   sv.cv_sched.notify_one();  // budget freed
   return ATLAS_OK;
 }
@@ -641,6 +700,7 @@ atlas_status atlas_serve_destroy(atlas_server_t srv) {
     {
       std::lock_guard<std::mutex> g(sv->mu);
       sv->stopping = true;
+      ++sv->wake_gen;
     }
     sv->cv_sched.notify_all();
     if (sv->thread.joinable()) sv->thread.join();

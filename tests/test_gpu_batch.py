@@ -35,7 +35,9 @@ def _make_items(P, meshes, n, dtype, seed):
     for i in range(n):
         N = int(rng.choice(list(meshes)))
         gm = meshes[N]
-        nlev = int(rng.choice([1, 10, 91, 137]))
+        # 300 levels: two lane vectors per lane in FP32, one level per lane
+        # past three chunks in FP64
+        nlev = int(rng.choice([1, 10, 91, 137, 300]))
         op = OPS[int(rng.integers(0, 4))]
         vec_in = op in ("div", "curl")
         shape = (gm.nnodes, nlev, 2) if vec_in else (gm.nnodes, nlev)

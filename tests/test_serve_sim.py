@@ -213,3 +213,47 @@ def test_destroy_drains_pending_requests():
     with pytest.raises(AtlasError):
         P.Server(hbm_budget_bytes=1, nstreams=1, max_batch=1, simulate=True,
                  sim_bytes_per_us=1.0).register_mesh(type("M", (), {"handle": None})())
+
+
+def test_fragmented_arena_holds_the_head_until_a_release():
+    """Server-owned outputs are ranges of one arena of the budget (plus one
+    4 KiB granule per range).  Four small outputs fill it in order; releasing
+    the first and third leaves free space that the budget allows but no
+    contiguous range for a larger output, which is admitted once the second
+    is released too (the freed ranges merge)."""
+    X = 4096 * 100
+    s = make(hbm_budget_bytes=3 * X, nstreams=4, max_batch=1, sim_bytes_per_us=1e4)
+    small = s.register_sim_mesh(X // 4 // 8)      # F64, 1 level: output X/2
+    big = s.register_sim_mesh(6 * X // 10 // 8)   # output 1.2 X
+    ts = [s.submit(small, GRAD, nlev=1, dtype=F64) for _ in range(4)]
+    assert all(s.wait(t)["status"] == P.ATLAS_OK for t in ts)
+    s.release(ts[0])
+    s.release(ts[2])
+    assert s.stats()["inflight_bytes"] == X
+    tb = s.submit(big, GRAD, nlev=1, dtype=F64)
+    assert footprint(6 * X // 10 // 8, 1, GRAD, 8) + X <= 3 * X  # within budget
+    with pytest.raises(AtlasError, match="ETIMEOUT"):
+        s.wait(tb, timeout_us=200_000)
+    s.release(ts[1])
+    assert s.wait(tb, timeout_us=5_000_000)["status"] == P.ATLAS_OK
+    s.release(tb)
+    s.release(ts[3])
+    assert s.stats()["inflight_bytes"] == 0
+    s.close()
+
+
+@pytest.mark.timeout(60)
+def test_destroy_cancels_requests_that_can_no_longer_be_admitted():
+    """A request queued behind server-owned outputs that are never released
+    cannot be admitted; destroying the server cancels it instead of waiting
+    forever."""
+    V = 1000
+    fp = footprint(V, 1, GRAD, 8)
+    s = make(hbm_budget_bytes=fp, nstreams=1, sim_bytes_per_us=1e4)
+    m = s.register_sim_mesh(V)
+    t0 = s.submit(m, GRAD, nlev=1, dtype=F64)
+    assert s.wait(t0)["status"] == P.ATLAS_OK
+    t1 = s.submit(m, GRAD, nlev=1, dtype=F64)  # blocked: t0's output is held
+    with pytest.raises(AtlasError, match="ETIMEOUT"):
+        s.wait(t1, timeout_us=100_000)
+    s.close()
