@@ -184,8 +184,10 @@ def accuracy(gm, om, f64, uv64, torch, np, nsample=2000):
 
 def batch_bench(P, torch, np, dev):
     """64 FP32 work items over O80/O160/O320 with nlev in {1,10,91,137} and
-    operators in {grad, div, lapl}, autotuned and captured in a hipGraph:
-    replay time against the same items launched one by one."""
+    operators in {grad, div, lapl}, autotuned and captured in a hipGraph
+    (items of 2^22+ elements as their own launches, the rest in the
+    persistent launch): replay time against the same items launched one by
+    one."""
     import synthetic as sy
     rng = np.random.default_rng(64)
     meshes = {N: P.Mesh(N) for N in (80, 160, 320)}
@@ -244,6 +246,7 @@ def batch_bench(P, torch, np, dev):
         for g_, r_ in comps:
             worst = max(worst, float(np.abs(g_ - r_).max() / np.abs(r_).max()))
     return {"items": 64, "dtype": "f32", "graph": bool(info.graph), "units": info.nunits,
+            "solo_items": info.solo_items,
             "grid_blocks": info.grid_blocks, "form_column": info.form_column,
             "form_flat": info.form_flat, "build_s_incl_autotune": round(build_s, 2),
             "ms_batch": round(ms_batch, 4), "ms_one_by_one": round(ms_seq, 4),

@@ -1,15 +1,17 @@
 /*
- * atlas_batch.h -- many operator applications in ONE persistent launch.
+ * atlas_batch.h -- many operator applications in one launch sequence.
  *
  * The paper groups fields into a FieldSet (Section 4.6) and applies the
  * Nabla operators of Section 4.7 field by field.  Here a batch is a table
  * of work items -- (mesh, operator, nlev, input, output) with uneven meshes
- * and level counts -- executed by one persistent kernel that pulls work
- * units (item, block of nodes, phase) from per-XCD queues; no workgroup
- * ever waits for another.  The Laplacian's second pass (divergence of the
- * gradient) is a second launch of the same kernel after the first (two
- * graph nodes: the launch order is the dependency).  The launch can be
- * captured once in a hipGraph and replayed.
+ * and level counts.  Small items are executed by one persistent kernel that
+ * pulls work units (item, block of nodes, phase) from per-XCD queues; no
+ * workgroup ever waits for another.  The Laplacian's second pass
+ * (divergence of the gradient) is a second launch of the same kernel after
+ * the first (two graph nodes: the launch order is the dependency).  Items
+ * large enough to fill the device alone (nnodes * nlev >= solo_min_elems)
+ * run after it as their own launches with their own (tuned) shapes.  The
+ * whole sequence can be captured once in a hipGraph and replayed.
  *
  * Every item's output is bitwise identical to the same operator launched
  * alone (same per-element operation sequence).
@@ -45,6 +47,8 @@ typedef struct {
                             with the items' own buffers at build time    */
   int32_t block_threads; /* persistent workgroup size, 0 = 256           */
   int32_t blocks_per_cu; /* 0 = as many as fit (occupancy)               */
+  int64_t solo_min_elems; /* items with nnodes * nlev at or above this run
+                             as their own launches (0 = 2^22; -1 = never) */
 } atlas_batch_config;
 
 typedef struct {
@@ -53,6 +57,7 @@ typedef struct {
   int32_t form_column;     /* items using the column tile form           */
   int32_t form_flat;       /* items using the flat tile form             */
   size_t owned_bytes;      /* device memory owned by the batch           */
+  int32_t solo_items;      /* items run as their own launches            */
 } atlas_batch_info;
 
 /* Validate every item (as the single operators do), choose a tile shape

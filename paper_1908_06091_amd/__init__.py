@@ -254,11 +254,13 @@ def autotune(mesh, op: int, x, out, workspace=None, stream=None):
 
 
 class Batch:
-    """Many operator applications in one persistent launch (atlas_batch.h).
+    """Many operator applications in one launch sequence (atlas_batch.h):
+    small items in one persistent launch, items with nnodes * nlev at or
+    above solo_min_elems (0: 2^22, -1: never) as their own launches.
     items: list of (mesh, op, x, out) or (mesh, op, x, out, workspace)."""
 
     def __init__(self, items, *, use_graph=True, autotune=False, block_threads=0,
-                 blocks_per_cu=0, stream=None):
+                 blocks_per_cu=0, solo_min_elems=0, stream=None):
         if not items:
             raise ValueError("a batch needs at least one item")
         self._keep = []
@@ -282,7 +284,7 @@ class Batch:
             arr[i].workspace = ws.data_ptr() if ws is not None else None
             self._keep.append((mesh, x, out, ws))
         cfg = _abi.BatchConfig(dtype, int(use_graph), int(autotune), int(block_threads),
-                               int(blocks_per_cu))
+                               int(blocks_per_cu), int(solo_min_elems))
         self._lib = lib()
         self._h = ctypes.c_void_p()
         _check(self._lib.atlas_batch_build(arr, len(items), ctypes.byref(cfg), _stream(stream),

@@ -68,14 +68,15 @@ class WorkItem(ctypes.Structure):
 class BatchConfig(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("solo_min_elems", ctypes.c_int64)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("nitems", ctypes.c_int32), ("nunits", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("form_column", ctypes.c_int32),
-                ("form_flat", ctypes.c_int32), ("owned_bytes", ctypes.c_size_t)]
+                ("form_flat", ctypes.c_int32), ("owned_bytes", ctypes.c_size_t),
+                ("solo_items", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol the headers declare

@@ -65,9 +65,21 @@ void plan_units(const std::vector<BatchItem> &items, const std::vector<ItemShape
 
 namespace {
 
+// An item that runs as its own launch (large enough to fill the device).
+struct SoloItem {
+  const MeshStore *m;
+  atlas_op op;
+  const void *in;
+  int nlev;
+  void *out, *ws;
+  LaunchShape sh;
+};
+
 struct Batch {
   atlas_dtype dtype = ATLAS_F32;
   int nitems = 0, nunits = 0, grid = 0, block = 256;
+  int nbatched = 0;             // items in the persistent launch
+  std::vector<SoloItem> solo;   // the others, launched after it in order
   bool two_pass = false;
   int form_column = 0, form_flat = 0;
   BatchItem *d_items = nullptr;
@@ -92,6 +104,21 @@ struct Batch {
     if (d_heads) (void)hipFree(d_heads);
   }
 };
+
+// Enqueues a batch on `st`: the persistent launch of the small items (two
+// launches if any is a Laplacian), then every solo item in item order.
+atlas_status enqueue(Batch &b, hipStream_t st) {
+  if (b.nbatched > 0) {
+    atlas_status s = launch_batch(b.dtype, b.d_items, b.d_units, b.d_qbeg, b.d_qbeg + 9,
+                                  b.two_pass, b.d_heads, b.grid, b.block, st);
+    if (s != ATLAS_OK) return s;
+  }
+  for (const SoloItem &x : b.solo) {
+    atlas_status s = launch_op(*x.m, x.op, b.dtype, x.in, x.nlev, x.out, x.ws, x.sh, st);
+    if (s != ATLAS_OK) return s;
+  }
+  return ATLAS_OK;
+}
 
 }  // namespace
 
@@ -265,13 +292,14 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
   *out = nullptr;
   if (!items || n < 1) return fail(ATLAS_EINVAL, "a batch needs at least one item");
   if (n > (1 << 20)) return fail(ATLAS_EINVAL, "too many items");
-  const atlas_batch_config c = cfg ? *cfg : atlas_batch_config{ATLAS_F32, 0, 0, 0, 0};
+  const atlas_batch_config c = cfg ? *cfg : atlas_batch_config{ATLAS_F32, 0, 0, 0, 0, 0};
   if (c.dtype != ATLAS_F32 && c.dtype != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
   const int block = c.block_threads ? c.block_threads : 256;
   if (block < 64 || block > 256 || (block & 63))
     return fail(ATLAS_EINVAL, "block_threads must be 64, 128, 192 or 256");
-  if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32)
+  if (c.blocks_per_cu < 0 || c.blocks_per_cu > 32 || c.solo_min_elems < -1)
     return fail(ATLAS_EINVAL, "bad batch configuration");
+  const int64_t solo_min = c.solo_min_elems == 0 ? ((int64_t)1 << 22) : c.solo_min_elems;
   const atlas_dtype dt = (atlas_dtype)c.dtype;
   const size_t w = dt == ATLAS_F64 ? 8 : 4;
   // validate every item before allocating anything
@@ -292,13 +320,14 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
     delete b;
     return s;
   };
-  std::vector<BatchItem> h_items(n);
-  std::vector<ItemShape> h_shapes(n);
+  std::vector<BatchItem> h_items;
+  std::vector<ItemShape> h_shapes;
   std::map<std::tuple<const void *, int, int>, ItemShape> shapes;
+  std::map<std::tuple<const void *, int, int>, bool> tuned;  // solo classes
   for (int i = 0; i < n; ++i) {
     const atlas_work_item &it = items[i];
     MeshStore &m = *it.mesh->store;
-    BatchItem &bi = h_items[i];
+    BatchItem bi;
     std::memset(&bi, 0, sizeof(bi));
     bi.m = m.d;
     bi.lapl = it.op == ATLAS_OP_LAPLACIAN ? 1 : 0;
@@ -316,6 +345,20 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
       bi.ws = p;
     }
     const auto key = std::make_tuple((const void *)&m, it.op, it.nlev);
+    if (solo_min >= 0 && (int64_t)m.d.V * it.nlev >= solo_min) {
+      // its own launch, with the shape a single call would use (tuned
+      // first if asked; the tuner stores the winner in the mesh)
+      if (c.autotune && !tuned[key]) {
+        atlas_status s = autotune(it.mesh, (atlas_op)it.op, it.in, it.nlev, dt, it.out, bi.ws,
+                                  stream, nullptr, nullptr);
+        if (s != ATLAS_OK) return bail(s);
+        tuned[key] = true;
+      }
+      LaunchShape sh = shape_from(nullptr, m, (atlas_op)it.op, it.nlev, dt);
+      if (sh.variant == ATLAS_VARIANT_FLUX) sh = default_shape(m, (atlas_op)it.op, it.nlev, dt);
+      b->solo.push_back({&m, (atlas_op)it.op, it.in, it.nlev, it.out, bi.ws, sh});
+      continue;
+    }
     auto f = shapes.find(key);
     ItemShape sh;
     if (f != shapes.end()) {
@@ -330,27 +373,32 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
     bi.form = sh.form;
     bi.level_vec = sh.level_vec;
     (sh.form == FORM_COLUMN ? b->form_column : b->form_flat) += 1;
-    h_shapes[i] = sh;
+    h_items.push_back(bi);
+    h_shapes.push_back(sh);
     b->two_pass = b->two_pass || bi.lapl;
   }
+  b->nbatched = (int)h_items.size();
   std::vector<BatchUnit> h_units;
   std::vector<int> qbeg;
   plan_units(h_items, h_shapes, h_units, qbeg);
   b->nunits = (int)h_units.size();
-  if (hipMalloc(&b->d_items, sizeof(BatchItem) * n) != hipSuccess ||
+  const size_t nb = std::max<size_t>(1, h_items.size());
+  if (hipMalloc(&b->d_items, sizeof(BatchItem) * nb) != hipSuccess ||
       hipMalloc(&b->d_units, sizeof(BatchUnit) * std::max<size_t>(1, h_units.size())) != hipSuccess ||
       hipMalloc(&b->d_qbeg, sizeof(int) * 18) != hipSuccess ||
       hipMalloc(&b->d_heads, sizeof(int) * 16) != hipSuccess)
     return bail(fail(ATLAS_ENOMEM, "batch tables"));
-  b->owned_bytes += sizeof(BatchItem) * n + sizeof(BatchUnit) * h_units.size() + 4 * (18 + 16);
-  if (hipMemcpy(b->d_items, h_items.data(), sizeof(BatchItem) * n, hipMemcpyHostToDevice) !=
-          hipSuccess ||
+  b->owned_bytes += sizeof(BatchItem) * nb + sizeof(BatchUnit) * h_units.size() + 4 * (18 + 16);
+  if ((!h_items.empty() && hipMemcpy(b->d_items, h_items.data(), sizeof(BatchItem) * h_items.size(),
+                                     hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(b->d_units, h_units.data(), sizeof(BatchUnit) * h_units.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_qbeg, qbeg.data(), sizeof(int) * 18, hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(ATLAS_EDEVICE, "batch table upload"));
   const int bpc = c.blocks_per_cu ? c.blocks_per_cu : batch_blocks_per_cu(dt, block);
-  b->grid = std::max(8, (device_cu_count() * bpc + 7) / 8 * 8);
+  // a full persistent grid, or fewer workgroups when there are few units
+  b->grid = std::min(std::max(8, (device_cu_count() * bpc + 7) / 8 * 8),
+                     std::max(8, (b->nunits + 7) / 8 * 8));
   if (hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess)
     return bail(fail(ATLAS_EDEVICE, "event"));
   if (c.use_graph) {
@@ -358,8 +406,7 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
       return bail(fail(ATLAS_EDEVICE, "capture stream"));
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return bail(fail(ATLAS_EDEVICE, "hipStreamBeginCapture"));
-    atlas_status s = launch_batch(dt, b->d_items, b->d_units, b->d_qbeg, b->d_qbeg + 9,
-                                  b->two_pass, b->d_heads, b->grid, block, b->cap);
+    atlas_status s = enqueue(*b, b->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (s != ATLAS_OK || e != hipSuccess) {
@@ -382,8 +429,7 @@ atlas_status atlas_batch_launch(atlas_batch_t batch, hipStream_t stream) {
   if (b.exec) {
     ATLASX_HIP(hipGraphLaunch(b.exec, stream));
   } else {
-    atlas_status s = launch_batch(b.dtype, b.d_items, b.d_units, b.d_qbeg, b.d_qbeg + 9,
-                                  b.two_pass, b.d_heads, b.grid, b.block, stream);
+    atlas_status s = enqueue(b, stream);
     if (s != ATLAS_OK) return s;
   }
   ATLASX_HIP(hipEventRecord(b.last, stream));
@@ -407,6 +453,7 @@ atlas_status atlas_batch_get_info(atlas_batch_t batch, atlas_batch_info *info) {
   info->form_column = b.form_column;
   info->form_flat = b.form_flat;
   info->owned_bytes = b.owned_bytes;
+  info->solo_items = (int32_t)b.solo.size();
   return ATLAS_OK;
 }
 

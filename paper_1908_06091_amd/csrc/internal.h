@@ -48,8 +48,9 @@ int build_octahedral(int N, double R, HostMesh &h);
 // into tiles (bands of parallels x longitude sectors) so that a tile's
 // neighbours were touched by the tiles just before it.
 constexpr uint32_t kPoleBit = 0x80000000u;
-constexpr int kIncPad = 8;
-constexpr int32_t kLrefPole = 1 << 30;  // sweep reference of a pole edge         // incidence arrays carry one extra group
+constexpr int kIncPad = 8;               // incidence arrays carry one extra group
+constexpr int32_t kLrefPole = 1 << 30;  // sweep reference of a pole edge
+constexpr int kGRefs = 8;               // references per gradient node (two-ring plan)
 constexpr int kDefaultBand = 32;   // parallels per band of the processing order
 constexpr int kDefaultWidth = 32;  // nodes per sector of a band's widest parallel
 
@@ -90,6 +91,18 @@ struct DevMesh {
                                      //      kLrefPole for a pole edge
   const double *ncos = nullptr;      // [I]  cos(lat) of the incidence's neighbour
   const double *vol = nullptr;       // [V]  dual volume V_i (by position; diagnostics)
+  // two-ring plan of the fused Laplacian: per tile a window of parallels,
+  // each with an f-run (field), a g-run (gradients formed) and own positions
+  int32_t l2_ok = 0;                 // plan valid for this mesh
+  int32_t l2_fmax = 0, l2_gmax = 0;  // longest f-run / g-run
+  const int32_t *l2_tile_seg = nullptr; // [ntiles+1] window range of a tile
+  const int4 *l2_fseg = nullptr;     // {ring offset, ring size, f first, f length}
+  const int4 *l2_gseg = nullptr;     // {g first, g length, first g record, 0}
+  const int2 *l2_seg_pos = nullptr;  // own positions on the parallel [lo, hi)
+  const int4 *l2_gnode = nullptr;    // per g record {row start, row length, f self slot, position}
+  const int32_t *l2_glref = nullptr; // [kGRefs] per g record: references into f-runs
+  const int32_t *l2_lref = nullptr;  // [I] references of own positions into g-runs
+  const int32_t *l2_lself = nullptr; // [V] slot of position p in its g-run
 };
 
 // ------------------------------------------------------------- kernels
@@ -176,6 +189,9 @@ atlas_status derive_scales(MeshStore &m, const double *vol_by_pos,
                            const double *cos_by_pos, double radius);
 atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hipStream_t st);
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
+// The shape a call with launch `l` (NULL: tuned, else built-in) runs with.
+LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
+                       atlas_dtype dt);
 
 }  // namespace atlasx
 

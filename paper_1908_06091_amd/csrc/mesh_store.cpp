@@ -242,6 +242,174 @@ static bool sweep_plan(const std::vector<int64_t> &off, const std::vector<int32_
   return true;
 }
 
+// Two-ring plan of the fused Laplacian.  For every tile: its own
+// parallels [ja, jb]; the gradient is needed at the tile's nodes and their
+// neighbours (parallels ja-1 .. jb+1), and those gradients need the field at
+// their own neighbours (parallels ja-2 .. jb+2).  Per parallel of that
+// window: the f-run (shortest cyclic run holding every node whose field is
+// read), the g-run (the same for the nodes whose gradient is formed; every
+// node of the g-run gets one, so all of them are covered by the f-runs), and
+// the tile's own positions.  Per g-run node: its incidence row start, count,
+// its slot in its f-run and its neighbours' f-run slots; per own position:
+// its slot in its g-run and its neighbours' g-run slots.  References are
+// ((dq + 1) << 16) | slot (dq = neighbour parallel - own parallel) plus
+// kLrefPole for a pole edge.  Returns false if a neighbour lies more than
+// one parallel away.
+struct LaplPlan {
+  std::vector<int32_t> tile_seg;  // [T+1] window range of a tile in fseg/gseg
+  std::vector<int4> fseg;         // {ring offset, ring size, f-run first, f-run length}
+  std::vector<int4> gseg;         // {g-run first, g-run length, first g record, 0}
+  std::vector<int2> seg_pos;      // own positions on the parallel [lo, hi)
+  std::vector<int4> gnode;        // per g record {row start, row length, f self slot, position}
+  std::vector<int32_t> glref;     // per g record: kGRefs references into the f-runs
+  std::vector<int32_t> lref;      // per incidence (own positions): into the g-runs
+  std::vector<int32_t> lself;     // per position: slot in its g-run
+  int32_t fmax = 0, gmax = 0;
+};
+
+static bool cyclic_run(std::vector<int32_t> &a, int32_t nx, int32_t &lo, int32_t &len) {
+  std::sort(a.begin(), a.end());
+  a.erase(std::unique(a.begin(), a.end()), a.end());
+  if (a.empty()) {
+    lo = 0;
+    len = 0;
+  } else if ((int32_t)a.size() == nx) {
+    lo = 0;
+    len = nx;
+  } else {
+    int32_t best = -1, at = 0;  // the run is the complement of the widest gap
+    for (size_t k = 0; k < a.size(); ++k) {
+      const int32_t g = (k + 1 < a.size()) ? a[k + 1] - a[k] : a[0] + nx - a[k];
+      if (g > best) {
+        best = g;
+        at = (int32_t)k;
+      }
+    }
+    lo = a[(at + 1) % a.size()];
+    len = nx - best + 1;
+  }
+  return len < 65536;
+}
+
+static bool lapl_plan(const std::vector<int64_t> &off, const std::vector<int32_t> &perm,
+                      const std::vector<int32_t> &tile_ptr, const std::vector<int32_t> &rowp,
+                      const std::vector<int32_t> &nbr, LaplPlan &lp) {
+  const int64_t V = (int64_t)perm.size();
+  const int32_t nr = (int32_t)off.size() - 1;
+  std::vector<int32_t> ring_of(V), inv(V);
+  for (int32_t j = 0; j < nr; ++j)
+    for (int64_t i = off[j]; i < off[j + 1]; ++i) ring_of[i] = j;
+  for (int64_t p = 0; p < V; ++p) inv[perm[p]] = (int32_t)p;
+  const int64_t T = (int64_t)tile_ptr.size() - 1;
+  lp.tile_seg.assign(1, 0);
+  lp.lref.assign(nbr.size(), 1 << 16);
+  lp.lself.assign(V, 0);
+  auto nb = [&](int32_t r) { return (int32_t)((uint32_t)nbr[r] & ~kPoleBit); };
+  for (int64_t t = 0; t < T; ++t) {
+    const int32_t p0 = tile_ptr[t], p1 = tile_ptr[t + 1];
+    int32_t ja = INT32_MAX, jb = -1;
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t j = ring_of[perm[p]];
+      if (p > p0 && j < ring_of[perm[p - 1]]) return false;  // parallels in order
+      ja = std::min(ja, j);
+      jb = std::max(jb, j);
+    }
+    const int32_t rlo = std::max(0, ja - 2), rhi = std::min(nr - 1, jb + 2);
+    const int32_t W = rhi - rlo + 1;
+    std::vector<std::vector<int32_t>> gneed(W), fneed(W);
+    std::vector<int2> pos(W, make_int2(0, 0));
+    auto local = [&](int32_t node) { return (int32_t)(node - off[ring_of[node]]); };
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t i = perm[p], j = ring_of[i];
+      gneed[j - rlo].push_back(local(i));
+      if (pos[j - rlo].y == 0) pos[j - rlo] = make_int2(p, p + 1);
+      else pos[j - rlo].y = p + 1;
+      for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
+        const int32_t n = nb(r), jn = ring_of[n];
+        if (jn < j - 1 || jn > j + 1) return false;
+        gneed[jn - rlo].push_back(local(n));
+      }
+    }
+    std::vector<int32_t> glo(W), glen(W), flo(W), flen(W);
+    for (int32_t q = 0; q < W; ++q) {
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      if (!cyclic_run(gneed[q], nx, glo[q], glen[q])) return false;
+      // every node of the g-run gets a gradient: its field and its
+      // neighbours' fields are read
+      for (int32_t s = 0; s < glen[q]; ++s) {
+        const int32_t i = (int32_t)off[rlo + q] + (glo[q] + s) % nx;
+        const int32_t p = inv[i], j = rlo + q;
+        fneed[q].push_back(local(i));
+        for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
+          const int32_t n = nb(r), jn = ring_of[n];
+          if (jn < j - 1 || jn > j + 1 || jn < rlo || jn > rhi) return false;
+          fneed[jn - rlo].push_back(local(n));
+        }
+      }
+    }
+    for (int32_t q = 0; q < W; ++q) {
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      if (!cyclic_run(fneed[q], nx, flo[q], flen[q])) return false;
+    }
+    auto fslot = [&](int32_t node) {
+      const int32_t q = ring_of[node] - rlo;
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      int32_t s = local(node) - flo[q];
+      if (s < 0) s += nx;
+      return s;
+    };
+    auto gslot = [&](int32_t node) {
+      const int32_t q = ring_of[node] - rlo;
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      int32_t s = local(node) - glo[q];
+      if (s < 0) s += nx;
+      return s;
+    };
+    for (int32_t q = 0; q < W; ++q) {
+      const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
+      lp.fmax = std::max(lp.fmax, flen[q]);
+      lp.gmax = std::max(lp.gmax, glen[q]);
+      lp.fseg.push_back(make_int4((int32_t)off[rlo + q], nx, flo[q], flen[q]));
+      lp.gseg.push_back(make_int4(glo[q], glen[q], (int32_t)lp.gnode.size(), 0));
+      lp.seg_pos.push_back(pos[q]);
+      const int32_t j = rlo + q;
+      for (int32_t s = 0; s < glen[q]; ++s) {
+        const int32_t i = (int32_t)off[j] + (glo[q] + s) % nx;
+        const int32_t p = inv[i], n0 = rowp[p], n1 = rowp[p + 1];
+        if (n1 - n0 > kGRefs) return false;
+        const int32_t self = fslot(i);
+        if (self >= flen[q]) return false;
+        lp.gnode.push_back(make_int4(n0, n1 - n0, self, p));
+        for (int32_t k = 0; k < kGRefs; ++k) {
+          int32_t ref = 1 << 16;  // padding: the own parallel, slot 0
+          if (k < n1 - n0) {
+            const int32_t r = n0 + k, n = nb(r), qn = ring_of[n] - rlo;
+            const int32_t sl = fslot(n);
+            if (sl >= flen[qn]) return false;
+            ref = ((((uint32_t)nbr[r] & kPoleBit) != 0) ? kLrefPole : 0) |
+                  ((ring_of[n] - j + 1) << 16) | sl;
+          }
+          lp.glref.push_back(ref);
+        }
+      }
+    }
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t i = perm[p], j = ring_of[i];
+      lp.lself[p] = gslot(i);
+      if (lp.lself[p] >= glen[j - rlo]) return false;
+      for (int32_t r = rowp[p]; r < rowp[p + 1]; ++r) {
+        const int32_t n = nb(r), qn = ring_of[n] - rlo;
+        const int32_t sl = gslot(n);
+        if (sl >= glen[qn]) return false;
+        lp.lref[r] = ((((uint32_t)nbr[r] & kPoleBit) != 0) ? kLrefPole : 0) |
+                     ((ring_of[n] - j + 1) << 16) | sl;
+      }
+    }
+    lp.tile_seg.push_back((int32_t)lp.fseg.size());
+  }
+  return true;
+}
+
 template <class T>
 static atlas_status upload_array(MeshStore &m, const std::vector<T> &h, const T **dptr) {
   void *p = nullptr;
@@ -318,6 +486,9 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   SweepPlan sp;
   const bool sweep_ok = nrings <= V / 4 && sweep_plan(rings_of(d), perm, tile_ptr, rowp, nbr, sp);
   if (!sweep_ok) sp = SweepPlan();
+  LaplPlan lp;
+  const bool l2_ok = sweep_ok && lapl_plan(rings_of(d), perm, tile_ptr, rowp, nbr, lp);
+  if (!l2_ok) lp = LaplPlan();
   // cos(lat) of every incidence's neighbour, so a node's row is read with
   // contiguous loads
   std::vector<double> ncos(nbr.size());
@@ -329,6 +500,7 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   inc_edge.resize(inc_edge.size() + kIncPad, 0);
   ncos.resize(ncos.size() + kIncPad, 1.0);
   sp.lref.resize(sp.lref.size() + kIncPad, 1 << 16);
+  if (l2_ok) lp.lref.resize(lp.lref.size() + kIncPad, 1 << 16);
 
   MeshStore *m = new (std::nothrow) MeshStore();
   if (!m) return fail(ATLAS_ENOMEM, "out of host memory");
@@ -344,6 +516,9 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->d.mindeg = V > 0 ? mindeg : 0;
   m->d.sweep_ok = sweep_ok ? 1 : 0;
   m->d.segmax = sp.segmax;
+  m->d.l2_ok = l2_ok ? 1 : 0;
+  m->d.l2_fmax = lp.fmax;
+  m->d.l2_gmax = lp.gmax;
   const double *vol_d = nullptr, *cos_pd = nullptr;
   std::vector<double> zeros(V, 0.0);
   if ((st = upload_array(*m, perm, &m->d.perm)) != ATLAS_OK ||
@@ -364,7 +539,15 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
       (st = upload_array(*m, sp.seg_pos, &m->d.seg_pos)) != ATLAS_OK ||
       (st = upload_array(*m, sp.selfslot, &m->d.selfslot)) != ATLAS_OK ||
       (st = upload_array(*m, sp.lref, &m->d.lref)) != ATLAS_OK ||
-      (st = upload_array(*m, ncos, &m->d.ncos)) != ATLAS_OK) {
+      (st = upload_array(*m, ncos, &m->d.ncos)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.tile_seg, &m->d.l2_tile_seg)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.fseg, &m->d.l2_fseg)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.gseg, &m->d.l2_gseg)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.seg_pos, &m->d.l2_seg_pos)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.gnode, &m->d.l2_gnode)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.glref, &m->d.l2_glref)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.lref, &m->d.l2_lref)) != ATLAS_OK ||
+      (st = upload_array(*m, lp.lself, &m->d.l2_lself)) != ATLAS_OK) {
     delete m;
     return st;
   }

@@ -38,9 +38,6 @@
 
 namespace atlasx {
 
-LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
-                       atlas_dtype dt);
-
 namespace {
 
 using Clock = std::chrono::steady_clock;

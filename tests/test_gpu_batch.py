@@ -51,11 +51,19 @@ def _make_items(P, meshes, n, dtype, seed):
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("use_graph", [True, False])
 @pytest.mark.parametrize("autotune", [False, True])
-def test_batch_items_equal_solo(P, meshes, dtype, use_graph, autotune):
-    print(f"batch dtype={dtype} graph={use_graph} autotune={autotune}", flush=True)
+@pytest.mark.parametrize("solo_min", [0, 20000, 1])
+def test_batch_items_equal_solo(P, meshes, dtype, use_graph, autotune, solo_min):
+    """solo_min 0: every item of these small meshes in the persistent
+    launch; 20000: items of 20000+ elements as their own launches; 1: all."""
+    print(f"batch dtype={dtype} graph={use_graph} autotune={autotune} solo_min={solo_min}",
+          flush=True)
     items = _make_items(P, meshes, 24, dtype, seed=7)
-    b = P.Batch(items, use_graph=use_graph, autotune=autotune)
+    b = P.Batch(items, use_graph=use_graph, autotune=autotune, solo_min_elems=solo_min)
     assert b.info.nitems == 24 and b.info.graph == int(use_graph)
+    nsolo = sum(1 for gm, op, x, out in items if gm.nnodes * x.shape[1] >= solo_min) if solo_min else 0
+    assert b.info.solo_items == nsolo
+    if solo_min == 20000:
+        assert 0 < nsolo < 24
     b.launch()
     b.check()
     for gm, op, x, out in items:
@@ -64,9 +72,11 @@ def test_batch_items_equal_solo(P, meshes, dtype, use_graph, autotune):
         assert torch.equal(out, ref), (op, x.shape)
 
 
-def test_graph_replays_with_eager_work_between(P, meshes):
+@pytest.mark.parametrize("solo_min", [0, 1])
+def test_graph_replays_with_eager_work_between(P, meshes, solo_min):
+    print(f"graph replays solo_min={solo_min}", flush=True)
     items = _make_items(P, meshes, 16, torch.float32, seed=11)
-    b = P.Batch(items, use_graph=True)
+    b = P.Batch(items, use_graph=True, solo_min_elems=solo_min)
     b.launch()
     b.check()
     first = [out.clone() for _, _, _, out in items]
