@@ -446,6 +446,13 @@ def main():
             ops[name] = {"ms": round(t, 4), "edge_level_per_s": E * nlev / (t * 1e-3),
                          "GBps": round(b / (t * 1e-3) / 1e9, 1),
                          "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if opname == "lapl":
+                # GBps above: the two passes' bytes (6 V L w + 2 G); the fused
+                # one-pass form (the FP64 default) needs only 2 V L w + G
+                b1 = 2 * V * nlev * w + geo
+                ops[name]["bytes_model"] = "two passes: 6*V*L*w + 2*G"
+                ops[name]["one_pass_GBps"] = round(b1 / (t * 1e-3) / 1e9, 1)
+                ops[name]["one_pass_hbm_frac"] = round(b1 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             del o
 
     sha = kernel_source_sha()

@@ -207,9 +207,17 @@ typedef enum {
   ATLAS_VARIANT_FLAT = 2,   /* lanes over flattened (node, level) pairs    */
   ATLAS_VARIANT_FLUX = 3,   /* two kernels: edge fluxes into an [E][nlev]
                                buffer (EdgeColumns-like), then the gather  */
-  ATLAS_VARIANT_SWEEP = 4   /* one workgroup per (tile, level chunk) walks
+  ATLAS_VARIANT_SWEEP = 4,  /* one workgroup per (tile, level chunk) walks
                                its band parallel by parallel, keeping three
                                consecutive parallels' columns in LDS       */
+  ATLAS_VARIANT_FUSED = 5   /* Laplacian only: one pass over a two-ring
+                               plan -- the workgroup forms the gradients of
+                               its tile and their neighbours in LDS and
+                               their divergence at once, reading the field
+                               once and writing no gradient to memory.  On
+                               meshes without the plan (or rows outside 4..6
+                               incidences) the two passes run instead.  No
+                               workspace is needed.                         */
 } atlas_variant;
 
 typedef struct {

@@ -20,7 +20,7 @@ from . import _abi
 from ._abi import (ATLAS_ECANCELLED, ATLAS_ENOMEM, ATLAS_OK,  # noqa: F401
                    ATLAS_F32, ATLAS_F64, ATLAS_OP_CURL, ATLAS_OP_DIVERGENCE,  # noqa: F401
                    ATLAS_OP_GRADIENT, ATLAS_OP_LAPLACIAN, VARIANT_AUTO, VARIANT_COLUMN,
-                   VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP, AtlasError, Launch, Layout, MeshDesc,
+                   VARIANT_FLAT, VARIANT_FLUX, VARIANT_FUSED, VARIANT_SWEEP, AtlasError, Launch, Layout, MeshDesc,
                    MeshInfo)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -419,4 +419,4 @@ class Server:
 __all__ = ["error_norms", "Server", "Batch", "autotune", "Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
            "ATLAS_F32", "ATLAS_F64", "ATLAS_OP_GRADIENT", "ATLAS_OP_DIVERGENCE",
            "ATLAS_OP_CURL", "ATLAS_OP_LAPLACIAN", "VARIANT_AUTO", "VARIANT_COLUMN",
-           "VARIANT_FLAT", "VARIANT_FLUX", "VARIANT_SWEEP"]
+           "VARIANT_FLAT", "VARIANT_FLUX", "VARIANT_FUSED", "VARIANT_SWEEP"]

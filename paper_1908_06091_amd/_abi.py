@@ -7,7 +7,7 @@ import numpy as np
 
 ATLAS_F32, ATLAS_F64 = 0, 1
 ATLAS_OP_GRADIENT, ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL, ATLAS_OP_LAPLACIAN = 0, 1, 2, 3
-VARIANT_AUTO, VARIANT_COLUMN, VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP = 0, 1, 2, 3, 4
+VARIANT_AUTO, VARIANT_COLUMN, VARIANT_FLAT, VARIANT_FLUX, VARIANT_SWEEP, VARIANT_FUSED = 0, 1, 2, 3, 4, 5
 
 STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EDEVICE",
           -4: "ATLAS_EBUSY", -5: "ATLAS_ESTATE", -6: "ATLAS_ETIMEOUT", -7: "ATLAS_ECANCELLED"}

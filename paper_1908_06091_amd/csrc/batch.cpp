@@ -226,6 +226,34 @@ atlas_status autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev, 
     s = tune_one(mesh, ATLAS_OP_GRADIENT, in, nlev, dt, grad, st, &bl, &bt);
     if (s == ATLAS_OK) s = tune_one(mesh, ATLAS_OP_DIVERGENCE, grad, nlev, dt, out, st, &bd, &td);
     bt += td;
+    if (s == ATLAS_OK) {
+      // the two tuned passes against the fused one-pass form
+      MeshStore &m = *mesh->store;
+      LaunchShape win;
+      win.variant = ATLAS_VARIANT_COLUMN;
+      win.per_pass = 1;
+      if (m.d.l2_ok) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+          for (int b : {1024, 768}) {
+            const atlas_launch c{ATLAS_VARIANT_FUSED, b, 0, 0, 0, 0};
+            const float t = time_shape(mesh, op, in, nlev, dt, out, grad, c, st, e0, e1);
+            if (t >= 0.0f && t < bt) {
+              bt = t;
+              bl = c;
+              win = LaunchShape();
+              win.variant = ATLAS_VARIANT_FUSED;
+              win.block = b;
+              win.nodes_per_block = 0;
+            }
+          }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+      }
+      std::lock_guard<std::mutex> g(m.tune_mu);
+      m.tuned[TuneKey{(int)op, (int)dt, nlev}] = win;
+    }
     if (owned) {
       (void)hipStreamSynchronize(st);
       (void)hipFree(owned);

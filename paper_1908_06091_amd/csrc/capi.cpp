@@ -292,9 +292,9 @@ namespace atlasx {
 LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
                        atlas_dtype dt) {
   LaunchShape s = default_shape(m, op, nlev, dt);
-  if ((!l || l->variant == ATLAS_VARIANT_AUTO) && op != ATLAS_OP_LAPLACIAN) {
-    // an autotuned shape for this (op, dtype, nlev), if any (the Laplacian
-    // takes each pass's own shape, tuned or built in)
+  if (!l || l->variant == ATLAS_VARIANT_AUTO) {
+    // an autotuned shape for this (op, dtype, nlev), if any (for the
+    // Laplacian: the fused form, or the two passes each with its own shape)
     MeshStore &ms = const_cast<MeshStore &>(m);
     std::lock_guard<std::mutex> g(ms.tune_mu);
     auto it = ms.tuned.find(TuneKey{(int)op, (int)dt, nlev});

@@ -103,6 +103,9 @@ struct DevMesh {
   const int32_t *l2_glref = nullptr; // [kGRefs] per g record: references into f-runs
   const int32_t *l2_lref = nullptr;  // [I] references of own positions into g-runs
   const int32_t *l2_lself = nullptr; // [V] slot of position p in its g-run
+  int32_t l2_pmax = 0;               // most own positions of a tile on one parallel
+  const int4 *l2_ggeo = nullptr;     // packed gradient-node records (device-built)
+  const int4 *l2_lgeo = nullptr;     // packed own-position records (device-built)
 };
 
 // ------------------------------------------------------------- kernels
@@ -189,6 +192,9 @@ atlas_status derive_scales(MeshStore &m, const double *vol_by_pos,
                            const double *cos_by_pos, double radius);
 atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hipStream_t st);
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
+// Packs the fused Laplacian's geometry records of a mesh with a two-ring
+// plan of `ngrec` gradient records (after derive_scales).
+atlas_status pack_lapl_geometry(MeshStore &m, int64_t ngrec);
 // The shape a call with launch `l` (NULL: tuned, else built-in) runs with.
 LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
                        atlas_dtype dt);

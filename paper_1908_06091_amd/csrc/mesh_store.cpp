@@ -264,7 +264,7 @@ struct LaplPlan {
   std::vector<int32_t> glref;     // per g record: kGRefs references into the f-runs
   std::vector<int32_t> lref;      // per incidence (own positions): into the g-runs
   std::vector<int32_t> lself;     // per position: slot in its g-run
-  int32_t fmax = 0, gmax = 0;
+  int32_t fmax = 0, gmax = 0, pmax = 0;
 };
 
 static bool cyclic_run(std::vector<int32_t> &a, int32_t nx, int32_t &lo, int32_t &len) {
@@ -369,6 +369,7 @@ static bool lapl_plan(const std::vector<int64_t> &off, const std::vector<int32_t
       const int32_t nx = (int32_t)(off[rlo + q + 1] - off[rlo + q]);
       lp.fmax = std::max(lp.fmax, flen[q]);
       lp.gmax = std::max(lp.gmax, glen[q]);
+      lp.pmax = std::max(lp.pmax, pos[q].y - pos[q].x);
       lp.fseg.push_back(make_int4((int32_t)off[rlo + q], nx, flo[q], flen[q]));
       lp.gseg.push_back(make_int4(glo[q], glen[q], (int32_t)lp.gnode.size(), 0));
       lp.seg_pos.push_back(pos[q]);
@@ -519,6 +520,7 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->d.l2_ok = l2_ok ? 1 : 0;
   m->d.l2_fmax = lp.fmax;
   m->d.l2_gmax = lp.gmax;
+  m->d.l2_pmax = lp.pmax;
   const double *vol_d = nullptr, *cos_pd = nullptr;
   std::vector<double> zeros(V, 0.0);
   if ((st = upload_array(*m, perm, &m->d.perm)) != ATLAS_OK ||
@@ -565,6 +567,10 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
     return st;
   }
   if ((st = derive_scales(*m, vol_d, cos_pd, d->radius)) != ATLAS_OK) {
+    delete m;
+    return st;
+  }
+  if (l2_ok && (st = pack_lapl_geometry(*m, (int64_t)lp.gnode.size())) != ATLAS_OK) {
     delete m;
     return st;
   }

@@ -1173,6 +1173,400 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused Laplacian: one pass over the two-ring plan.  A workgroup owns one
+// tile and one chunk of lane vectors and walks the tile's window of
+// parallels.  At step q it forms the gradient at every node of the g-run of
+// parallel q from the field runs q-1, q, q+1 (LDS) into a 4-slot LDS ring,
+// and the divergence of those gradients at the tile's own positions of
+// parallel q-2 from the g-runs q-3, q-2, q-1 (the ring slot written at step
+// q held the g-run of q-4, last read at step q-1).  Meanwhile it loads the
+// field run of parallel q+2 and the packed geometry of step q+1 (records of
+// the g-run q+1 and of the own positions of parallel q-1) into registers
+// and deposits them in LDS after the compute, so the compute reads nothing
+// but LDS.  Every gradient goes through the gradient policy and is rounded
+// to its output type exactly as the two-pass form stores it, and every
+// divergence through the divergence policy: the result is bitwise that of
+// the two passes.
+// ---------------------------------------------------------------------------
+constexpr int kGGeoWords = 10;  // packed gradient-node record (16-byte words):
+                                // S[6], refs[8], (alpha, beta), (f self, n)
+constexpr int kLGeoWords = 13;  // packed own-position record: S[6], refs[8],
+                                // ncos[6], (alpha, cos lat), (node, n, g self)
+constexpr int kGeoEpt = 2;      // geometry words a thread stages per step
+constexpr int kLsweepEpt = 2;   // field lane vectors a thread stages per step
+
+__device__ __forceinline__ int4 cst_int4(const int4 *p, size_t i) {
+  const ATLASX_CST int *d = cst(reinterpret_cast<const int *>(p));
+  return make_int4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
+}
+__device__ __forceinline__ int2 cst_int2(const int2 *p, size_t i) {
+  const ATLASX_CST int *d = cst(reinterpret_cast<const int *>(p));
+  return make_int2(d[2 * i], d[2 * i + 1]);
+}
+
+template <class T, int NV, int EPT, int NPW>
+__global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict__ in,
+                                                 T *__restrict__ out, int nlev, int vpc,
+                                                 int ntiles, int per_xcd) {
+  using PG = Pol<T, OP_GRAD>;
+  using PD = Pol<T, OP_DIV>;
+  using LF = LaneVec<T, NV>;
+  using RF = typename LF::raw;         // NV levels of the field
+  using GV = typename PD::V;           // gradient (zonal, meridional) of one level
+  using LG = LaneVec<GV, NV>;
+  using RG = typename LG::raw;         // NV levels of the gradient
+  static_assert(sizeof(typename PG::Out) == sizeof(GV), "gradient output type");
+  constexpr int G = 6;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int fmax = m.l2_fmax, gmax = m.l2_gmax;
+  const int gw = gmax * kGGeoWords;                          // g part of a geometry slot
+  const int geo_stride = gw + m.l2_pmax * kLGeoWords;        // words per geometry slot
+  // the gradient ring holds each lane vector as two planes of its first
+  // and second half (consecutive lanes then read consecutive 16-byte words)
+  static_assert(sizeof(RG) == 2 * sizeof(RF), "gradient lane vector = two field lane vectors");
+  RF *fbuf = reinterpret_cast<RF *>(smem_raw);               // [4][fmax][vpc]
+  RF *gbuf = fbuf + 4 * fmax * vpc;                          // [4][gmax][2][vpc]
+  i32x4 *geo = reinterpret_cast<i32x4 *>(gbuf + 8 * gmax * vpc);  // [2][geo_stride]
+  const int fstride = fmax * vpc, gstride = 2 * gmax * vpc;
+  auto gload = [&](int at) {  // at: ring slot offset + node * 2 * vpc + lane vector
+    RG r;
+    __builtin_memcpy(&r, &gbuf[at], sizeof(RF));
+    __builtin_memcpy(reinterpret_cast<char *>(&r) + sizeof(RF), &gbuf[at + vpc], sizeof(RF));
+    return r;
+  };
+  const int u = xcd_tile(blockIdx.x, per_xcd);
+  const int c = u / ntiles;
+  const int tile = u - c * ntiles;
+  const int nvec = (nlev + NV - 1) / NV;
+  const int v0 = c * vpc;
+  if (v0 >= nvec) return;
+  const int nvc = min(vpc, nvec - v0);
+  const int k0 = cst(m.l2_tile_seg)[tile];
+  const int W = cst(m.l2_tile_seg)[tile + 1] - k0;
+  const size_t L = (size_t)nlev;
+  const uint32_t col_bytes = (uint32_t)(L * sizeof(T));
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  auto first = [&](int k) { return min(NV * (v0 + k), nlev - NV); };
+
+  // ---- field runs: item = (node t of the run, lane vector k); a thread's
+  // items are the same every step
+  RF regs[EPT];
+  int it_t[EPT], it_off[EPT], it_lds[EPT];  // it_off: byte offset of (t, k) from the run start
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int i = threadIdx.x + e * (int)blockDim.x;
+    const int t = i / nvc, k = i - t * nvc;
+    it_t[e] = t;
+    it_off[e] = t * (int)col_bytes + first(k) * (int)sizeof(T);
+    it_lds[e] = t * vpc + k;
+  }
+  int run_len = 0;
+  auto fetch = [&](int q) {
+    const int4 f = cst_int4(m.l2_fseg, k0 + q);  // {ring offset, ring size, first, length}
+    run_len = f.w;
+    const i32x4 rs = make_rsrc(in + (size_t)f.x * L, (uint32_t)f.y * col_bytes);
+    const int start = f.z * (int)col_bytes, wrap = f.y * (int)col_bytes;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      int off = start + it_off[e];
+      if (off >= wrap) off -= wrap;  // the run wraps round the parallel
+      regs[e] = buf_load<RF>(rs, it_t[e] < run_len ? off : kBufOff);
+    }
+  };
+  auto deposit = [&](int q) {
+    RF *b = fbuf + (q & 3) * fstride;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (it_t[e] < run_len) b[it_lds[e]] = regs[e];
+  };
+  // ---- packed geometry of step q: the g-run records of parallel q (words
+  // [0, glen * kGGeoWords)) and the own-position records of parallel q - 2
+  // (from word gw on), into slot q & 1
+  // On deposit, the references of a record become LDS element offsets for
+  // the step it serves (ring slot and run slot resolved, the pole flag
+  // kept), and the self slots likewise, so the compute adds only the lane.
+  // A thread's geometry items are fixed: item i < gw is word i % kGGeoWords
+  // of g record i / kGGeoWords; item gw + j is word j % kLGeoWords of own
+  // position record j / kLGeoWords.
+  i32x4 greg[kGeoEpt];
+  int gdst[kGeoEpt], gkind[kGeoEpt];  // kind: 0 plain, 1 f-refs, 2 f-self, 3 g-refs, 4 g-self
+  int grec[kGeoEpt], gword[kGeoEpt];  // record index (-1: none) and word
+  bool gisg[kGeoEpt], gon[kGeoEpt];
+#pragma unroll
+  for (int e = 0; e < kGeoEpt; ++e) {
+    const int i = threadIdx.x + e * (int)blockDim.x;
+    gdst[e] = i;
+    gisg[e] = i < gw;
+    if (i < gw) {
+      grec[e] = i / kGGeoWords;
+      gword[e] = i - grec[e] * kGGeoWords;
+      gkind[e] = (gword[e] == 6 || gword[e] == 7) ? 1 : (gword[e] == 9) ? 2 : 0;
+    } else if (i < geo_stride) {
+      grec[e] = (i - gw) / kLGeoWords;
+      gword[e] = (i - gw) - grec[e] * kLGeoWords;
+      gkind[e] = (gword[e] == 6 || gword[e] == 7) ? 3 : (gword[e] == 12) ? 4 : 0;
+    } else {
+      grec[e] = -1;
+      gword[e] = 0;
+      gkind[e] = 0;
+    }
+    gon[e] = false;
+  }
+  auto fref = [&](int r, int qq) {
+    const int l = r & ~kLrefPole;
+    return (r & kLrefPole) | (((qq + ((l >> 16) & 3) - 1) & 3) * fstride + (l & 0xffff) * vpc);
+  };
+  auto gref = [&](int r, int qq) {
+    const int l = r & ~kLrefPole;
+    return (r & kLrefPole) | (((qq + ((l >> 16) & 3) - 1) & 3) * gstride + (l & 0xffff) * 2 * vpc);
+  };
+  auto fetch_geo = [&](int q) {
+    int ng = 0, gb = 0, p0 = 0, np = 0;  // records of each kind this step
+    if (q < W) {
+      const int4 gs = cst_int4(m.l2_gseg, k0 + q);
+      ng = gs.y;
+      gb = gs.z;
+    }
+    if (q >= 2 && q - 2 < W) {
+      const int2 sp = cst_int2(m.l2_seg_pos, k0 + q - 2);
+      p0 = sp.x;
+      np = sp.y - sp.x;
+    }
+#pragma unroll
+    for (int e = 0; e < kGeoEpt; ++e) {
+      gon[e] = grec[e] >= 0 && grec[e] < (gisg[e] ? ng : np);
+      if (gon[e]) {
+        const int4 *src = gisg[e] ? m.l2_ggeo + (size_t)(gb + grec[e]) * kGGeoWords
+                                  : m.l2_lgeo + (size_t)(p0 + grec[e]) * kLGeoWords;
+        greg[e] = *reinterpret_cast<const i32x4 *>(src + gword[e]);
+      }
+    }
+  };
+  auto deposit_geo = [&](int q) {  // records of step q: g-run q, own positions of q - 2
+    i32x4 *g = geo + (q & 1) * geo_stride;
+#pragma unroll
+    for (int e = 0; e < kGeoEpt; ++e) {
+      if (!gon[e]) continue;
+      i32x4 v = greg[e];
+      if (gkind[e] == 1) {
+        v.x = fref(v.x, q); v.y = fref(v.y, q); v.z = fref(v.z, q); v.w = fref(v.w, q);
+      } else if (gkind[e] == 2) {
+        v.x = (q & 3) * fstride + v.x * vpc;
+      } else if (gkind[e] == 3) {
+        v.x = gref(v.x, q - 2); v.y = gref(v.y, q - 2); v.z = gref(v.z, q - 2); v.w = gref(v.w, q - 2);
+      } else if (gkind[e] == 4) {
+        v.z = ((q - 2) & 3) * gstride + v.z * 2 * vpc;
+      }
+      g[gdst[e]] = v;
+    }
+  };
+
+  for (int q = 0; q < min(W, 2); ++q) {
+    fetch(q);
+    deposit(q);
+  }
+  fetch_geo(0);
+  deposit_geo(0);
+  __syncthreads();
+
+  // NPW nodes per wavefront: its lanes split into NPW groups of 64 / NPW,
+  // one node each (the chunk has at most 64 / NPW lane vectors)
+  constexpr int LPN = 64 / NPW;
+  const int sub = lane / LPN;
+  const int hl = lane - sub * LPN;
+  const int kc = min(hl, nvc - 1);  // lanes past the chunk read a valid entry
+  const int s_l = first(kc);
+  const bool lane_on = hl < nvc;
+  for (int q = 0; q < W + 2; ++q) {
+    const bool pf = q + 2 < W;
+    if (pf) fetch(q + 2);
+    const bool gf = q + 1 < W + 2;
+    if (gf) fetch_geo(q + 1);
+    const i32x4 *gq = geo + (q & 1) * geo_stride;
+    // ---- gradients at the g-run of parallel q
+    if (q < W) {
+      const int glen = cst_int4(m.l2_gseg, k0 + q).y;
+      for (int s = NPW * wave + sub; s < glen; s += NPW * nw) {
+        const i32x4 *r = gq + s * kGGeoWords;
+        double2 S[G];
+        int lr[8];
+#pragma unroll
+        for (int j = 0; j < G; ++j) __builtin_memcpy(&S[j], &r[j], 16);
+        {
+          const i32x4 a = r[6], b = r[7];
+          lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
+          lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
+        }
+        double al, be;
+        {
+          const i32x4 w8 = r[8];
+          const int a2[2] = {w8.x, w8.y}, b2[2] = {w8.z, w8.w};
+          __builtin_memcpy(&al, a2, 8);
+          __builtin_memcpy(&be, b2, 8);
+        }
+        const i32x4 w9 = r[9];
+        const int fself = w9.x, n = w9.y;  // fself: LDS offset
+        typename PG::St st[NV];
+        {
+          const RF xi = fbuf[fself + kc];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) PG::init(st[v], LF::get(xi, v), 0.0);
+        }
+        RF xn[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) xn[j] = fbuf[(lr[j] & ~kLrefPole) + kc];
+        double cx = 0.0, cy = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          const bool pole = (lr[j] & kLrefPole) != 0;
+          if (j < kMinRow) {  // present in every row, never the pole edge
+            closure_add<OP_GRAD>(cx, cy, S[j], false);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) PG::add(st[v], LF::get(xn[j], v), S[j], false, 0.0);
+            continue;
+          }
+          const bool use = j < n;
+          double tx = cx, ty = cy;
+          closure_add<OP_GRAD>(tx, ty, S[j], pole);
+          cx = use ? tx : cx;
+          cy = use ? ty : cy;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            typename PG::St tt = st[v];
+            PG::add(tt, LF::get(xn[j], v), S[j], pole, 0.0);
+            PG::keep(st[v], tt, use);
+          }
+        }
+        RG g;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const typename PG::Out o = PG::result(st[v], al, be, cx, cy, 0.0);
+          g.e[2 * v] = o.x;
+          g.e[2 * v + 1] = o.y;
+        }
+        if (lane_on) {
+          RF *d = gbuf + (q & 3) * gstride + s * 2 * vpc + kc;
+          __builtin_memcpy(d, &g, sizeof(RF));
+          __builtin_memcpy(d + vpc, reinterpret_cast<const char *>(&g) + sizeof(RF), sizeof(RF));
+        }
+      }
+    }
+    // ---- Laplacian at the own positions of parallel q - 2
+    if (q >= 2) {
+      const int q2 = q - 2;
+      const int2 sp = cst_int2(m.l2_seg_pos, k0 + q2);
+      for (int t = NPW * wave + sub; t < sp.y - sp.x; t += NPW * nw) {
+        const i32x4 *r = gq + gw + t * kLGeoWords;
+        double2 S[G];
+        int lr[8];
+        double cn[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) __builtin_memcpy(&S[j], &r[j], 16);
+        {
+          const i32x4 a = r[6], b = r[7];
+          lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
+          lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) __builtin_memcpy(&cn[2 * k], &r[8 + k], 16);
+        double al, ci;
+        {
+          const i32x4 w11 = r[11];
+          const int a2[2] = {w11.x, w11.y}, c2[2] = {w11.z, w11.w};
+          __builtin_memcpy(&al, a2, 8);
+          __builtin_memcpy(&ci, c2, 8);
+        }
+        const i32x4 w12 = r[12];
+        const int node = w12.x, n = w12.y, self = w12.z;  // self: LDS offset
+        typename PD::St st[NV];
+        {
+          const RG gi = gload(self + kc);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) PD::init(st[v], LG::get(gi, v), ci);
+        }
+        RG gn[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) gn[j] = gload((lr[j] & ~kLrefPole) + kc);
+        double cx = 0.0, cy = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          const bool pole = (lr[j] & kLrefPole) != 0;
+          if (j < kMinRow) {
+            closure_add<OP_DIV>(cx, cy, S[j], false);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) PD::add(st[v], LG::get(gn[j], v), S[j], false, cn[j]);
+            continue;
+          }
+          const bool use = j < n && !pole;
+          double tx = cx, ty = cy;
+          closure_add<OP_DIV>(tx, ty, S[j], pole);
+          cx = use ? tx : cx;
+          cy = use ? ty : cy;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            typename PD::St tt = st[v];
+            PD::add(tt, LG::get(gn[j], v), S[j], pole, cn[j]);
+            PD::keep(st[v], tt, use);
+          }
+        }
+        constexpr int WD = NV * (int)sizeof(T) / 4;
+        int w[WD];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T o = PD::result(st[v], al, 0.0, cx, cy, ci);
+          __builtin_memcpy(&w[v * (int)sizeof(T) / 4], &o, sizeof(T));
+        }
+        if constexpr (NPW == 1) {
+          // one node per wavefront: a buffer store over the node's row (the
+          // resource is wavefront-uniform)
+          const i32x4 ro = make_rsrc(out + (size_t)node * L, (uint32_t)(L * sizeof(T)));
+          buf_store_words<WD>(w, ro, lane_on ? s_l * (int)sizeof(T) : kBufOff);
+        } else if (lane_on) {
+          // several nodes per wavefront: a plain store through each lane's
+          // own address
+          struct Words { int v[WD]; } o;
+          __builtin_memcpy(o.v, w, sizeof(o));
+          *reinterpret_cast<Words *>(out + (size_t)node * L + s_l) = o;
+        }
+      }
+    }
+    if (pf) deposit(q + 2);
+    if (gf) deposit_geo(q + 1);
+    __syncthreads();
+  }
+}
+
+// Packs the fused Laplacian's per-record geometry (after the scales are
+// derived): gradient-node records in g-record order, own-position records
+// in position order.
+__global__ void k_pack_ggeo(DevMesh m, int ng, i32x4 *__restrict__ dst) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const int4 gn = m.l2_gnode[g];  // {row start, row length, f self, position}
+  i32x4 *o = dst + (size_t)g * kGGeoWords;
+  for (int j = 0; j < 6; ++j) __builtin_memcpy(&o[j], &m.S[gn.x + j], 16);
+  __builtin_memcpy(&o[6], m.l2_glref + (size_t)g * kGRefs, 32);
+  const PosRec pr = m.pos[gn.w];
+  const double ab[2] = {pr.alpha, pr.beta};
+  __builtin_memcpy(&o[8], ab, 16);
+  o[9] = i32x4{gn.z, gn.y, 0, 0};
+}
+__global__ void k_pack_lgeo(DevMesh m, i32x4 *__restrict__ dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m.V) return;
+  const PosRec pr = m.pos[p];
+  i32x4 *o = dst + (size_t)p * kLGeoWords;
+  for (int j = 0; j < 6; ++j) __builtin_memcpy(&o[j], &m.S[pr.r0 + j], 16);
+  __builtin_memcpy(&o[6], m.l2_lref + pr.r0, 32);
+  __builtin_memcpy(&o[8], m.ncos + pr.r0, 48);
+  const double ac[2] = {pr.alpha, m.coslat[pr.node]};
+  __builtin_memcpy(&o[11], ac, 16);
+  o[12] = i32x4{pr.node, pr.r1 - pr.r0, m.l2_lself[p], 0};
+}
+
 template <class T, int OP>
 __global__ void __launch_bounds__(1024) k_flat(DevMesh m, const T *__restrict__ in,
                                                T *__restrict__ out, int nlev, int npb,
@@ -1519,6 +1913,27 @@ __global__ void k_derive_scales(int V, const double *__restrict__ vol,
   }
 }
 
+atlas_status pack_lapl_geometry(MeshStore &m, int64_t ngrec) {
+  void *g = nullptr, *l = nullptr;
+  const size_t gb = std::max<size_t>(16, (size_t)ngrec * kGGeoWords * 16);
+  const size_t lb = std::max<size_t>(16, (size_t)m.d.V * kLGeoWords * 16);
+  if (hipMalloc(&g, gb) != hipSuccess) return fail(ATLAS_ENOMEM, "hipMalloc of mesh store failed");
+  m.allocations.push_back(g);
+  if (hipMalloc(&l, lb) != hipSuccess) return fail(ATLAS_ENOMEM, "hipMalloc of mesh store failed");
+  m.allocations.push_back(l);
+  m.bytes += gb + lb;
+  if (ngrec > 0)
+    hipLaunchKernelGGL(k_pack_ggeo, dim3((unsigned)((ngrec + 255) / 256)), dim3(256), 0, 0, m.d,
+                       (int)ngrec, static_cast<i32x4 *>(g));
+  if (m.d.V > 0)
+    hipLaunchKernelGGL(k_pack_lgeo, dim3((m.d.V + 255) / 256), dim3(256), 0, 0, m.d,
+                       static_cast<i32x4 *>(l));
+  ATLASX_HIP(hipGetLastError());
+  m.d.l2_ggeo = static_cast<const int4 *>(g);
+  m.d.l2_lgeo = static_cast<const int4 *>(l);
+  return ATLAS_OK;
+}
+
 atlas_status derive_scales(MeshStore &m, const double *vol_by_pos, const double *cos_by_pos,
                            double radius) {
   const int V = m.d.V;
@@ -1554,6 +1969,15 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   s.nodes_per_block = s.variant == ATLAS_VARIANT_COLUMN ? 16 : 0;
   s.level_vec = 0;
   if (op == ATLAS_OP_LAPLACIAN) {
+    // FP64 on large meshes: the fused one-pass form (it moves a third of the
+    // two passes' field bytes; in FP32 the two passes are still faster)
+    if (dt == ATLAS_F64 && nlev >= 48 && m.d.l2_ok && m.d.ntiles >= kSweepMinTiles &&
+        m.d.maxdeg <= 6 && m.d.mindeg >= kMinRow) {
+      s.variant = ATLAS_VARIANT_FUSED;
+      s.block = 1024;
+      s.nodes_per_block = 0;
+      return s;
+    }
     s.per_pass = 1;
     return s;
   }
@@ -1765,6 +2189,8 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       hipLaunchKernelGGL(kern, dim3(per * 8), block, lds, st, m, in, out, nlev, kc, m.ntiles, per);
       break;
     }
+    case ATLAS_VARIANT_FUSED:
+      return fail(ATLAS_EINVAL, "the fused variant is for the Laplacian only");
     default:
       return fail(ATLAS_EINVAL, "unknown launch variant");
   }
@@ -1796,8 +2222,77 @@ static LaunchShape pass_shape(const MeshStore &ms, atlas_op op, int nlev, atlas_
 
 // Laplacian: gradient into the workspace [V][nlev][2], then its divergence;
 // the flux form needs its flux buffer behind the gradient.
+// The fused Laplacian on the two-ring plan.  *ran = false (nothing
+// launched) where the plan or the kernel's assumptions do not hold: no
+// plan, rows outside 4..6 incidences, or a block too small for the staging.
+template <class T>
+atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *out,
+                               const LaunchShape &sh, hipStream_t st, bool *ran) {
+  const DevMesh &m = ms.d;
+  *ran = false;
+  if (!m.l2_ok || m.maxdeg > 6 || m.mindeg < kMinRow) return ATLAS_OK;
+  constexpr int NVW = (int)(16 / sizeof(T));  // 16-byte field lanes
+  const int nv = (nlev >= NVW && sh.level_vec != 1) ? NVW : 1;
+  const int nvec = (nlev + nv - 1) / nv;
+  const size_t fb = (size_t)nv * sizeof(T), gb = 2 * fb;  // lane-vector bytes
+  const size_t per_vec = 4 * (size_t)m.l2_fmax * fb + 4 * (size_t)m.l2_gmax * gb;
+  // two slots of packed geometry; a thread stages at most kGeoEpt words
+  const size_t geo_words = (size_t)m.l2_gmax * kGGeoWords + (size_t)m.l2_pmax * kLGeoWords;
+  const size_t geo = 2 * geo_words * 16;
+  if (geo_words > (size_t)kGeoEpt * sh.block) return ATLAS_OK;
+  int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + nv - 1) / nv) : 64;
+  vpc = min(vpc, nvec);
+  {
+    const int nchunk = (nvec + vpc - 1) / vpc;
+    vpc = (nvec + nchunk - 1) / nchunk;
+  }
+  // the chunk shrinks until both rings fit in LDS and a field run fits the
+  // staging registers (kLsweepEpt lane vectors per thread)
+  while (vpc > 1 && (per_vec * vpc + geo > kMaxLds ||
+                     ((size_t)m.l2_fmax * vpc + sh.block - 1) / sh.block > (size_t)kLsweepEpt))
+    vpc = (vpc + 1) / 2;
+  if (per_vec * vpc + geo > kMaxLds ||
+      ((size_t)m.l2_fmax * vpc + sh.block - 1) / sh.block > (size_t)kLsweepEpt)
+    return ATLAS_OK;
+  const int nchunk = (nvec + vpc - 1) / vpc;
+  const size_t lds = per_vec * vpc + geo;
+  const int units = m.ntiles * nchunk;
+  const int per = (units + 7) / 8;
+  // several nodes per wavefront when the chunk fills at most half or a
+  // quarter of it
+  void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
+  if (nv == 1)
+    kern = vpc <= 16 ? k_lsweep<T, 1, kLsweepEpt, 4>
+           : vpc <= 32 ? k_lsweep<T, 1, kLsweepEpt, 2> : k_lsweep<T, 1, kLsweepEpt, 1>;
+  else
+    kern = vpc <= 16 ? k_lsweep<T, NVW, kLsweepEpt, 4>
+           : vpc <= 32 ? k_lsweep<T, NVW, kLsweepEpt, 2> : k_lsweep<T, NVW, kLsweepEpt, 1>;
+  ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3(per * 8), dim3(sh.block), lds, st, m, in, out, nlev, vpc,
+                     m.ntiles, per);
+  ATLASX_HIP(hipGetLastError());
+  *ran = true;
+  return ATLAS_OK;
+}
+
 atlas_status launch_op(const MeshStore &ms, atlas_op op, atlas_dtype dt, const void *in,
                        int nlev, void *out, void *ws, const LaunchShape &sh, hipStream_t st) {
+  if (op == ATLAS_OP_LAPLACIAN && sh.variant == ATLAS_VARIANT_FUSED) {
+    bool ran = false;
+    const atlas_status s =
+        dt == ATLAS_F64
+            ? launch_lapl_fused<double>(ms, static_cast<const double *>(in), nlev,
+                                        static_cast<double *>(out), sh, st, &ran)
+            : launch_lapl_fused<float>(ms, static_cast<const float *>(in), nlev,
+                                       static_cast<float *>(out), sh, st, &ran);
+    if (s != ATLAS_OK || ran) return s;
+    // otherwise the two passes with their built-in shapes (same results)
+    LaunchShape two = sh;
+    two.variant = ATLAS_VARIANT_COLUMN;
+    two.per_pass = 1;
+    return launch_op(ms, op, dt, in, nlev, out, ws, two, st);
+  }
   if (op == ATLAS_OP_LAPLACIAN) {
     const size_t w = dt == ATLAS_F64 ? 8 : 4;
     char *grad = static_cast<char *>(ws);
