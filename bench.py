@@ -410,6 +410,8 @@ def main():
     def alg_bytes(op, w):
         if op == "lapl":
             return 6 * V * nlev * w + 2 * geo
+        if op == "divcurl":  # (u, v) read once, two scalar outputs
+            return 4 * V * nlev * w + geo
         return 3 * V * nlev * w + geo
 
     # headline: FP64 gradient
@@ -426,10 +428,15 @@ def main():
     if not args.no_extra_ops:
         f32, uv32 = f64.float(), uv64.float()
         for name, dt, fn_in, w in (("div_f64", "f64", uv64, 8), ("lapl_f64", "f64", f64, 8),
-                                   ("curl_f64", "f64", uv64, 8), ("grad_f32", "f32", f32, 4),
-                                   ("div_f32", "f32", uv32, 4), ("lapl_f32", "f32", f32, 4)):
+                                   ("curl_f64", "f64", uv64, 8), ("divcurl_f64", "f64", uv64, 8),
+                                   ("grad_f32", "f32", f32, 4), ("div_f32", "f32", uv32, 4),
+                                   ("lapl_f32", "f32", f32, 4), ("divcurl_f32", "f32", uv32, 4)):
             opname = name.split("_")[0]
-            if opname == "grad":
+            if opname == "divcurl":
+                o = (torch.empty(V, nlev, dtype=fn_in.dtype, device=dev),
+                     torch.empty(V, nlev, dtype=fn_in.dtype, device=dev))
+                fn = lambda o=o, x=fn_in: gm.div_curl(x, out_div=o[0], out_curl=o[1])
+            elif opname == "grad":
                 o = torch.empty(V, nlev, 2, dtype=fn_in.dtype, device=dev)
                 fn = lambda o=o, x=fn_in: gm.gradient(x, out=o)
             elif opname == "div":
@@ -443,7 +450,8 @@ def main():
                 fn = lambda o=o, x=fn_in: gm.laplacian(x, out=o)
             t = time_op(fn, max(5, args.steps // 2), 2, torch)
             b = alg_bytes(opname, w)
-            ops[name] = {"ms": round(t, 4), "edge_level_per_s": E * nlev / (t * 1e-3),
+            napp = 2 if opname == "divcurl" else 1  # operator applications per call
+            ops[name] = {"ms": round(t, 4), "edge_level_per_s": napp * E * nlev / (t * 1e-3),
                          "GBps": round(b / (t * 1e-3) / 1e9, 1),
                          "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             if opname == "lapl":

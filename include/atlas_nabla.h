@@ -188,6 +188,16 @@ atlas_status atlas_nabla_divergence(atlas_mesh_t mesh, const void *uv,
                                     hipStream_t stream);
 atlas_status atlas_nabla_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
                               atlas_dtype dtype, void *out, hipStream_t stream);
+/* Divergence and curl of the same (u, v) field in one pass (Section 4.7:
+ * both operators of one Nabla object applied to one field): the field is
+ * read once and each output is bitwise the result of its own entry point.
+ * out_div and out_curl: [V][nlev] each, caller-owned, disjoint from each
+ * other and from uv.  Short columns (nlev < 48) and meshes outside the
+ * level-vector form run the two operators one after the other.  Errors: as
+ * atlas_nabla_divergence, and ATLAS_EINVAL for overlapping outputs. */
+atlas_status atlas_nabla_div_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
+                                  atlas_dtype dtype, void *out_div, void *out_curl,
+                                  hipStream_t stream);
 /* workspace: device buffer of atlas_laplacian_workspace_bytes() bytes, or
  * NULL to use a workspace the mesh keeps (grown on first use with
  * hipMalloc; calls that share it on different streams must be ordered by

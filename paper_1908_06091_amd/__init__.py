@@ -222,6 +222,18 @@ class Mesh:
                                           _dev_ptr(out, "out"), _stream(stream)))
         return out
 
+    def div_curl(self, uv, out_div=None, out_curl=None, stream=None):
+        """Divergence and curl of one (u, v) field in one pass."""
+        nlev = self._nlev_vector(uv)
+        if out_div is None:
+            out_div = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        if out_curl is None:
+            out_curl = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        _check(self._lib.atlas_nabla_div_curl(self._h, _dev_ptr(uv, "uv"), nlev, _dtype_code(uv),
+                                              _dev_ptr(out_div, "out_div"),
+                                              _dev_ptr(out_curl, "out_curl"), _stream(stream)))
+        return out_div, out_curl
+
     def laplacian(self, f, out=None, workspace=None, stream=None):
         nlev = self._nlev_scalar(f)
         if out is None:

@@ -125,6 +125,9 @@ SIGNATURES = {
                                               ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "atlas_nabla_curl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_nabla_div_curl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "atlas_nabla_laplacian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]),

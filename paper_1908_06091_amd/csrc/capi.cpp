@@ -258,6 +258,19 @@ atlas_status atlas_nabla_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
   return apply(mesh, ATLAS_OP_CURL, uv, nlev, dtype, out, nullptr, nullptr, stream);
 }
 
+atlas_status atlas_nabla_div_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
+                                  atlas_dtype dtype, void *out_div, void *out_curl,
+                                  hipStream_t stream) {
+  atlas_status st = check_call(mesh, ATLAS_OP_DIVERGENCE, uv, nlev, dtype, out_div);
+  if (st != ATLAS_OK) return st;
+  st = check_call(mesh, ATLAS_OP_CURL, uv, nlev, dtype, out_curl);
+  if (st != ATLAS_OK) return st;
+  const MeshStore &m = *mesh->store;
+  const size_t ob = out_bytes(m, ATLAS_OP_DIVERGENCE, nlev, dtype);
+  if (overlap(out_div, ob, out_curl, ob)) return fail(ATLAS_EINVAL, "the two outputs overlap");
+  return launch_div_curl(m, dtype, uv, nlev, out_div, out_curl, stream);
+}
+
 atlas_status atlas_nabla_laplacian(atlas_mesh_t mesh, const void *f, int32_t nlev,
                                    atlas_dtype dtype, void *out, void *workspace,
                                    hipStream_t stream) {

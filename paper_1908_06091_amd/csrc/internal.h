@@ -192,6 +192,9 @@ atlas_status derive_scales(MeshStore &m, const double *vol_by_pos,
                            const double *cos_by_pos, double radius);
 atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hipStream_t st);
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
+// Divergence and curl of one vector field (one read of the field).
+atlas_status launch_div_curl(const MeshStore &ms, atlas_dtype dt, const void *in, int nlev,
+                             void *out_div, void *out_curl, hipStream_t st);
 // Packs the fused Laplacian's geometry records of a mesh with a two-ring
 // plan of `ngrec` gradient records (after derive_scales).
 atlas_status pack_lapl_geometry(MeshStore &m, int64_t ngrec);

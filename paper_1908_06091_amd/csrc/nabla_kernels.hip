@@ -760,6 +760,133 @@ __global__ void __launch_bounds__(512)
   }
 }
 
+// Divergence and curl of one vector field in one pass: the column form of
+// colv_node with both operators' states fed from the same loads, so (u, v)
+// is read once and each output gets exactly the operation sequence of its
+// own operator (bitwise equal to the two separate calls).
+template <class T, int NV, int NCH>
+__device__ __forceinline__ void colv_node_dc(const DevMesh &m, const T *__restrict__ in,
+                                             T *__restrict__ out_d, T *__restrict__ out_c,
+                                             int nlev, const PosRec &pr, int lane) {
+  using PD = Pol<T, OP_DIV>;
+  using PC = Pol<T, OP_CURL>;
+  using V = typename PD::V;
+  using LV = LaneVec<V, NV>;
+  using R = typename LV::raw;
+  const V *vin = reinterpret_cast<const V *>(in);
+  const size_t L = (size_t)nlev;
+  const uint32_t col_bytes = (uint32_t)(L * sizeof(V));
+  const int node = pr.node, r0 = pr.r0, n = pr.r1 - pr.r0;
+  const int nvec = (nlev + NV - 1) / NV;
+  int s[NCH], off[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int idx = lane + 64 * c;
+    s[c] = min(NV * idx, nlev - NV);
+    off[c] = idx < nvec ? s[c] * (int)sizeof(V) : kBufOff;
+  }
+  const double ci = cst(m.coslat)[node];
+  typename PD::St sd[NCH][NV];
+  typename PC::St sc[NCH][NV];
+  {
+    const i32x4 rs = make_rsrc(vin + (size_t)node * L, col_bytes);
+    R xi[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) xi[c] = buf_load<R>(rs, off[c]);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        PD::init(sd[c][v], LV::get(xi[c], v), ci);
+        PC::init(sc[c][v], LV::get(xi[c], v), ci);
+      }
+  }
+  constexpr int G = 6;
+  uint32_t nb[G];
+  double2 S[G];
+  double cn[G];
+  R xn[G][NCH];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    nb[j] = (uint32_t)cst(m.nbr)[r0 + j];
+    S[j] = cst_double2(m.S, r0 + j);
+    cn[j] = cst(m.ncos)[r0 + j];
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const size_t q = nb[j] & ~kPoleBit;
+    const i32x4 rs = make_rsrc(vin + q * L, col_bytes);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) xn[j][c] = buf_load<R>(rs, off[c]);
+  }
+  double cx = 0.0, cy = 0.0;  // the same closure sums serve both operators
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const bool pole = (nb[j] & kPoleBit) != 0;
+    if (j < kMinRow) {
+      closure_add<OP_DIV>(cx, cy, S[j], false);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          PD::add(sd[c][v], LV::get(xn[j][c], v), S[j], false, cn[j]);
+          PC::add(sc[c][v], LV::get(xn[j][c], v), S[j], false, cn[j]);
+        }
+      continue;
+    }
+    const bool use = j < n && !pole;
+    double tx = cx, ty = cy;
+    closure_add<OP_DIV>(tx, ty, S[j], pole);
+    cx = use ? tx : cx;
+    cy = use ? ty : cy;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        typename PD::St td = sd[c][v];
+        PD::add(td, LV::get(xn[j][c], v), S[j], pole, cn[j]);
+        PD::keep(sd[c][v], td, use);
+        typename PC::St tc = sc[c][v];
+        PC::add(tc, LV::get(xn[j][c], v), S[j], pole, cn[j]);
+        PC::keep(sc[c][v], tc, use);
+      }
+  }
+  const double al = pr.alpha;
+  const i32x4 rd = make_rsrc(out_d + (size_t)node * L, (uint32_t)(L * sizeof(T)));
+  const i32x4 rc = make_rsrc(out_c + (size_t)node * L, (uint32_t)(L * sizeof(T)));
+  constexpr int W = NV * (int)sizeof(T) / 4;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    int wd[W], wc[W];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T a = PD::result(sd[c][v], al, 0.0, cx, cy, ci);
+      const T b = PC::result(sc[c][v], al, 0.0, cx, cy, ci);
+      __builtin_memcpy(&wd[v * (int)sizeof(T) / 4], &a, sizeof(T));
+      __builtin_memcpy(&wc[v * (int)sizeof(T) / 4], &b, sizeof(T));
+    }
+    const int ob = off[c] == kBufOff ? kBufOff : s[c] * (int)sizeof(T);
+    buf_store_words<W>(wd, rd, ob);
+    buf_store_words<W>(wc, rc, ob);
+  }
+}
+
+template <class T, int NV, int NCH>
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(colv_waves<NCH>(), colv_waves<NCH>())))
+    k_colv_dc(DevMesh m, const T *__restrict__ in, T *__restrict__ out_d,
+              T *__restrict__ out_c, int nlev, int npb, int per_xcd) {
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int p0, p1;
+  if (!tile_range(m, xcd_tile(blockIdx.x, per_xcd), npb, p0, p1)) return;
+  for (int p = p0 + wave; p < p1; p += nw) {
+    const PosRec pr = cst_pos(m.pos, p);
+    colv_node_dc<T, NV, NCH>(m, in, out_d, out_c, nlev, pr, lane);
+  }
+}
+
 // Levels per lane of the level-vector form for (T, OP, nlev).  FP64 (bound
 // by memory traffic): 16-byte lanes.  FP32 (its compensated sums make the
 // arithmetic the larger cost): the width (1..4 levels, at most 32 bytes per
@@ -2222,6 +2349,65 @@ static LaunchShape pass_shape(const MeshStore &ms, atlas_op op, int nlev, atlas_
 
 // Laplacian: gradient into the workspace [V][nlev][2], then its divergence;
 // the flux form needs its flux buffer behind the gradient.
+// Divergence and curl of one field in one pass (column form, level-vector
+// lanes of the divergence's automatic width).  Short columns (below 48
+// levels) and meshes outside the level-vector form run the two operators
+// one after the other with their own shapes (same results).
+template <class T>
+static atlas_status launch_div_curl_typed(const MeshStore &ms, atlas_dtype dt, const T *in,
+                                          int nlev, T *od, T *oc, hipStream_t st) {
+  const DevMesh &m = ms.d;
+  const int nv = nlev >= 48 ? auto_level_vec<T, OP_DIV>(nlev, m.maxdeg, m.mindeg) : 0;
+  if (nv == 0) {
+    for (atlas_op op : {ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL}) {
+      LaunchShape sh = shape_from(nullptr, ms, op, nlev, dt);
+      if (sh.variant == ATLAS_VARIANT_FLUX) sh = default_shape(ms, op, nlev, dt);
+      atlas_status s = launch_op(ms, op, dt, in, nlev, op == ATLAS_OP_CURL ? (void *)oc : (void *)od,
+                                 nullptr, sh, st);
+      if (s != ATLAS_OK) return s;
+    }
+    return ATLAS_OK;
+  }
+  const int nvec = (nlev + nv - 1) / nv, nch = (nvec + 63) / 64;
+  constexpr int kNpb = 16;
+  const int ntiles = (m.V + kNpb - 1) / kNpb;
+  const int per_xcd = (ntiles + 7) / 8;
+  void (*kern)(DevMesh, const T *, T *, T *, int, int, int) = nullptr;
+#define ATLASX_DC(NV)                                                  \
+  if constexpr (lane_vec_ok<T, OP_DIV, NV>()) {                          \
+    if (nch == 1) kern = k_colv_dc<T, NV, 1>;                            \
+    else if (nch == 2) kern = k_colv_dc<T, NV, 2>;                       \
+    else if (nch == 3) kern = k_colv_dc<T, NV, 3>;                       \
+    else kern = k_colv_dc<T, NV, 4>;                                     \
+  }
+  if (nv == 1) {
+    ATLASX_DC(1)
+  } else if (nv == 2) {
+    ATLASX_DC(2)
+  } else if (nv == 3) {
+    ATLASX_DC(3)
+  } else {
+    ATLASX_DC(4)
+  }
+#undef ATLASX_DC
+  if (!kern || nch > 4) return fail(ATLAS_EINVAL, "no level-vector width for this column");
+  hipLaunchKernelGGL(kern, dim3(per_xcd * 8), dim3(256), 0, st, m, in, od, oc, nlev, kNpb,
+                     per_xcd);
+  ATLASX_HIP(hipGetLastError());
+  return ATLAS_OK;
+}
+
+atlas_status launch_div_curl(const MeshStore &ms, atlas_dtype dt, const void *in, int nlev,
+                             void *out_div, void *out_curl, hipStream_t st) {
+  if (dt == ATLAS_F64)
+    return launch_div_curl_typed<double>(ms, dt, static_cast<const double *>(in), nlev,
+                                         static_cast<double *>(out_div),
+                                         static_cast<double *>(out_curl), st);
+  return launch_div_curl_typed<float>(ms, dt, static_cast<const float *>(in), nlev,
+                                      static_cast<float *>(out_div),
+                                      static_cast<float *>(out_curl), st);
+}
+
 // The fused Laplacian on the two-ring plan.  *ran = false (nothing
 // launched) where the plan or the kernel's assumptions do not hold: no
 // plan, rows outside 4..6 incidences, or a block too small for the staging.

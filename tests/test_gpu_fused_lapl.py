@@ -110,3 +110,40 @@ def test_fused_is_for_the_laplacian_only(P):
     x = torch.randn(gm.nnodes, 4, dtype=torch.float64, device="cuda")
     with pytest.raises(P.AtlasError, match="Laplacian only"):
         gm.apply(P.ATLAS_OP_GRADIENT, x, launch=_fused(P))
+
+
+# ---- divergence and curl in one pass (atlas_nabla_div_curl)
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nlev", [1, 47, 48, 64, 137, 300])
+@pytest.mark.parametrize("N", [2, 16, 48])
+def test_div_curl_equals_separate_calls(P, N, nlev, dtype):
+    """One read of (u, v), two outputs, each bitwise the separate operator's
+    result (which the parity tests pin to the oracle)."""
+    print(f"div_curl O{N} nlev={nlev} {dtype}", flush=True)
+    gm = _mesh(P, N)
+    uv = torch.randn(gm.nnodes, nlev, 2, dtype=dtype, device="cuda")
+    d, c = gm.div_curl(uv)
+    torch.cuda.synchronize()
+    assert torch.equal(d, gm.divergence(uv))
+    assert torch.equal(c, gm.curl(uv))
+
+
+def test_div_curl_against_oracle(P):
+    N, nlev = 24, 137
+    gm, om = _mesh(P, N), _oracle_mesh(N)
+    _, uv = make_inputs(om, nlev)
+    d, c = gm.div_curl(torch.from_numpy(uv).cuda())
+    torch.cuda.synchronize()
+    for got, op in ((d, "div"), (c, "curl")):
+        ref = oracle_apply(om, op, uv, nlev)
+        err, _ = normwise_error(got.cpu().numpy().reshape(ref.shape), ref)
+        assert err <= TOL["f64"], (op, err)
+
+
+def test_div_curl_rejects_overlapping_outputs(P):
+    gm = _mesh(P, 8)
+    uv = torch.randn(gm.nnodes, 4, 2, dtype=torch.float64, device="cuda")
+    o = torch.empty(gm.nnodes, 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.AtlasError, match="overlap"):
+        gm.div_curl(uv, out_div=o, out_curl=o)
