@@ -100,3 +100,27 @@ def test_o1280_l137_sampled(big, op, dtype):
     print(msg, flush=True)
     assert np.isfinite(got).all()
     assert emax <= TOL[dtype], (op, dtype, emax)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_o1280_l137_laplacian_forms_and_div_curl(big, dtype):
+    """At full size, in the shapes the benchmark times: the fused one-pass
+    Laplacian equals the two passes bit for bit, and the one-pass divergence
+    and curl equal the separate operators bit for bit (each of which the
+    sampled test above pins to the oracle)."""
+    P, gm = big["P"], big["gm"]
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    print(f"fullsize forms {dtype}", flush=True)
+    f = big["f"].to(dt)
+    one = gm.apply(P.ATLAS_OP_LAPLACIAN, f, launch=P.Launch(P.VARIANT_FUSED, 1024, 0, 0, 0, 0))
+    two = gm.apply(P.ATLAS_OP_LAPLACIAN, f, launch=P.Launch(P.VARIANT_COLUMN, 256, 16, 0, 0, 0))
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+    del one, two, f
+    uv = big["uv"].to(dt)
+    d, c = gm.div_curl(uv)
+    torch.cuda.synchronize()
+    assert torch.equal(d, gm.divergence(uv))
+    assert torch.equal(c, gm.curl(uv))
+    del d, c, uv
+    torch.cuda.empty_cache()
