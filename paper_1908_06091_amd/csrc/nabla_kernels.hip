@@ -1077,10 +1077,15 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
   R *buf = reinterpret_cast<R *>(smem_raw);                        // [4][segmax][vpc]
   i32x4 *gpos = reinterpret_cast<i32x4 *>(buf + 4 * segmax * vpc);  // [4][segmax][2]
   i32x4 *grow = gpos + 4 * segmax * 2;                              // [4][segmax][kGeoWords]
+  // chunk-minor order: the chunks of a tile run next to each other on one
+  // XCD, so the geometry and the cache lines a chunk boundary splits are
+  // fetched once into its L2
   const int u = xcd_tile(blockIdx.x, per_xcd);
-  const int c = u / ntiles;
-  const int tile = u - c * ntiles;
   const int nvec = (nlev + NV - 1) / NV;
+  const int nchunk = (nvec + vpc - 1) / vpc;
+  const int tile = u / nchunk;
+  const int c = u - tile * nchunk;
+  if (tile >= ntiles) return;
   const int v0 = c * vpc;
   if (v0 >= nvec) return;
   const int nvc = min(vpc, nvec - v0);  // lane vectors in this chunk
@@ -1362,10 +1367,14 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
     __builtin_memcpy(reinterpret_cast<char *>(&r) + sizeof(RF), &gbuf[at + vpc], sizeof(RF));
     return r;
   };
+  // chunk-minor order (as in k_sweepv): a tile's chunks share its geometry
+  // and boundary lines through one XCD's L2
   const int u = xcd_tile(blockIdx.x, per_xcd);
-  const int c = u / ntiles;
-  const int tile = u - c * ntiles;
   const int nvec = (nlev + NV - 1) / NV;
+  const int nchunk = (nvec + vpc - 1) / vpc;
+  const int tile = u / nchunk;
+  const int c = u - tile * nchunk;
+  if (tile >= ntiles) return;
   const int v0 = c * vpc;
   if (v0 >= nvec) return;
   const int nvc = min(vpc, nvec - v0);
