@@ -1322,11 +1322,43 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
 // the two passes.
 // ---------------------------------------------------------------------------
 constexpr int kGGeoWords = 10;  // packed gradient-node record (16-byte words):
-                                // S[6], refs[8], (alpha, beta), (f self, n)
-constexpr int kLGeoWords = 13;  // packed own-position record: S[6], refs[8],
-                                // ncos[6], (alpha, cos lat), (node, n, g self)
+                                // S[6] / 2, refs[8], (alpha, beta),
+                                // (f self, n, cos lat)
+constexpr int kLGeoWords = 13;  // packed own-position record: S[6] / 2,
+                                // refs[8], (alpha, cos lat), (node, n, g self),
+                                // ncos[6] (FP32 only: the FP64 kernel stages
+                                // the first kLGeoWords64 words)
+constexpr int kLGeoWords64 = 10;
 constexpr int kGeoEpt = 2;      // geometry words a thread stages per step
 constexpr int kLsweepEpt = 2;   // field lane vectors a thread stages per step
+
+// FP64 steps of the fused Laplacian with halved normals Sh = S / 2 (exact):
+// (xi + xn) Sh rounds like S (0.5 (xi + xn)), so these give the bits of
+// Pol<double, OP_GRAD>::add and PolDC64<OP_DIV>::add (operands not
+// subnormal).  For the divergence the second component arrives as
+// w = v cos(lat), the product PolDC64 forms from v and the node's cos(lat).
+__device__ __forceinline__ void grad_add_half(Pol<double, OP_GRAD>::St &s, double xn,
+                                              const double2 &Sh, bool pole) {
+  const double xe = s.xi + xn;
+  if (!pole) s.gl = s.gl + Sh.x * xe;
+  s.gt = s.gt + Sh.y * xe;
+}
+__device__ __forceinline__ void div_init_w(PolDC64<OP_DIV>::St &s, const v2d &uw) {
+  s.ai = uw.x;
+  s.bi = uw.y;
+  s.acc = 0.0;
+}
+__device__ __forceinline__ void div_add_half_w(PolDC64<OP_DIV>::St &s, const v2d &uw,
+                                               const double2 &Sh) {
+  const double ae = s.ai + uw.x, be = s.bi + uw.y;
+  s.acc = s.acc + (Sh.x * ae + Sh.y * be);
+}
+// (overloads for the FP32 instantiation, never called)
+__device__ __forceinline__ void grad_add_half(Pol<float, OP_GRAD>::St &, float, const double2 &,
+                                              bool) {}
+__device__ __forceinline__ void div_init_w(PolDC32<OP_DIV>::St &, const v2f &) {}
+__device__ __forceinline__ void div_add_half_w(PolDC32<OP_DIV>::St &, const v2f &,
+                                               const double2 &) {}
 
 __device__ __forceinline__ int4 cst_int4(const int4 *p, size_t i) {
   const ATLASX_CST int *d = cst(reinterpret_cast<const int *>(p));
@@ -1350,10 +1382,15 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
   using RG = typename LG::raw;         // NV levels of the gradient
   static_assert(sizeof(typename PG::Out) == sizeof(GV), "gradient output type");
   constexpr int G = 6;
+  // FP64 keeps the second gradient component multiplied by cos(lat) in the
+  // ring (the divergence's b = v cos(lat), formed once per node instead of
+  // once per incidence) and uses the halved normals as they are
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int LGW = F64 ? kLGeoWords64 : kLGeoWords;  // own-position words staged
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int fmax = m.l2_fmax, gmax = m.l2_gmax;
   const int gw = gmax * kGGeoWords;                          // g part of a geometry slot
-  const int geo_stride = gw + m.l2_pmax * kLGeoWords;        // words per geometry slot
+  const int geo_stride = gw + m.l2_pmax * LGW;               // words per geometry slot
   // the gradient ring holds each lane vector as two planes of its first
   // and second half (consecutive lanes then read consecutive 16-byte words)
   static_assert(sizeof(RG) == 2 * sizeof(RF), "gradient lane vector = two field lane vectors");
@@ -1441,9 +1478,9 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
       gword[e] = i - grec[e] * kGGeoWords;
       gkind[e] = (gword[e] == 6 || gword[e] == 7) ? 1 : (gword[e] == 9) ? 2 : 0;
     } else if (i < geo_stride) {
-      grec[e] = (i - gw) / kLGeoWords;
-      gword[e] = (i - gw) - grec[e] * kLGeoWords;
-      gkind[e] = (gword[e] == 6 || gword[e] == 7) ? 3 : (gword[e] == 12) ? 4 : 0;
+      grec[e] = (i - gw) / LGW;
+      gword[e] = (i - gw) - grec[e] * LGW;
+      gkind[e] = (gword[e] == 6 || gword[e] == 7) ? 3 : (gword[e] == 9) ? 4 : 0;
     } else {
       grec[e] = -1;
       gword[e] = 0;
@@ -1527,10 +1564,13 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
       const int glen = cst_int4(m.l2_gseg, k0 + q).y;
       for (int s = NPW * wave + sub; s < glen; s += NPW * nw) {
         const i32x4 *r = gq + s * kGGeoWords;
-        double2 S[G];
+        double2 S[G];  // halved normals (FP64), the normals (FP32)
         int lr[8];
 #pragma unroll
-        for (int j = 0; j < G; ++j) __builtin_memcpy(&S[j], &r[j], 16);
+        for (int j = 0; j < G; ++j) {
+          __builtin_memcpy(&S[j], &r[j], 16);
+          if constexpr (!F64) S[j] = make_double2(S[j].x + S[j].x, S[j].y + S[j].y);
+        }
         {
           const i32x4 a = r[6], b = r[7];
           lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
@@ -1545,6 +1585,11 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
         }
         const i32x4 w9 = r[9];
         const int fself = w9.x, n = w9.y;  // fself: LDS offset
+        double cosg;
+        {
+          const int c2[2] = {w9.z, w9.w};
+          __builtin_memcpy(&cosg, c2, 8);
+        }
         typename PG::St st[NV];
         {
           const RF xi = fbuf[fself + kc];
@@ -1561,7 +1606,10 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
           if (j < kMinRow) {  // present in every row, never the pole edge
             closure_add<OP_GRAD>(cx, cy, S[j], false);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) PG::add(st[v], LF::get(xn[j], v), S[j], false, 0.0);
+            for (int v = 0; v < NV; ++v) {
+              if constexpr (F64) grad_add_half(st[v], LF::get(xn[j], v), S[j], false);
+              else PG::add(st[v], LF::get(xn[j], v), S[j], false, 0.0);
+            }
             continue;
           }
           const bool use = j < n;
@@ -1572,7 +1620,8 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             typename PG::St tt = st[v];
-            PG::add(tt, LF::get(xn[j], v), S[j], pole, 0.0);
+            if constexpr (F64) grad_add_half(tt, LF::get(xn[j], v), S[j], pole);
+            else PG::add(tt, LF::get(xn[j], v), S[j], pole, 0.0);
             PG::keep(st[v], tt, use);
           }
         }
@@ -1581,7 +1630,8 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
         for (int v = 0; v < NV; ++v) {
           const typename PG::Out o = PG::result(st[v], al, be, cx, cy, 0.0);
           g.e[2 * v] = o.x;
-          g.e[2 * v + 1] = o.y;
+          if constexpr (F64) g.e[2 * v + 1] = o.y * cosg;  // v cos(lat), as the divergence forms it
+          else g.e[2 * v + 1] = o.y;
         }
         if (lane_on) {
           RF *d = gbuf + (q & 3) * gstride + s * 2 * vpc + kc;
@@ -1595,33 +1645,44 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
       const int q2 = q - 2;
       const int2 sp = cst_int2(m.l2_seg_pos, k0 + q2);
       for (int t = NPW * wave + sub; t < sp.y - sp.x; t += NPW * nw) {
-        const i32x4 *r = gq + gw + t * kLGeoWords;
-        double2 S[G];
+        const i32x4 *r = gq + gw + t * LGW;
+        double2 S[G];  // halved normals (FP64), the normals (FP32)
         int lr[8];
         double cn[G];
 #pragma unroll
-        for (int j = 0; j < G; ++j) __builtin_memcpy(&S[j], &r[j], 16);
+        for (int j = 0; j < G; ++j) {
+          __builtin_memcpy(&S[j], &r[j], 16);
+          if constexpr (!F64) S[j] = make_double2(S[j].x + S[j].x, S[j].y + S[j].y);
+        }
         {
           const i32x4 a = r[6], b = r[7];
           lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
           lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
         }
+        if constexpr (!F64) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) __builtin_memcpy(&cn[2 * k], &r[8 + k], 16);
+          for (int k = 0; k < 3; ++k) __builtin_memcpy(&cn[2 * k], &r[10 + k], 16);
+        } else {
+#pragma unroll
+          for (int j = 0; j < G; ++j) cn[j] = 0.0;
+        }
         double al, ci;
         {
-          const i32x4 w11 = r[11];
-          const int a2[2] = {w11.x, w11.y}, c2[2] = {w11.z, w11.w};
+          const i32x4 w8 = r[8];
+          const int a2[2] = {w8.x, w8.y}, c2[2] = {w8.z, w8.w};
           __builtin_memcpy(&al, a2, 8);
           __builtin_memcpy(&ci, c2, 8);
         }
-        const i32x4 w12 = r[12];
-        const int node = w12.x, n = w12.y, self = w12.z;  // self: LDS offset
+        const i32x4 w9 = r[9];
+        const int node = w9.x, n = w9.y, self = w9.z;  // self: LDS offset
         typename PD::St st[NV];
         {
           const RG gi = gload(self + kc);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) PD::init(st[v], LG::get(gi, v), ci);
+          for (int v = 0; v < NV; ++v) {
+            if constexpr (F64) div_init_w(st[v], LG::get(gi, v));
+            else PD::init(st[v], LG::get(gi, v), ci);
+          }
         }
         RG gn[G];
 #pragma unroll
@@ -1633,7 +1694,10 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
           if (j < kMinRow) {
             closure_add<OP_DIV>(cx, cy, S[j], false);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) PD::add(st[v], LG::get(gn[j], v), S[j], false, cn[j]);
+            for (int v = 0; v < NV; ++v) {
+              if constexpr (F64) div_add_half_w(st[v], LG::get(gn[j], v), S[j]);
+              else PD::add(st[v], LG::get(gn[j], v), S[j], false, cn[j]);
+            }
             continue;
           }
           const bool use = j < n && !pole;
@@ -1644,7 +1708,8 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             typename PD::St tt = st[v];
-            PD::add(tt, LG::get(gn[j], v), S[j], pole, cn[j]);
+            if constexpr (F64) div_add_half_w(tt, LG::get(gn[j], v), S[j]);
+            else PD::add(tt, LG::get(gn[j], v), S[j], pole, cn[j]);
             PD::keep(st[v], tt, use);
           }
         }
@@ -1683,24 +1748,33 @@ __global__ void k_pack_ggeo(DevMesh m, int ng, i32x4 *__restrict__ dst) {
   if (g >= ng) return;
   const int4 gn = m.l2_gnode[g];  // {row start, row length, f self, position}
   i32x4 *o = dst + (size_t)g * kGGeoWords;
-  for (int j = 0; j < 6; ++j) __builtin_memcpy(&o[j], &m.S[gn.x + j], 16);
+  for (int j = 0; j < 6; ++j) {  // halved normals (exact)
+    const double2 h = make_double2(0.5 * m.S[gn.x + j].x, 0.5 * m.S[gn.x + j].y);
+    __builtin_memcpy(&o[j], &h, 16);
+  }
   __builtin_memcpy(&o[6], m.l2_glref + (size_t)g * kGRefs, 32);
   const PosRec pr = m.pos[gn.w];
   const double ab[2] = {pr.alpha, pr.beta};
   __builtin_memcpy(&o[8], ab, 16);
-  o[9] = i32x4{gn.z, gn.y, 0, 0};
+  const double c = m.coslat[pr.node];
+  int cw[2];
+  __builtin_memcpy(cw, &c, 8);
+  o[9] = i32x4{gn.z, gn.y, cw[0], cw[1]};
 }
 __global__ void k_pack_lgeo(DevMesh m, i32x4 *__restrict__ dst) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m.V) return;
   const PosRec pr = m.pos[p];
   i32x4 *o = dst + (size_t)p * kLGeoWords;
-  for (int j = 0; j < 6; ++j) __builtin_memcpy(&o[j], &m.S[pr.r0 + j], 16);
+  for (int j = 0; j < 6; ++j) {  // halved normals (exact)
+    const double2 h = make_double2(0.5 * m.S[pr.r0 + j].x, 0.5 * m.S[pr.r0 + j].y);
+    __builtin_memcpy(&o[j], &h, 16);
+  }
   __builtin_memcpy(&o[6], m.l2_lref + pr.r0, 32);
-  __builtin_memcpy(&o[8], m.ncos + pr.r0, 48);
   const double ac[2] = {pr.alpha, m.coslat[pr.node]};
-  __builtin_memcpy(&o[11], ac, 16);
-  o[12] = i32x4{pr.node, pr.r1 - pr.r0, m.l2_lself[p], 0};
+  __builtin_memcpy(&o[8], ac, 16);
+  o[9] = i32x4{pr.node, pr.r1 - pr.r0, m.l2_lself[p], 0};
+  __builtin_memcpy(&o[10], m.ncos + pr.r0, 48);
 }
 
 template <class T, int OP>
@@ -2432,7 +2506,8 @@ atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *ou
   const size_t fb = (size_t)nv * sizeof(T), gb = 2 * fb;  // lane-vector bytes
   const size_t per_vec = 4 * (size_t)m.l2_fmax * fb + 4 * (size_t)m.l2_gmax * gb;
   // two slots of packed geometry; a thread stages at most kGeoEpt words
-  const size_t geo_words = (size_t)m.l2_gmax * kGGeoWords + (size_t)m.l2_pmax * kLGeoWords;
+  const size_t geo_words = (size_t)m.l2_gmax * kGGeoWords +
+                           (size_t)m.l2_pmax * (sizeof(T) == 8 ? kLGeoWords64 : kLGeoWords);
   const size_t geo = 2 * geo_words * 16;
   if (geo_words > (size_t)kGeoEpt * sh.block) return ATLAS_OK;
   int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + nv - 1) / nv) : 64;
