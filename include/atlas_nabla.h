@@ -239,7 +239,9 @@ typedef struct {
                                units run chunk by chunk over the whole mesh
                                so a parallel's columns are still cached when
                                the next parallel reads them; 0 = all levels
-                               in one unit                                  */
+                               in one unit.  Sweep and fused forms: at most
+                               this many levels per workgroup (0 = as many
+                               as LDS holds)                                */
   int32_t blocks_per_cu;    /* column/flat: > 0 launches a persistent grid of
                                this many workgroups per compute unit; each
                                XCD's wavefronts then walk that XCD's share of
@@ -247,13 +249,14 @@ typedef struct {
                                per wavefront per step, so the set of columns
                                in flight stays small enough for the L2;
                                0 = one workgroup per tile                   */
-  int32_t level_vec;        /* column and sweep forms: levels per lane.  0 =
-                               the level-vector kernels with the width (1..4
-                               levels, at most 32 bytes per lane) that
-                               needs the fewest level slots per lane, then
-                               the fewest loads (at 137 levels: 3 for FP64
-                               and FP32 scalars and FP32 vectors, 1 for FP64
-                               vectors); 2..4 = that width (capped at 32
+  int32_t level_vec;        /* column, sweep and fused forms: levels per
+                               lane.  0 = the level-vector kernels at the
+                               automatic width: FP64 16-byte lanes (2
+                               levels of a scalar, 1 of a vector); FP32 the
+                               width (1..4 levels, at most 32 bytes per
+                               lane) that needs the fewest level slots per
+                               lane, then the fewest loads (3 at 137
+                               levels); 2..4 = that width (capped at 32
                                bytes); 1 = the one-level-per-lane kernels.
                                Lanes past the column make no memory access.
                                The level-vector kernels need a mesh of
