@@ -43,7 +43,7 @@ def parse_args():
     ap.add_argument("--nlev", type=int, default=137)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-ops", action="store_true")
-    ap.add_argument("--cpu-levels", type=int, default=16,
+    ap.add_argument("--cpu-levels", type=int, default=137,
                     help="levels of the workload the CPU oracle sample covers")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -118,23 +118,41 @@ def time_op(fn, steps, warmup, torch):
     return start.elapsed_time(end) / steps  # ms per launch sequence
 
 
-def cpu_baseline(N, nlev_total, levels, f_host):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(N, nlev_total, levels, f_host, runs=5):
     """The FP64 oracle on this host: dense gradient over all edges for the
-    first `levels` levels of the same field (a bounded sample)."""
+    first `levels` levels of the same field, median of `runs` runs (a bounded
+    sample: about 13 s at O1280 with all 137 levels on 16 threads)."""
     import numpy as np
     import oracle
     om = oracle.Mesh(N)
     fs = np.ascontiguousarray(f_host[:, :levels])
-    t0 = time.perf_counter()
-    om.gradient(fs, levels)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        om.gradient(fs, levels)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     return {
         "value": om.E * levels / dt,
         "unit": "edge*level updates/s",
         "cores": oracle.threads_used(levels),
         "kind": "oracle",
-        "sample": f"O{N} FP64 gradient, all {om.E} edges, first {levels} of {nlev_total} levels "
-                  f"({dt:.1f} s)",
+        "sample": f"O{N} FP64 gradient, all {om.E} edges, {levels} of {nlev_total} levels, "
+                  f"median of {runs} runs ({dt:.2f} s each)",
+        "nproc": os.cpu_count(),
+        "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+        "cpu_model": _cpu_model(),
     }, om
 
 
