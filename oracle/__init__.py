@@ -56,6 +56,8 @@ def _load():
         lib.orc_gauss_mu.argtypes = [ctypes.c_int, _c_dp]
         lib.orc_mesh_build.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.orc_mesh_build.restype = ctypes.c_void_p
+        lib.orc_mesh_build_pl.argtypes = [ctypes.c_int, _c_i32p, ctypes.c_double]
+        lib.orc_mesh_build_pl.restype = ctypes.c_void_p
         lib.orc_mesh_free.argtypes = [ctypes.c_void_p]
         lib.orc_mesh_sizes.argtypes = [ctypes.c_void_p, _c_i64p]
         lib.orc_mesh_copy.argtypes = [ctypes.c_void_p, _c_i32p, _c_i64p, _c_dp,
@@ -89,16 +91,32 @@ def threads_used(nlev: int) -> int:
     return int(_load().orc_threads_used(int(nlev)))
 
 
-class Mesh:
-    """Octahedral grid O<N>, its triangulation, edges and median-dual
-    geometry, built by the oracle from (N, R) alone."""
+def regular_gaussian_nx(N: int) -> np.ndarray:
+    """Points per parallel of the regular Gaussian grid F<N> (Section
+    4.2.3.6: nx = 4N on each of the 2N parallels)."""
+    return np.full(2 * int(N), 4 * int(N), dtype=np.int32)
 
-    def __init__(self, N: int, R: float = 1.0):
+
+class Mesh:
+    """A reduced Gaussian grid, its triangulation, edges and median-dual
+    geometry, built by the oracle: O<N> from (N, R) alone (Section 4.2.3.7,
+    Listing 6), or any grid from its points per parallel ``nx`` (2N even
+    entries' worth of parallels at the Gaussian latitudes of degree 2N;
+    ``regular_gaussian_nx(N)`` gives F<N>)."""
+
+    def __init__(self, N: int = 0, R: float = 1.0, nx=None):
         lib = _load()
         self._lib = lib
-        self._h = lib.orc_mesh_build(int(N), float(R))
+        if nx is None:
+            self._h = lib.orc_mesh_build(int(N), float(R))
+            what = f"O{N}"
+        else:
+            nx = np.ascontiguousarray(nx, dtype=np.int32)
+            N = len(nx) // 2
+            self._h = lib.orc_mesh_build_pl(len(nx), nx.ctypes.data_as(_c_i32p), float(R))
+            what = f"the grid with nx={nx.tolist()[:4]}..."
         if not self._h:
-            raise ValueError(f"cannot build O{N} with R={R}")
+            raise ValueError(f"cannot build {what} with R={R}")
         sz = np.zeros(6, dtype=np.int64)
         lib.orc_mesh_sizes(self._h, sz.ctypes.data_as(_c_i64p))
         self.N = int(N)

@@ -172,24 +172,28 @@ void orc_mesh_free(orc_mesh *m) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Build grid O<N>, its triangulation, edges and median-dual geometry.       */
+/* Build a reduced Gaussian grid (Section 4.2.3.7: nrings = 2N parallels at  */
+/* the Gaussian latitudes of degree 2N, nx[j] points on parallel j; the      */
+/* regular grid F<N> of Section 4.2.3.6 has nx[j] = 4N), its triangulation,  */
+/* edges and median-dual geometry.  Needs nrings even, every nx >= 4 and     */
+/* the two polar parallels even (their nodes pair up across the pole).       */
 /* ------------------------------------------------------------------------ */
-orc_mesh *orc_mesh_build(int N, double R) {
-  if (N < 1 || !(R > 0.0)) return NULL;
+orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
+  if (nrings < 2 || (nrings & 1) || !nx_in || !(R > 0.0)) return NULL;
+  for (int j = 0; j < nrings; ++j)
+    if (nx_in[j] < 4) return NULL;
+  if ((nx_in[0] & 1) || (nx_in[nrings - 1] & 1)) return NULL;
   orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
   if (!m) return NULL;
+  const int N = nrings / 2;
   m->N = N;
   m->R = R;
-  m->nrings = 2 * N;
+  m->nrings = nrings;
   const int nr = m->nrings;
 
-  /* --- grid: Section 4.2.3.7, Listing 6 (nx = 20 + 4j, mirrored) -------- */
   m->nx = (int32_t *)malloc(sizeof(int32_t) * nr);
   m->ring_off = (int64_t *)malloc(sizeof(int64_t) * (nr + 1));
-  for (int j = 0; j < N; ++j) {
-    m->nx[j] = 20 + 4 * j;
-    m->nx[nr - 1 - j] = m->nx[j];
-  }
+  for (int j = 0; j < nr; ++j) m->nx[j] = nx_in[j];
   m->ring_off[0] = 0;
   for (int j = 0; j < nr; ++j) m->ring_off[j + 1] = m->ring_off[j] + m->nx[j];
   const int64_t V = m->ring_off[nr];
@@ -324,9 +328,9 @@ orc_mesh *orc_mesh_build(int N, double R) {
    * midpoint to the pole line; each polar node gains the rectangle
    * dlon0 x (pi/2 - |lat0|); its face on the pole line (length dlon0,
    * outward normal (0, sigma dlon0)) is carried by the node's pole edge,
-   * which pairs it with the node half-way round the same parallel.       */
-  const double dlon0 = 2.0 * ORC_PI / 20.0;
-  m->npole = 20;
+   * which pairs it with the node half-way round the same parallel.  dlon0
+   * is the spacing of that polar parallel (2 pi / 20 on O<N>).           */
+  m->npole = m->nx[0] / 2 + m->nx[nr - 1] / 2;
   m->pole_edge = (int32_t *)malloc(sizeof(int32_t) * 2 * m->npole);
   m->pole_normal = (double *)malloc(sizeof(double) * m->npole);
   for (int side = 0; side < 2; ++side) {
@@ -334,6 +338,7 @@ orc_mesh *orc_mesh_build(int N, double R) {
     const double sigma = side == 0 ? 1.0 : -1.0;
     const int64_t off = m->ring_off[j];
     const int n = m->nx[j];
+    const double dlon0 = 2.0 * ORC_PI / (double)n;
     const double th = m->lat[off];
     const double ext = 0.5 * ORC_PI - fabs(th);
     for (int i = 0; i < n; ++i) {
@@ -350,7 +355,7 @@ orc_mesh *orc_mesh_build(int N, double R) {
       m->A[p] += dlon0 * ext;
     }
     for (int i = 0; i < n / 2; ++i) {
-      const int k = side * (n / 2) + i;
+      const int k = side * (m->nx[0] / 2) + i;
       m->pole_edge[2 * k + 0] = (int32_t)(off + i);
       m->pole_edge[2 * k + 1] = (int32_t)(off + i + n / 2);
       m->pole_normal[k] = sigma * dlon0;
@@ -383,6 +388,21 @@ orc_mesh *orc_mesh_build(int N, double R) {
     m->pole_of[m->pole_edge[2 * k + 1]] = k;
   }
   free(first);
+  return m;
+}
+
+/* Grid O<N>: Section 4.2.3.7, Listing 6 (nx = 20 + 4j up to the equator,
+ * mirrored about it). */
+orc_mesh *orc_mesh_build(int N, double R) {
+  if (N < 1) return NULL;
+  int32_t *nx = (int32_t *)malloc(sizeof(int32_t) * 2 * N);
+  if (!nx) return NULL;
+  for (int j = 0; j < N; ++j) {
+    nx[j] = 20 + 4 * j;
+    nx[2 * N - 1 - j] = nx[j];
+  }
+  orc_mesh *m = orc_mesh_build_pl(2 * N, nx, R);
+  free(nx);
   return m;
 }
 
