@@ -481,6 +481,29 @@ def main():
                 ops[name]["one_pass_hbm_frac"] = round(b1 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             del o
 
+    # another reduced Gaussian grid: the regular grid F640 (nx = 2560 on all
+    # 1280 parallels, 3.28 M nodes), default shapes
+    grids = {}
+    if not args.no_extra_ops:
+        nxF = P.regular_gaussian_nx(640)
+        gF = P.Mesh(nx=nxF)
+        VF, EF, geoF = gF.nnodes, gF.nedges, gF.info.geometry_bytes_per_call
+        xF = torch.randn(VF, nlev, dtype=torch.float64, device=dev)
+        for name, op, shape, nbytes in (
+                ("F640_grad_f64", "grad", (VF, nlev, 2), 3 * VF * nlev * 8 + geoF),
+                ("F640_lapl_f64", "lapl", (VF, nlev), 6 * VF * nlev * 8 + 2 * geoF)):
+            o = torch.empty(shape, dtype=torch.float64, device=dev)
+            fn = (lambda o=o: gF.gradient(xF, out=o)) if op == "grad" else \
+                 (lambda o=o: gF.laplacian(xF, out=o))
+            t = time_op(fn, max(5, args.steps // 2), 2, torch)
+            grids[name] = {"ms": round(t, 4), "nodes": VF, "edges": EF,
+                           "edge_level_per_s": EF * nlev / (t * 1e-3),
+                           "GBps": round(nbytes / (t * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del o
+        del xF, gF
+        torch.cuda.empty_cache()
+
     sha = kernel_source_sha()
     rec = counters_for(sha)
     traffic = None
@@ -536,6 +559,7 @@ def main():
                      "algorithmic_bytes": alg_bytes("grad", 8)},
         "cpu_baseline": cpu,
         "ops": ops,
+        "other_grids": grids,
         "accuracy_vs_oracle": acc,
         "batch": batch,
         "serving": serving,

@@ -129,6 +129,17 @@ typedef struct {
  * Errors: ATLAS_EINVAL for N < 1, N > 8192 or radius <= 0; ATLAS_ENOMEM. */
 atlas_status atlas_mesh_desc_octahedral(int32_t N, double radius,
                                         atlas_mesh_desc **out);
+/* The same for any reduced Gaussian grid (Section 4.2.3.7): nrings = 2N
+ * parallels at the Gaussian latitudes of degree 2N, nx[j] points on
+ * parallel j (first at lon 0, equispaced), triangulated between consecutive
+ * parallels; the regular Gaussian grid F<N> of Section 4.2.3.6 has
+ * nx[j] = 4N.  The polar parallels' nodes pair up across the pole, so those
+ * two parallels need an even count.  nx: host array, read during the call.
+ * Errors: ATLAS_EINVAL (nrings odd or outside [2, 16384], an nx outside
+ * [4, 2^20], an odd polar parallel, radius <= 0, grid too large),
+ * ATLAS_ENOMEM. */
+atlas_status atlas_mesh_desc_reduced_gaussian(int32_t nrings, const int32_t *nx, double radius,
+                                              atlas_mesh_desc **out);
 atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc);
 
 /* ---------------------------------------------------------------------- */

@@ -92,6 +92,29 @@ def mesh_desc_octahedral(N: int, radius: float = 1.0) -> dict:
         L.atlas_mesh_desc_free(p)
 
 
+def mesh_desc_reduced_gaussian(nx, radius: float = 1.0) -> dict:
+    """The library's host description of the reduced Gaussian grid with
+    nx[j] points on parallel j (2N parallels); ``regular_gaussian_nx(N)``
+    gives F<N>."""
+    import numpy as _np
+    L = lib()
+    arr = _np.ascontiguousarray(nx, dtype=_np.int32)
+    p = ctypes.POINTER(MeshDesc)()
+    _check(L.atlas_mesh_desc_reduced_gaussian(len(arr),
+                                              arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                              float(radius), ctypes.byref(p)))
+    try:
+        return _abi.desc_to_numpy(p.contents)
+    finally:
+        L.atlas_mesh_desc_free(p)
+
+
+def regular_gaussian_nx(N: int):
+    """Points per parallel of F<N> (nx = 4N on each of the 2N parallels)."""
+    import numpy as _np
+    return _np.full(2 * int(N), 4 * int(N), dtype=_np.int32)
+
+
 def bandwidth_probe(x, out, stream=None):
     """Streaming reference: read x (n elements), write 2n elements to out."""
     n = x.numel()
@@ -106,10 +129,15 @@ class Mesh:
     """A mesh resident on the current device (``atlas_mesh_upload``)."""
 
     def __init__(self, N: int | None = None, radius: float = 1.0, *, desc: dict | None = None,
-                 layout: tuple[int, int] | None = None):
+                 layout: tuple[int, int] | None = None, nx=None):
+        """O<N> by default; ``nx`` (points per parallel) gives any reduced
+        Gaussian grid, ``desc`` any mesh description."""
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
+        if nx is not None and desc is None:
+            desc = mesh_desc_reduced_gaussian(nx, radius)
+            N = len(nx) // 2
         if layout is not None and desc is None:
             desc = mesh_desc_octahedral(N, radius)
         if desc is not None:
@@ -428,7 +456,8 @@ class Server:
             pass
 
 
-__all__ = ["error_norms", "Server", "Batch", "autotune", "Mesh", "mesh_desc_octahedral", "lib", "build", "Launch", "AtlasError",
+__all__ = ["error_norms", "Server", "Batch", "autotune", "Mesh", "mesh_desc_octahedral",
+           "mesh_desc_reduced_gaussian", "regular_gaussian_nx", "lib", "build", "Launch", "AtlasError",
            "ATLAS_F32", "ATLAS_F64", "ATLAS_OP_GRADIENT", "ATLAS_OP_DIVERGENCE",
            "ATLAS_OP_CURL", "ATLAS_OP_LAPLACIAN", "VARIANT_AUTO", "VARIANT_COLUMN",
            "VARIANT_FLAT", "VARIANT_FLUX", "VARIANT_FUSED", "VARIANT_SWEEP"]

@@ -111,6 +111,9 @@ SIGNATURES = {
     "atlas_version": (ctypes.c_char_p, []),
     "atlas_mesh_desc_octahedral": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double,
                                                   ctypes.POINTER(ctypes.POINTER(MeshDesc))]),
+    "atlas_mesh_desc_reduced_gaussian": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                        ctypes.c_double,
+                                                        ctypes.POINTER(ctypes.POINTER(MeshDesc))]),
     "atlas_mesh_desc_free": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
     "atlas_mesh_upload": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
     "atlas_mesh_upload_ex": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Layout),

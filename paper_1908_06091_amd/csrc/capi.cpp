@@ -17,7 +17,8 @@ namespace atlasx {
 
 static thread_local std::string g_last_error;
 
-// host mesh descriptions handed out by atlas_mesh_desc_octahedral
+// host mesh descriptions handed out by atlas_mesh_desc_octahedral and
+// atlas_mesh_desc_reduced_gaussian
 static std::mutex g_desc_mu;
 static std::unordered_map<const atlas_mesh_desc *, HostMesh *> g_descs;
 
@@ -157,6 +158,38 @@ atlas_status atlas_mesh_desc_octahedral(int32_t N, double radius, atlas_mesh_des
   return ATLAS_OK;
 }
 
+atlas_status atlas_mesh_desc_reduced_gaussian(int32_t nrings, const int32_t *nx, double radius,
+                                              atlas_mesh_desc **out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!nx) return fail(ATLAS_EINVAL, "nx is NULL");
+  if (nrings < 2 || nrings > 16384 || (nrings & 1))
+    return fail(ATLAS_EINVAL, "nrings must be even and in [2, 16384]");
+  int64_t total = 0;
+  for (int j = 0; j < nrings; ++j) {
+    if (nx[j] < 4 || nx[j] > (1 << 20)) return fail(ATLAS_EINVAL, "every nx must be in [4, 2^20]");
+    total += nx[j];
+  }
+  if ((nx[0] & 1) || (nx[nrings - 1] & 1))
+    return fail(ATLAS_EINVAL, "the polar parallels need an even number of points");
+  if (total * 3 >= ((int64_t)1 << 31)) return fail(ATLAS_EINVAL, "grid too large");
+  if (!(radius > 0.0)) return fail(ATLAS_EINVAL, "radius must be positive");
+  HostMesh *h = new (std::nothrow) HostMesh();
+  if (!h) return fail(ATLAS_ENOMEM, "out of host memory");
+  try {
+    build_reduced_gaussian(std::vector<int32_t>(nx, nx + nrings), radius, *h);
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(ATLAS_ENOMEM, "out of host memory building the mesh");
+  }
+  {
+    std::lock_guard<std::mutex> g(g_desc_mu);
+    g_descs[&h->desc] = h;
+  }
+  *out = &h->desc;
+  return ATLAS_OK;
+}
+
 atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc) {
   if (!desc) return ATLAS_OK;
   HostMesh *h = nullptr;
@@ -164,7 +197,7 @@ atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc) {
     std::lock_guard<std::mutex> g(g_desc_mu);
     auto it = g_descs.find(desc);
     if (it == g_descs.end())
-      return fail(ATLAS_EINVAL, "description was not created by atlas_mesh_desc_octahedral");
+      return fail(ATLAS_EINVAL, "description was not created by atlas_mesh_desc_*");
     h = it->second;
     g_descs.erase(it);
   }

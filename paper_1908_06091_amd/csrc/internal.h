@@ -42,6 +42,7 @@ struct HostMesh {
 };
 
 int build_octahedral(int N, double R, HostMesh &h);
+int build_reduced_gaussian(const std::vector<int32_t> &nx, double R, HostMesh &h);
 
 // ------------------------------------------------------ device mesh store
 // All "position" arrays follow the processing order: the nodes re-ordered

@@ -1,9 +1,12 @@
-// mesh_build.cpp -- host problem setup: grid O<N>, its triangulation, the
-// edge and node->edge tables, and the median-dual geometry.
+// mesh_build.cpp -- host problem setup: a reduced Gaussian grid, its
+// triangulation, the edge and node->edge tables, and the median-dual
+// geometry.
 //
 // Grid: Section 4.2.3.5 (Gaussian latitudes = roots of the Legendre
 // polynomial of degree 2N; first point of every parallel at lon 0) and
-// Section 4.2.3.7, Listing 6 (nx = 20 + 4j to the equator, mirrored).
+// Section 4.2.3.7 (any number of points per parallel); O<N> is Listing 6
+// (nx = 20 + 4j to the equator, mirrored), F<N> is Section 4.2.3.6
+// (nx = 4N on every parallel).
 // Mesh: Section 4.3 (the structured mesh generator triangulates between
 // parallels; edges are mesh lines between nodes).  Geometry: the
 // ingredients of the edge-based finite-volume method of Section 4.7
@@ -55,11 +58,20 @@ void gaussian_mu(int N, std::vector<double> &mu) {
 
 // Builds every array of an atlas_mesh_desc for O<N>.
 int build_octahedral(int N, double R, HostMesh &h) {
-  const int nr = 2 * N;
+  std::vector<int32_t> nx(2 * N);
+  for (int j = 0; j < N; ++j) nx[j] = nx[2 * N - 1 - j] = 20 + 4 * j;
+  return build_reduced_gaussian(nx, R, h);
+}
+
+// Builds every array of an atlas_mesh_desc for the reduced Gaussian grid
+// with nx[j] points on parallel j (nx.size() = 2N parallels; every nx >= 4,
+// the two polar parallels even).
+int build_reduced_gaussian(const std::vector<int32_t> &nx_in, double R, HostMesh &h) {
+  const int nr = (int)nx_in.size();
+  const int N = nr / 2;
   h.N = N;
   h.radius = R;
-  h.nx.resize(nr);
-  for (int j = 0; j < N; ++j) h.nx[j] = h.nx[nr - 1 - j] = 20 + 4 * j;
+  h.nx = nx_in;
   h.ring_off.resize(nr + 1);
   h.ring_off[0] = 0;
   for (int j = 0; j < nr; ++j) h.ring_off[j + 1] = h.ring_off[j] + h.nx[j];
@@ -182,8 +194,8 @@ int build_octahedral(int N, double R, HostMesh &h) {
       h.dual_normals[2 * e + 1] += sgn * sy;
     }
   }
-  // polar closure: cells of the first / last parallel reach the pole line
-  const double dlon0 = 2.0 * kPi / 20.0;
+  // polar closure: cells of the first / last parallel reach the pole line;
+  // each polar node's face there is one spacing of its parallel wide
   h.pole_edges.clear();
   h.pole_normals.clear();
   for (int side = 0; side < 2; ++side) {
@@ -191,6 +203,7 @@ int build_octahedral(int N, double R, HostMesh &h) {
     const double sigma = side ? -1.0 : 1.0;
     const int64_t o = h.ring_off[j];
     const int n = h.nx[j];
+    const double dlon0 = 2.0 * kPi / (double)n;
     const double height = 0.5 * kPi - std::fabs(h.lat[o]);
     for (int i = 0; i < n; ++i) {
       const int32_t p = (int32_t)(o + i), q = (int32_t)(o + (i + 1) % n);

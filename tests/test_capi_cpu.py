@@ -94,3 +94,30 @@ def test_product_package_has_no_cpu_fallback():
         text = open(py).read()
         assert "import oracle" not in text and "from oracle" not in text, py
         assert "synthetic" not in text, py
+
+
+@pytest.mark.parametrize("nx", [[4] * 2, [8] * 4, [64] * 32, [6, 9, 13, 13, 10, 8]])
+def test_host_reduced_gaussian_matches_oracle(P, nx):
+    """Regular (F<N>) and hand-made reduced Gaussian grids: the library's
+    host description against the oracle's, topology bit for bit."""
+    nx = np.array(nx, np.int32)
+    d = P.mesh_desc_reduced_gaussian(nx)
+    m = oracle.Mesh(nx=nx)
+    np.testing.assert_array_equal(d["edge2node"], m.edge)
+    np.testing.assert_array_equal(d["pole_edges"], m.pole_edge)
+    np.testing.assert_allclose(d["lat"], m.lat, rtol=0, atol=4e-16)
+    np.testing.assert_array_equal(d["lon"], m.lon)
+    np.testing.assert_allclose(d["dual_normals"], m.S, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(d["dual_volumes"], m.vol, rtol=1e-13)
+    np.testing.assert_array_equal(d["pole_normals"], m.pole_normal)
+
+
+def test_host_reduced_gaussian_rejects_bad_grids(P):
+    for nx in ([5, 8, 8, 6], [6, 8, 8], [6, 3, 8, 6]):
+        with pytest.raises(P.AtlasError):
+            P.mesh_desc_reduced_gaussian(np.array(nx, np.int32))
+    # O<N> through the general builder is O<N>
+    o = P.mesh_desc_octahedral(3)
+    r = P.mesh_desc_reduced_gaussian(np.array([20, 24, 28, 28, 24, 20], np.int32))
+    for k in ("edge2node", "lon", "lat", "dual_normals", "dual_volumes", "pole_edges"):
+        np.testing.assert_array_equal(o[k], r[k])
