@@ -212,7 +212,8 @@ atlas_status atlas_nabla_div_curl(atlas_mesh_t mesh, const void *uv, int32_t nle
 /* workspace: device buffer of atlas_laplacian_workspace_bytes() bytes, or
  * NULL to use a workspace the mesh keeps (grown on first use with
  * hipMalloc; calls that share it on different streams must be ordered by
- * the caller). */
+ * the caller).  The fused one-pass form (the FP64 default on large meshes,
+ * ATLAS_VARIANT_FUSED) writes no gradient and uses no workspace. */
 atlas_status atlas_nabla_laplacian(atlas_mesh_t mesh, const void *f, int32_t nlev,
                                    atlas_dtype dtype, void *out, void *workspace,
                                    hipStream_t stream);

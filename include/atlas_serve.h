@@ -11,7 +11,8 @@
  * bitwise identical to the same request run alone.
  *
  * Footprint of a request while in the server: its input, its output and, for
- * the Laplacian, its [V][nlev][2] workspace.  A request whose footprint alone
+ * the Laplacian, its [V][nlev][2] workspace (none for a Laplacian that
+ * launches alone in the fused one-pass form).  A request whose footprint alone
  * exceeds the budget is rejected at submit with ATLAS_ENOMEM.  A server-owned
  * output stays in the footprint until atlas_serve_release.  Server-owned
  * outputs and workspaces are ranges of one arena reserved at creation, so

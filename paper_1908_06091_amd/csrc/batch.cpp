@@ -364,18 +364,23 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
     bi.in = it.in;
     bi.out = it.out;
     bi.ws = it.workspace;
-    if (bi.lapl && !bi.ws) {
+    // a Laplacian's gradient workspace, owned by the batch when the item
+    // brings none (the fused one-pass form needs none)
+    auto own_ws = [&]() -> atlas_status {
+      if (bi.ws) return ATLAS_OK;
       void *p = nullptr;
       const size_t bytes = (size_t)m.d.V * it.nlev * 2 * w;
-      if (hipMalloc(&p, bytes) != hipSuccess) return bail(fail(ATLAS_ENOMEM, "batch workspace"));
+      if (hipMalloc(&p, bytes) != hipSuccess) return fail(ATLAS_ENOMEM, "batch workspace");
       b->owned.push_back(p);
       b->owned_bytes += bytes;
       bi.ws = p;
-    }
+      return ATLAS_OK;
+    };
     const auto key = std::make_tuple((const void *)&m, it.op, it.nlev);
     if (solo_min >= 0 && (int64_t)m.d.V * it.nlev >= solo_min) {
       // its own launch, with the shape a single call would use (tuned
-      // first if asked; the tuner stores the winner in the mesh)
+      // first if asked; the tuner stores the winner in the mesh and brings
+      // its own workspace when given none)
       if (c.autotune && !tuned[key]) {
         atlas_status s = autotune(it.mesh, (atlas_op)it.op, it.in, it.nlev, dt, it.out, bi.ws,
                                   stream, nullptr, nullptr);
@@ -384,8 +389,16 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
       }
       LaunchShape sh = shape_from(nullptr, m, (atlas_op)it.op, it.nlev, dt);
       if (sh.variant == ATLAS_VARIANT_FLUX) sh = default_shape(m, (atlas_op)it.op, it.nlev, dt);
+      if (bi.lapl && !lapl_fused_runs(m, it.nlev, dt, sh)) {
+        atlas_status s = own_ws();
+        if (s != ATLAS_OK) return bail(s);
+      }
       b->solo.push_back({&m, (atlas_op)it.op, it.in, it.nlev, it.out, bi.ws, sh});
       continue;
+    }
+    if (bi.lapl) {
+      atlas_status s = own_ws();
+      if (s != ATLAS_OK) return bail(s);
     }
     auto f = shapes.find(key);
     ItemShape sh;

@@ -113,7 +113,8 @@ atlas_status apply(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
   if (sh.level_vec < 0 || sh.level_vec > 4)
     return fail(ATLAS_EINVAL, "level_vec must be in [0, 4]");
   size_t need = 0;
-  if (op == ATLAS_OP_LAPLACIAN) need += lapl_ws_bytes(m, nlev, dt);
+  if (op == ATLAS_OP_LAPLACIAN && !lapl_fused_runs(m, nlev, dt, sh))
+    need += lapl_ws_bytes(m, nlev, dt);  // the fused form needs none
   if (sh.variant == ATLAS_VARIANT_FLUX) need += flux_ws_bytes(m, op, nlev, dt);
   void *ws = workspace;
   if (need && !ws) {

@@ -193,6 +193,9 @@ atlas_status derive_scales(MeshStore &m, const double *vol_by_pos,
                            const double *cos_by_pos, double radius);
 atlas_status bandwidth_probe(const void *in, void *out, int64_t n, int elem, hipStream_t st);
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt);
+// True if a Laplacian launched with `sh` runs the fused one-pass form
+// (which needs no workspace) rather than falling back to the two passes.
+bool lapl_fused_runs(const MeshStore &ms, int nlev, atlas_dtype dt, const LaunchShape &sh);
 // Divergence and curl of one vector field (one read of the field).
 atlas_status launch_div_curl(const MeshStore &ms, atlas_dtype dt, const void *in, int nlev,
                              void *out_div, void *out_curl, hipStream_t st);

@@ -2491,15 +2491,18 @@ atlas_status launch_div_curl(const MeshStore &ms, atlas_dtype dt, const void *in
                                       static_cast<float *>(out_curl), st);
 }
 
-// The fused Laplacian on the two-ring plan.  *ran = false (nothing
-// launched) where the plan or the kernel's assumptions do not hold: no
-// plan, rows outside 4..6 incidences, or a block too small for the staging.
+// The fused Laplacian's launch plan: lane width, level chunk and LDS bytes;
+// false where the plan or the kernel's assumptions do not hold (no plan,
+// rows outside 4..6 incidences, a block too small for the staging, runs too
+// long for LDS).
+struct FusedPlan {
+  int nv, vpc, nchunk;
+  size_t lds;
+};
 template <class T>
-atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *out,
-                               const LaunchShape &sh, hipStream_t st, bool *ran) {
+static bool fused_plan(const MeshStore &ms, int nlev, const LaunchShape &sh, FusedPlan *fp) {
   const DevMesh &m = ms.d;
-  *ran = false;
-  if (!m.l2_ok || m.maxdeg > 6 || m.mindeg < kMinRow) return ATLAS_OK;
+  if (!m.l2_ok || m.maxdeg > 6 || m.mindeg < kMinRow) return false;
   constexpr int NVW = (int)(16 / sizeof(T));  // 16-byte field lanes
   const int nv = (nlev >= NVW && sh.level_vec != 1) ? NVW : 1;
   const int nvec = (nlev + nv - 1) / nv;
@@ -2509,7 +2512,7 @@ atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *ou
   const size_t geo_words = (size_t)m.l2_gmax * kGGeoWords +
                            (size_t)m.l2_pmax * (sizeof(T) == 8 ? kLGeoWords64 : kLGeoWords);
   const size_t geo = 2 * geo_words * 16;
-  if (geo_words > (size_t)kGeoEpt * sh.block) return ATLAS_OK;
+  if (geo_words > (size_t)kGeoEpt * sh.block) return false;
   int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + nv - 1) / nv) : 64;
   vpc = min(vpc, nvec);
   {
@@ -2523,9 +2526,33 @@ atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *ou
     vpc = (vpc + 1) / 2;
   if (per_vec * vpc + geo > kMaxLds ||
       ((size_t)m.l2_fmax * vpc + sh.block - 1) / sh.block > (size_t)kLsweepEpt)
-    return ATLAS_OK;
-  const int nchunk = (nvec + vpc - 1) / vpc;
-  const size_t lds = per_vec * vpc + geo;
+    return false;
+  fp->nv = nv;
+  fp->vpc = vpc;
+  fp->nchunk = (nvec + vpc - 1) / vpc;
+  fp->lds = per_vec * vpc + geo;
+  return true;
+}
+
+bool lapl_fused_runs(const MeshStore &ms, int nlev, atlas_dtype dt, const LaunchShape &sh) {
+  if (sh.variant != ATLAS_VARIANT_FUSED) return false;
+  FusedPlan fp;
+  return dt == ATLAS_F64 ? fused_plan<double>(ms, nlev, sh, &fp)
+                         : fused_plan<float>(ms, nlev, sh, &fp);
+}
+
+// The fused Laplacian on the two-ring plan; *ran = false (nothing
+// launched) where fused_plan refuses.
+template <class T>
+atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *out,
+                               const LaunchShape &sh, hipStream_t st, bool *ran) {
+  const DevMesh &m = ms.d;
+  *ran = false;
+  FusedPlan fp;
+  if (!fused_plan<T>(ms, nlev, sh, &fp)) return ATLAS_OK;
+  constexpr int NVW = (int)(16 / sizeof(T));
+  const int nv = fp.nv, vpc = fp.vpc, nchunk = fp.nchunk;
+  const size_t lds = fp.lds;
   const int units = m.ntiles * nchunk;
   const int per = (units + 7) / 8;
   // several nodes per wavefront when the chunk fills at most half or a
@@ -2558,12 +2585,14 @@ atlas_status launch_op(const MeshStore &ms, atlas_op op, atlas_dtype dt, const v
                                        static_cast<float *>(out), sh, st, &ran);
     if (s != ATLAS_OK || ran) return s;
     // otherwise the two passes with their built-in shapes (same results)
+    if (!ws) return fail(ATLAS_EINVAL, "the two-pass Laplacian needs a workspace");
     LaunchShape two = sh;
     two.variant = ATLAS_VARIANT_COLUMN;
     two.per_pass = 1;
     return launch_op(ms, op, dt, in, nlev, out, ws, two, st);
   }
   if (op == ATLAS_OP_LAPLACIAN) {
+    if (!ws) return fail(ATLAS_EINVAL, "the two-pass Laplacian needs a workspace");
     const size_t w = dt == ATLAS_F64 ? 8 : 4;
     char *grad = static_cast<char *>(ws);
     void *flux = grad + (size_t)ms.d.V * nlev * 2 * w;

@@ -55,6 +55,8 @@ struct Req {
   int64_t V = 0;
   size_t in_b = 0, out_b = 0, ws_b = 0;
   size_t out_off = SIZE_MAX, ws_off = SIZE_MAX;  // arena ranges (SIZE_MAX: none)
+  LaunchShape sh;      // a large Laplacian's shape, fixed at submit
+  bool sh_set = false;
   bool own_out = false;
   bool out_charged = false;  // out_b still counted in flight (a server-owned
                              // output stays counted until it is released)
@@ -304,7 +306,7 @@ struct Server {
       Req &q = reqs.at(run[0]);
       const atlas_op op = (atlas_op)q.r.op;
       const atlas_dtype dt = (atlas_dtype)q.r.dtype;
-      LaunchShape sh = shape_from(nullptr, *q.m, op, q.r.nlev, dt);
+      LaunchShape sh = q.sh_set ? q.sh : shape_from(nullptr, *q.m, op, q.r.nlev, dt);
       if (sh.variant == ATLAS_VARIANT_FLUX) sh = default_shape(*q.m, op, q.r.nlev, dt);
       status = launch_op(*q.m, op, dt, q.r.in, q.r.nlev, q.r.out, q.ws, sh, s.stream);
     } else {
@@ -589,6 +591,18 @@ atlas_status atlas_serve_submit(atlas_server_t srv, const atlas_request *req, ui
   q.in_b = base * (vin ? 2 : 1);
   q.out_b = base * (req->op == ATLAS_OP_GRADIENT ? 2 : 1);
   q.ws_b = req->op == ATLAS_OP_LAPLACIAN ? 2 * base : 0;
+  if (q.m && req->op == ATLAS_OP_LAPLACIAN &&
+      (me.V * req->nlev > sv.cfg.batch_max_elems || sv.cfg.max_batch <= 1)) {
+    // a large Laplacian launches alone: if its shape is the fused one-pass
+    // form it needs no workspace (the shape is kept for the launch)
+    LaunchShape sh = shape_from(nullptr, *q.m, ATLAS_OP_LAPLACIAN, req->nlev,
+                                (atlas_dtype)req->dtype);
+    if (lapl_fused_runs(*q.m, req->nlev, (atlas_dtype)req->dtype, sh)) {
+      q.ws_b = 0;
+      q.sh = sh;
+      q.sh_set = true;
+    }
+  }
   q.own_out = req->out == nullptr;
   if (!sv.cfg.simulate) {
     const size_t iw = vin ? 2 * w : w, ow = req->op == ATLAS_OP_GRADIENT ? 2 * w : w;
