@@ -241,6 +241,13 @@ def batch_bench(P, torch, np, dev):
     b = P.Batch(items, use_graph=True, autotune=True)
     build_s = time.perf_counter() - t0
     ms_batch = time_op(lambda: b.launch(), 20, 3, torch)
+    hybrid = [it[3].clone() for it in items]
+    # every item inside the one persistent kernel (no item launched on its own)
+    bp = P.Batch(items, use_graph=True, autotune=True, solo_min_elems=-1)
+    ms_persistent = time_op(lambda: bp.launch(), 20, 3, torch)
+    same_persistent = all(torch.equal(a, it[3]) for a, it in zip(hybrid, items))
+    info_p = bp.info
+    bp.close()
     solo = [it[3].clone() for it in items]
     ms_seq = time_op(lambda: [gm.apply(c, x, out=o) for gm, c, x, o in items], 20, 3, torch)
     same = all(torch.equal(a, it[3]) for a, it in zip(solo, items))
@@ -269,6 +276,9 @@ def batch_bench(P, torch, np, dev):
             "form_flat": info.form_flat, "build_s_incl_autotune": round(build_s, 2),
             "ms_batch": round(ms_batch, 4), "ms_one_by_one": round(ms_seq, 4),
             "speedup": round(ms_seq / ms_batch, 3),
+            "persistent_only": {"ms": round(ms_persistent, 4), "units": info_p.nunits,
+                                "grid_blocks": info_p.grid_blocks,
+                                "bitwise_equal": bool(same_persistent)},
             "edge_level_per_s": edges_levels / (ms_batch * 1e-3),
             "bitwise_equal_to_solo": bool(same),
             "max_rel_error_vs_oracle": worst,

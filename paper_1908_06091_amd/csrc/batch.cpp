@@ -32,6 +32,8 @@ ItemShape heuristic_shape(int op, atlas_dtype dt, int nlev) {
   return {FORM_FLAT, npb, 0};
 }
 
+constexpr int kMinColumnUnit = 64;  // positions per column-form unit (16 per wavefront)
+
 // Units of a batch: every item's nodes in blocks of its npb, each item's
 // blocks split into 8 contiguous runs, one per queue (XCD); pass 0 holds
 // every unit of phase 0, pass 1 the divergence units of the Laplacians.
@@ -40,7 +42,13 @@ void plan_units(const std::vector<BatchItem> &items, const std::vector<ItemShape
                 std::vector<BatchUnit> &units, std::vector<int> &qbeg) {
   std::vector<std::vector<BatchUnit>> q0(8), q1(8);
   for (size_t i = 0; i < items.size(); ++i) {
-    const int V = items[i].m.V, npb = std::max(1, shapes[i].npb);
+    // a unit costs the workgroup an atomic and a barrier: column-form units
+    // hold at least kMinColumnUnit positions (the tile size tuned for a
+    // single launch may be smaller)
+    const int V = items[i].m.V;
+    const int npb = std::max(1, shapes[i].form == FORM_COLUMN
+                                    ? std::max(shapes[i].npb, kMinColumnUnit)
+                                    : shapes[i].npb);
     const int nu = (V + npb - 1) / npb;
     for (int x = 0; x < 8; ++x) {
       const int u0 = (int)((int64_t)nu * x / 8), u1 = (int)((int64_t)nu * (x + 1) / 8);

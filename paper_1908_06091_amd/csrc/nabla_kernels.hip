@@ -2015,14 +2015,20 @@ template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves<T>()))) k_batch(const BatchItem *__restrict__ items,
                                                const BatchUnit *__restrict__ units,
                                                const int *__restrict__ qbeg, int *heads) {
-  __shared__ int s_u;
+  // Unit indices pass through two LDS slots: while the workgroup runs unit
+  // s_u[k], thread 0 already takes the next one into s_u[k ^ 1], so the
+  // atomic's latency hides behind the unit and one barrier per unit
+  // suffices (s_u[k] is rewritten only after every thread has passed the
+  // barrier that follows its read).
+  __shared__ int s_u[2];
   const int x = blockIdx.x & 7;
-  for (;;) {
-    if (threadIdx.x == 0) s_u = qbeg[x] + atomicAdd(&heads[x], 1);
-    __syncthreads();
-    const int u = s_u;
-    __syncthreads();
-    if (u >= qbeg[x + 1]) break;  // this queue is drained: every wave exits
+  const int qend = qbeg[x + 1];
+  if (threadIdx.x == 0) s_u[0] = qbeg[x] + atomicAdd(&heads[x], 1);
+  __syncthreads();
+  for (int k = 0;; k ^= 1) {
+    const int u = s_u[k];
+    if (u >= qend) break;  // this queue is drained: every wave exits
+    if (threadIdx.x == 0) s_u[k ^ 1] = qbeg[x] + atomicAdd(&heads[x], 1);
     const BatchUnit un = units[u];
     const BatchItem &it = items[un.item];
     const int op = it.lapl ? (un.phase ? OP_DIV : OP_GRAD) : it.op;
@@ -2035,6 +2041,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_
       batch_unit_op<T, OP_DIV>(it.m, it.form, lv, src, dst, it.nlev, un.p0, un.p1);
     else
       batch_unit_op<T, OP_CURL>(it.m, it.form, lv, src, dst, it.nlev, un.p0, un.p1);
+    __syncthreads();
   }
 }
 
