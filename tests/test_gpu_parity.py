@@ -247,3 +247,36 @@ def test_autotune_keeps_results(P, op, dtype):
     torch.cuda.synchronize()
     assert torch.equal(after, before)
     assert torch.equal(out, before)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("nlev", [255, 513, 1100])
+def test_parity_long_columns(P, nlev, op, dtype):
+    """Columns longer than the level-vector forms take (more than 4 chunks
+    of 64 lane vectors fall back to one level per lane, beyond 3 chunks to
+    the generic loop): every default shape against the oracle on O4, plus
+    the fused Laplacian and the one-pass divergence + curl bitwise."""
+    print(f"long columns nlev={nlev} {op} {dtype}", flush=True)
+    N = 4
+    om, gm = _oracle_mesh(N), _gpu_mesh(P, N)
+    rng = np.random.default_rng(nlev)
+    f = rng.standard_normal((om.V, nlev))
+    uv = rng.standard_normal((om.V, nlev, 2))
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+        uv = uv.astype(np.float32).astype(np.float64)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    x = _device_input(op, f, uv, tdt)
+    got = _run(P, gm, op, x)
+    ref = oracle_apply(om, op, uv if op in ("div", "curl") else f, nlev)
+    emax, _ = normwise_error(got.double().cpu().numpy().reshape(ref.shape), ref)
+    assert emax <= TOL[dtype], (nlev, op, dtype, emax)
+    if op == "lapl":
+        fused = _run(P, gm, op, x, launch=P.Launch(P.VARIANT_FUSED, 1024, 0, 0, 0, 0))
+        assert torch.equal(fused, got)
+    if op == "div":
+        d, c = gm.div_curl(x)
+        torch.cuda.synchronize()
+        assert torch.equal(d, got)
+        assert torch.equal(c, _run(P, gm, "curl", x))
