@@ -279,8 +279,12 @@ typedef struct {
 
 /* Apply `op` with an explicit launch shape (tests, autotuner).  For
  * ATLAS_VARIANT_FLUX, `workspace` must hold atlas_flux_workspace_bytes();
- * for the Laplacian it must hold the larger of the two requirements.
- * shape == NULL is the same as the named entry points. */
+ * a two-pass Laplacian with ATLAS_VARIANT_FLUX keeps the gradient at the
+ * start of the workspace and the fluxes after it, so it needs the SUM
+ * atlas_laplacian_workspace_bytes() + atlas_flux_workspace_bytes(mesh,
+ * ATLAS_OP_LAPLACIAN, ...).  workspace == NULL: the mesh's own workspace,
+ * grown to what the call needs.  shape == NULL is the same as the named
+ * entry points. */
 atlas_status atlas_nabla_apply(atlas_mesh_t mesh, atlas_op op, const void *in,
                                int32_t nlev, atlas_dtype dtype, void *out,
                                void *workspace, const atlas_launch *shape,

@@ -11,6 +11,7 @@ Section 4.5 / Figure 31 layout [node][level]).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -78,6 +79,27 @@ def _dev_ptr(t, what):
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _out_ptr(t, like, numel, what):
+    """Device pointer of a caller-supplied output, checked to hold exactly
+    the `numel` elements of `like`'s dtype the library will write."""
+    if t.dtype != like.dtype:
+        raise TypeError(f"{what} dtype must match the input dtype")
+    if t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements, the operator writes {numel}")
+    return _dev_ptr(t, what)
+
+
+def _ws_ptr(t, need):
+    """Device pointer of a caller-supplied workspace of at least `need` bytes
+    (None: the mesh's own workspace)."""
+    if t is None:
+        return ctypes.c_void_p()
+    if t.numel() * t.element_size() < need:
+        raise ValueError(f"workspace holds {t.numel() * t.element_size()} bytes, "
+                         f"the call needs {need}")
+    return _dev_ptr(t, "workspace")
 
 
 def mesh_desc_octahedral(N: int, radius: float = 1.0) -> dict:
@@ -213,41 +235,48 @@ class Mesh:
         torch = _torch()
         vec_in = op in (ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL)
         nlev = self._nlev_vector(x) if vec_in else self._nlev_scalar(x)
+        shape = (self.nnodes, nlev, 2) if op == ATLAS_OP_GRADIENT else (self.nnodes, nlev)
         if out is None:
-            shape = (self.nnodes, nlev, 2) if op == ATLAS_OP_GRADIENT else (self.nnodes, nlev)
             out = torch.empty(shape, dtype=x.dtype, device=x.device)
-        if out.dtype != x.dtype:
-            raise TypeError("output dtype must match the input dtype")
-        ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+        op_ = _out_ptr(out, x, math.prod(shape), "output")
+        need = 0
+        if workspace is not None:
+            dc = _dtype_code(x)
+            if op == ATLAS_OP_LAPLACIAN:
+                need += self.laplacian_workspace_bytes(nlev, dc)
+            if launch is not None and launch.variant == VARIANT_FLUX:
+                need += self.flux_workspace_bytes(op, nlev, dc)
+        ws = _ws_ptr(workspace, need)
         lp = ctypes.byref(launch) if launch is not None else None
         _check(self._lib.atlas_nabla_apply(self._h, int(op), _dev_ptr(x, "input"), nlev,
-                                           _dtype_code(x), _dev_ptr(out, "output"), ws, lp,
-                                           _stream(stream)))
+                                           _dtype_code(x), op_, ws, lp, _stream(stream)))
         return out
 
     def gradient(self, f, out=None, stream=None):
         nlev = self._nlev_scalar(f)
         if out is None:
             out = _torch().empty((self.nnodes, nlev, 2), dtype=f.dtype, device=f.device)
+        op_ = _out_ptr(out, f, self.nnodes * nlev * 2, "out")
         _check(self._lib.atlas_nabla_gradient(self._h, _dev_ptr(f, "f"), nlev, _dtype_code(f),
-                                              _dev_ptr(out, "out"), _stream(stream)))
+                                              op_, _stream(stream)))
         return out
 
     def divergence(self, uv, out=None, stream=None):
         nlev = self._nlev_vector(uv)
         if out is None:
             out = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        op_ = _out_ptr(out, uv, self.nnodes * nlev, "out")
         _check(self._lib.atlas_nabla_divergence(self._h, _dev_ptr(uv, "uv"), nlev,
-                                                _dtype_code(uv), _dev_ptr(out, "out"),
-                                                _stream(stream)))
+                                                _dtype_code(uv), op_, _stream(stream)))
         return out
 
     def curl(self, uv, out=None, stream=None):
         nlev = self._nlev_vector(uv)
         if out is None:
             out = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        op_ = _out_ptr(out, uv, self.nnodes * nlev, "out")
         _check(self._lib.atlas_nabla_curl(self._h, _dev_ptr(uv, "uv"), nlev, _dtype_code(uv),
-                                          _dev_ptr(out, "out"), _stream(stream)))
+                                          op_, _stream(stream)))
         return out
 
     def div_curl(self, uv, out_div=None, out_curl=None, stream=None):
@@ -257,18 +286,22 @@ class Mesh:
             out_div = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
         if out_curl is None:
             out_curl = _torch().empty((self.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+        od = _out_ptr(out_div, uv, self.nnodes * nlev, "out_div")
+        oc = _out_ptr(out_curl, uv, self.nnodes * nlev, "out_curl")
         _check(self._lib.atlas_nabla_div_curl(self._h, _dev_ptr(uv, "uv"), nlev, _dtype_code(uv),
-                                              _dev_ptr(out_div, "out_div"),
-                                              _dev_ptr(out_curl, "out_curl"), _stream(stream)))
+                                              od, oc, _stream(stream)))
         return out_div, out_curl
 
     def laplacian(self, f, out=None, workspace=None, stream=None):
         nlev = self._nlev_scalar(f)
         if out is None:
             out = _torch().empty((self.nnodes, nlev), dtype=f.dtype, device=f.device)
-        ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+        op_ = _out_ptr(out, f, self.nnodes * nlev, "out")
+        need = (self.laplacian_workspace_bytes(nlev, _dtype_code(f))
+                if workspace is not None else 0)
+        ws = _ws_ptr(workspace, need)
         _check(self._lib.atlas_nabla_laplacian(self._h, _dev_ptr(f, "f"), nlev, _dtype_code(f),
-                                               _dev_ptr(out, "out"), ws, _stream(stream)))
+                                               op_, ws, _stream(stream)))
         return out
 
     def laplacian_workspace_bytes(self, nlev: int, dtype_code: int) -> int:

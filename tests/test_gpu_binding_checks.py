@@ -1,0 +1,83 @@
+"""The binding refuses outputs and workspaces of the wrong size before any
+launch (so a wrong buffer never reaches a kernel), and a caller-supplied
+workspace of the documented size gives the same bits as the mesh's own
+(two-pass Laplacian with the edge-flux form: gradient, then the fluxes of
+each pass, Section 4.7)."""
+import pytest
+
+from gpu_util import make_inputs
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_06091_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def setup(P):
+    om = oracle.Mesh(24)
+    nlev = 37
+    f, uv = make_inputs(om, nlev)
+    gm = P.Mesh(24)
+    fd = torch.from_numpy(f).cuda()
+    uvd = torch.from_numpy(uv).cuda()
+    return gm, fd, uvd, nlev
+
+
+def test_wrong_output_size_is_refused(P, setup):
+    gm, f, uv, nlev = setup
+    V = gm.nnodes
+    bad = torch.empty(V, nlev, dtype=torch.float64, device="cuda")  # gradient needs [V][nlev][2]
+    with pytest.raises(ValueError):
+        gm.gradient(f, out=bad)
+    with pytest.raises(ValueError):
+        gm.apply(P.ATLAS_OP_GRADIENT, f, out=bad)
+    short = torch.empty(V - 1, nlev, dtype=torch.float64, device="cuda")
+    for call in (lambda: gm.divergence(uv, out=short), lambda: gm.curl(uv, out=short),
+                 lambda: gm.laplacian(f, out=short),
+                 lambda: gm.div_curl(uv, out_div=short),
+                 lambda: gm.div_curl(uv, out_curl=short)):
+        with pytest.raises(ValueError):
+            call()
+    with pytest.raises(TypeError):
+        gm.divergence(uv, out=torch.empty(V, nlev, dtype=torch.float32, device="cuda"))
+
+
+def test_small_workspace_is_refused(P, setup):
+    gm, f, uv, nlev = setup
+    need = gm.laplacian_workspace_bytes(nlev, P.ATLAS_F64)
+    small = torch.empty(need // 8 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        gm.laplacian(f, workspace=small)
+    flux = P.Launch(P.VARIANT_FLUX, 256, 0, 0, 0, 0)
+    just_lapl = torch.empty(need // 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):  # the flux form needs the sum of both
+        gm.apply(P.ATLAS_OP_LAPLACIAN, f, workspace=just_lapl, launch=flux)
+
+
+def test_user_workspace_matches_internal(P, setup):
+    gm, f, uv, nlev = setup
+    flux = P.Launch(P.VARIANT_FLUX, 256, 0, 0, 0, 0)
+    need = (gm.laplacian_workspace_bytes(nlev, P.ATLAS_F64)
+            + gm.flux_workspace_bytes(P.ATLAS_OP_LAPLACIAN, nlev, P.ATLAS_F64))
+    ws = torch.full((need // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    a = gm.apply(P.ATLAS_OP_LAPLACIAN, f, workspace=ws, launch=flux)
+    b = gm.apply(P.ATLAS_OP_LAPLACIAN, f, launch=flux)
+    c = gm.laplacian(f)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+    for op in (P.ATLAS_OP_GRADIENT, P.ATLAS_OP_DIVERGENCE):
+        x = f if op == P.ATLAS_OP_GRADIENT else uv
+        fw = torch.empty(gm.flux_workspace_bytes(op, nlev, P.ATLAS_F64) // 8,
+                         dtype=torch.float64, device="cuda")
+        assert torch.equal(gm.apply(op, x, workspace=fw, launch=flux), gm.apply(op, x))
