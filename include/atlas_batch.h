@@ -83,11 +83,15 @@ atlas_status atlas_batch_free(atlas_batch_t batch);
  * (column / flat / sweep forms, block sizes, tile sizes) for this
  * (mesh, op, dtype, nlev) on the given buffers, remembers the fastest in
  * the mesh (later calls with the same key use it) and returns it.  The
- * Laplacian is tuned pass by pass (gradient into `workspace`, or an
- * internal one when NULL, then its divergence into `out`): later Laplacian
- * calls run each pass with its own tuned shape; *best is the gradient
- * pass's shape, *best_ms the sum of both passes.
- * Errors: as atlas_nabla_apply. */
+ * Laplacian is tuned pass by pass (gradient into `workspace` -- device,
+ * atlas_laplacian_workspace_bytes() bytes -- or a temporary one when NULL,
+ * then its divergence into `out`), and the two tuned passes are timed
+ * against the fused one-pass form (ATLAS_VARIANT_FUSED, 1024 and 768
+ * threads) where the mesh has its plan.  Later Laplacian calls run the
+ * winner: *best is the fused shape if it won, else the gradient pass's
+ * shape; *best_ms the winner's time (both passes summed).
+ * Errors: as atlas_nabla_apply; ATLAS_ENOMEM if the temporary workspace
+ * cannot be allocated. */
 atlas_status atlas_autotune(atlas_mesh_t mesh, atlas_op op, const void *in, int32_t nlev,
                             atlas_dtype dtype, void *out, void *workspace,
                             hipStream_t stream, atlas_launch *best, float *best_ms);

@@ -319,9 +319,12 @@ def autotune(mesh, op: int, x, out, workspace=None, stream=None):
     nlev = mesh._nlev_vector(x) if vec_in else mesh._nlev_scalar(x)
     best = Launch()
     ms = ctypes.c_float()
-    ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+    nout = mesh.nnodes * nlev * (2 if op == ATLAS_OP_GRADIENT else 1)
+    o = _out_ptr(out, x, nout, "out")
+    need = mesh.laplacian_workspace_bytes(nlev, _dtype_code(x)) if op == ATLAS_OP_LAPLACIAN else 0
+    ws = _ws_ptr(workspace, need) if workspace is not None else ctypes.c_void_p()
     _check(lib().atlas_autotune(mesh.handle, int(op), _dev_ptr(x, "x"), nlev, _dtype_code(x),
-                                _dev_ptr(out, "out"), ws, _stream(stream), ctypes.byref(best),
+                                o, ws, _stream(stream), ctypes.byref(best),
                                 ctypes.byref(ms)))
     return best, ms.value
 
@@ -353,8 +356,13 @@ class Batch:
             arr[i].op = int(op)
             arr[i].nlev = nlev
             arr[i].in_ = _dev_ptr(x, "input").value
-            arr[i].out = _dev_ptr(out, "output").value
-            arr[i].workspace = ws.data_ptr() if ws is not None else None
+            nout = mesh.nnodes * nlev * (2 if op == ATLAS_OP_GRADIENT else 1)
+            arr[i].out = _out_ptr(out, x, nout, "output").value
+            if ws is not None:
+                need = mesh.laplacian_workspace_bytes(nlev, d) if op == ATLAS_OP_LAPLACIAN else 0
+                arr[i].workspace = _ws_ptr(ws, need).value
+            else:
+                arr[i].workspace = None
             self._keep.append((mesh, x, out, ws))
         cfg = _abi.BatchConfig(dtype, int(use_graph), int(autotune), int(block_threads),
                                int(blocks_per_cu), int(solo_min_elems))
