@@ -433,6 +433,7 @@ class Server:
         self._h = ctypes.c_void_p()
         self._keep = {}
         self._meshes = []
+        self._nnodes = {}  # mesh id -> nodes, to check request buffers
         _check(self._lib.atlas_serve_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self.simulate = bool(simulate)
 
@@ -440,11 +441,13 @@ class Server:
         mid = ctypes.c_int32()
         _check(self._lib.atlas_serve_register_mesh(self._h, mesh.handle, ctypes.byref(mid)))
         self._meshes.append(mesh)
+        self._nnodes[mid.value] = mesh.nnodes
         return mid.value
 
     def register_sim_mesh(self, nnodes: int) -> int:
         mid = ctypes.c_int32()
         _check(self._lib.atlas_serve_register_sim_mesh(self._h, int(nnodes), ctypes.byref(mid)))
+        self._nnodes[mid.value] = int(nnodes)
         return mid.value
 
     def submit(self, mesh_id: int, op: int, x=None, out=None, *, nlev=None, dtype=None) -> int:
@@ -458,9 +461,17 @@ class Server:
             lev = x.shape[1] if x.dim() >= 2 else 1
             if vec_in and (x.dim() != 3 or x.shape[2] != 2):
                 raise ValueError("vector input must be [V][nlev][2]")
+            V = self._nnodes.get(int(mesh_id))
+            if V is not None and x.shape[0] != V:
+                raise ValueError(f"input has {x.shape[0]} nodes, mesh {mesh_id} has {V}")
+            if V is not None and x.numel() != V * lev * (2 if vec_in else 1):
+                raise ValueError("input must be [V][nlev] (scalar) or [V][nlev][2] (vector)")
+            o = None
+            if out is not None:
+                nout = (V or x.shape[0]) * lev * (2 if op == ATLAS_OP_GRADIENT else 1)
+                o = _out_ptr(out, x, nout, "output").value
             req = _abi.Request(int(mesh_id), int(op), _dtype_code(x), int(lev),
-                               _dev_ptr(x, "input").value,
-                               _dev_ptr(out, "output").value if out is not None else None)
+                               _dev_ptr(x, "input").value, o)
         t = ctypes.c_uint64()
         _check(self._lib.atlas_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (x, out)
