@@ -81,3 +81,13 @@ def test_user_workspace_matches_internal(P, setup):
         fw = torch.empty(gm.flux_workspace_bytes(op, nlev, P.ATLAS_F64) // 8,
                          dtype=torch.float64, device="cuda")
         assert torch.equal(gm.apply(op, x, workspace=fw, launch=flux), gm.apply(op, x))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_bandwidth_probe_writes_each_element_twice(P, dtype):
+    n = 1000006  # spans many blocks and a partial last block
+    x = torch.randn(n, dtype=torch.float64, device="cuda").to(dtype)
+    y = torch.full((2 * n,), float("nan"), dtype=dtype, device="cuda")
+    P.bandwidth_probe(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, x.repeat_interleave(2))
