@@ -514,6 +514,22 @@ def main():
         del xF, gF
         torch.cuda.empty_cache()
 
+    # one GPU's share when the levels are split over eight GPUs (the larger
+    # share: ceil(nlev / 8) levels, 18 of 137), FP64 gradient, default shape
+    slab = {}
+    if not args.no_extra_ops:
+        ls = (nlev + 7) // 8
+        xs = f64[:, :ls].contiguous()
+        os_ = torch.empty(V, ls, 2, dtype=torch.float64, device=dev)
+        t = time_op(lambda: gm.gradient(xs, out=os_), max(5, args.steps // 2), 2, torch)
+        b = 3 * V * ls * 8 + geo
+        slab = {"gpus": 8, "nlev": ls, "grad_f64_ms": round(t, 4),
+                "edge_level_per_s": E * ls / (t * 1e-3),
+                "GBps": round(b / (t * 1e-3) / 1e9, 1),
+                "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del xs, os_
+        torch.cuda.empty_cache()
+
     sha = kernel_source_sha()
     rec = counters_for(sha)
     traffic = None
@@ -570,6 +586,7 @@ def main():
         "cpu_baseline": cpu,
         "ops": ops,
         "other_grids": grids,
+        "level_slab_share": slab,
         "accuracy_vs_oracle": acc,
         "batch": batch,
         "serving": serving,

@@ -165,3 +165,31 @@ def test_o1280_longest_columns_allowed(big, dtype):
             del over
         del x, xl
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nlev", [1, 17])
+def test_o1280_short_columns_sampled(big, nlev, dtype):
+    """O1280 with one level and with 17 levels (one GPU's slab when 137
+    levels are split over eight GPUs), in the default shapes of those sizes,
+    against the oracle at the sampled nodes (the first nlev levels of the
+    benchmark fields)."""
+    from gpu_util import TOL, normwise_error
+    P, gm, om, nodes = big["P"], big["gm"], big["om"], big["nodes"]
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    print(f"fullsize short columns nlev={nlev} {dtype}", flush=True)
+    for op, name in (("grad", "f"), ("div", "uv"), ("curl", "uvr"), ("lapl", "f")):
+        x = big[name][:, :nlev].contiguous().to(dt)
+        fn = {"grad": gm.gradient, "div": gm.divergence, "curl": gm.curl,
+              "lapl": gm.laplacian}[op]
+        got = fn(x).index_select(0, big["nodes_d"]).double().cpu().numpy()
+        xh = x.double().cpu().numpy()
+        ofn = {"grad": om.gradient_at, "div": om.divergence_at, "curl": om.curl_at,
+               "lapl": om.laplacian_at}[op]
+        ref = ofn(xh, nlev, nodes)
+        del x, xh
+        emax, erms = normwise_error(got, ref)
+        print(f"O1280 L{nlev} {op} {dtype}: max_rel={emax:.3e} rms_rel={erms:.3e}", flush=True)
+        assert np.isfinite(got).all()
+        assert emax <= TOL[dtype], (op, nlev, dtype, emax)
+    torch.cuda.empty_cache()
