@@ -2179,13 +2179,21 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
 // lane-vector width, except: the FP64 gradient runs the level-vector sweep
 // (768 threads), the FP32 gradient one level per lane (its compensated sums
 // keep every lane busy that way).  The Laplacian takes each pass's own
-// shape.  Short columns: the flat form over the mesh's tiles.
+// shape.  Short columns (measured at O320 and O1280, 1 to 47 levels, within
+// 1.3x of the best candidate everywhere, 2-4x faster than the flat form over
+// the mesh's tiles): below 24 levels the flat form over blocks of 64
+// positions (512 threads); from 24 levels the column form over blocks of 16
+// positions, one level per lane (FP64 divergence and curl: the automatic
+// lane-vector width), and on meshes of many tiles the level-vector sweep for
+// the FP32 gradient.
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   LaunchShape s;
-  s.variant = nlev >= 48 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
-  s.block = 256;
-  s.nodes_per_block = s.variant == ATLAS_VARIANT_COLUMN ? 16 : 0;
+  s.variant = nlev >= 24 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
+  s.block = nlev >= 24 ? 256 : 512;
+  s.nodes_per_block = nlev >= 24 ? 16 : 64;
   s.level_vec = 0;
+  const bool sweep_fits = m.d.sweep_ok && m.d.ntiles >= kSweepMinTiles &&
+                          max(1, m.d.segmax) * kGeoWords <= 768;
   if (op == ATLAS_OP_LAPLACIAN) {
     // FP64 on large meshes: the fused one-pass form (it moves a third of the
     // two passes' field bytes; in FP32 the two passes are still faster)
@@ -2199,12 +2207,21 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
     s.per_pass = 1;
     return s;
   }
-  if (nlev < 48) return s;
-  if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) s.level_vec = 1;
+  if (nlev < 24) return s;
   // the sweep runs one workgroup per tile and level chunk, each walking its
   // band's parallels in turn: only a mesh of many tiles fills the chip
-  if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && m.d.sweep_ok &&
-      m.d.ntiles >= kSweepMinTiles && max(1, m.d.segmax) * kGeoWords <= 768) {
+  if (nlev < 48) {
+    if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT && sweep_fits) {
+      s.variant = ATLAS_VARIANT_SWEEP;
+      s.block = 768;
+      s.nodes_per_block = 0;
+    } else if (!(dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL))) {
+      s.level_vec = 1;
+    }
+    return s;
+  }
+  if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) s.level_vec = 1;
+  if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && sweep_fits) {
     s.variant = ATLAS_VARIANT_SWEEP;
     s.block = 768;
     s.nodes_per_block = 0;
