@@ -200,21 +200,18 @@ def accuracy(gm, om, f64, uv64, torch, np, nsample=2000):
     return res
 
 
-def batch_bench(P, torch, np, dev):
-    """64 FP32 work items over O80/O160/O320 with nlev in {1,10,91,137} and
-    operators in {grad, div, lapl}, autotuned and captured in a hipGraph
-    (items of 2^22+ elements as their own launches, the rest in the
-    persistent launch): replay time against the same items launched one by
-    one."""
+def batch_items(P, torch, np, dev, grids, nlevs, seed):
+    """64 seeded FP32 work items: grid from `grids`, nlev from `nlevs`,
+    operator from {grad, div, lapl}."""
     import synthetic as sy
-    rng = np.random.default_rng(64)
-    meshes = {N: P.Mesh(N) for N in (80, 160, 320)}
+    rng = np.random.default_rng(seed)
+    meshes = {N: P.Mesh(N) for N in grids}
     lonlat = {N: P.mesh_desc_octahedral(N) for N in meshes}
     fields = {}
     items, edges_levels = [], 0
     for i in range(64):
-        N = int(rng.choice([80, 160, 320]))
-        nlev = int(rng.choice([1, 10, 91, 137]))
+        N = int(rng.choice(list(grids)))
+        nlev = int(rng.choice(list(nlevs)))
         op = ["grad", "div", "lapl"][int(rng.integers(0, 3))]
         gm = meshes[N]
         if N not in fields:
@@ -237,6 +234,32 @@ def batch_bench(P, torch, np, dev):
         items.append((gm, code, x, out))
         edges_levels += gm.nedges * nlev * (2 if op == "lapl" else 1)
     torch.cuda.synchronize()
+    return items, meshes, edges_levels, rng
+
+
+def batch_small_items(P, torch, np, dev):
+    """64 small FP32 items (O80, nlev in {1, 10}): launch overhead dominates,
+    which one persistent launch replayed from a graph removes."""
+    items, _, _, _ = batch_items(P, torch, np, dev, (80,), (1, 10), 65)
+    b = P.Batch(items, use_graph=True)
+    ms_batch = time_op(lambda: b.launch(), 20, 3, torch)
+    out_b = [it[3].clone() for it in items]
+    ms_seq = time_op(lambda: [gm.apply(c, x, out=o) for gm, c, x, o in items], 20, 3, torch)
+    same = all(torch.equal(a, it[3]) for a, it in zip(out_b, items))
+    b.close()
+    return {"items": 64, "mix": "O80, nlev 1/10, grad/div/lapl, f32", "ms_batch": round(ms_batch, 4),
+            "ms_one_by_one": round(ms_seq, 4), "speedup": round(ms_seq / ms_batch, 3),
+            "bitwise_equal_to_solo": bool(same)}
+
+
+def batch_bench(P, torch, np, dev):
+    """64 FP32 work items over O80/O160/O320 with nlev in {1,10,91,137} and
+    operators in {grad, div, lapl}, autotuned and captured in a hipGraph
+    (items of 2^22+ elements as their own launches, the rest in the
+    persistent launch): replay time against the same items launched one by
+    one."""
+    items, meshes, edges_levels, rng = batch_items(P, torch, np, dev, (80, 160, 320),
+                                                   (1, 10, 91, 137), 64)
     t0 = time.perf_counter()
     b = P.Batch(items, use_graph=True, autotune=True)
     build_s = time.perf_counter() - t0
@@ -553,6 +576,7 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_bench(P, torch, np, dev)
+        batch["small_items"] = batch_small_items(P, torch, np, dev)
         print("# batch done", file=sys.stderr, flush=True)
     serving = None
     if not args.no_serve:
