@@ -148,11 +148,18 @@ static float time_shape(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev
   return best;
 }
 
-static std::vector<atlas_launch> candidates(const MeshStore &m, int nlev) {
+static std::vector<atlas_launch> candidates(const MeshStore &m, atlas_op op, atlas_dtype dt,
+                                            int nlev) {
   std::vector<atlas_launch> c;
   auto add = [&](int v, int b, int npb, int kc, int bpc, int lv) {
     c.push_back({v, b, npb, kc, bpc, lv});
   };
+  // the built-in shape first, so that a tuned shape is never one that lost
+  // to it
+  {
+    const LaunchShape d = default_shape(m, op, nlev, dt);
+    add(d.variant, d.block, d.nodes_per_block, d.level_chunk, d.blocks_per_cu, d.level_vec);
+  }
   if (nlev >= 32) {
     for (int lv : {0, 1, 2, 3}) add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0, lv);
     add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 0, 0);
@@ -168,7 +175,13 @@ static std::vector<atlas_launch> candidates(const MeshStore &m, int nlev) {
   add(ATLAS_VARIANT_FLAT, 256, fl, 0, 0, 0);
   add(ATLAS_VARIANT_FLAT, 256, std::max(1, fl / 4), 0, 0, 0);
   add(ATLAS_VARIANT_FLAT, 256, 0, 0, 0, 0);
-  if (nlev < 32) add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 256, 32, 0, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 512, 64, 0, 0, 0);
+  add(ATLAS_VARIANT_FLAT, 1024, 128, 0, 0, 0);
+  if (nlev < 32) {
+    add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0, 0);
+    add(ATLAS_VARIANT_COLUMN, 256, 16, 0, 0, 1);
+  }
   return c;
 }
 
@@ -186,7 +199,7 @@ static atlas_status tune_one(atlas_mesh_t mesh, atlas_op op, const void *in, int
   }
   float bt = 1e30f;
   atlas_launch bl{};
-  for (const atlas_launch &c : candidates(m, nlev)) {
+  for (const atlas_launch &c : candidates(m, op, dt, nlev)) {
     const float t = time_shape(mesh, op, in, nlev, dt, out, nullptr, c, st, e0, e1);
     if (t >= 0.0f && t < bt) {
       bt = t;
