@@ -726,12 +726,24 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
 // Same schedules as k_column (tiled, or persistent wave-cyclic).  The
 // occupancy hint lets the register allocator keep a node's whole load burst
 // in flight (at the default target it delays part of the burst to save
-// registers, and each delayed load is then waited for on its own).
-template <int NCH> constexpr int colv_waves() { return NCH <= 2 ? 4 : 2; }
+// registers, and each delayed load is then waited for on its own).  Four
+// waves per SIMD where the burst fits 128 registers without spilling: up to
+// two chunks, and FP64 lanes of at most 16 bytes (the FP64 divergence at
+// 137 levels: 97 registers and 7.31 ms, against 169 and 7.73 ms at two
+// waves); otherwise two.
+template <class T, int LB, int NCH> constexpr int colv_waves() {
+  return NCH <= 2 || (sizeof(T) == 8 && LB <= 16) ? 4 : 2;
+}
+// The same for the one-pass divergence + curl (two states per level).
+template <class T, int NV, int NCH> constexpr int colv_dc_waves() {
+  return NCH <= 2 || (sizeof(T) == 8 && NV == 1 && NCH == 3) ? 4 : 2;
+}
 
 template <class T, int OP, int NV, int NCH>
 __global__ void __launch_bounds__(512)
-    __attribute__((amdgpu_waves_per_eu(colv_waves<NCH>(), colv_waves<NCH>())))
+    __attribute__((amdgpu_waves_per_eu(
+        colv_waves<T, NV * (int)sizeof(typename Pol<T, OP>::V), NCH>(),
+        colv_waves<T, NV * (int)sizeof(typename Pol<T, OP>::V), NCH>())))
     k_colv(DevMesh m, const T *__restrict__ in,
                                                T *__restrict__ out, int nlev, int npb,
                                                int per_xcd, int cyc) {
@@ -873,7 +885,7 @@ __device__ __forceinline__ void colv_node_dc(const DevMesh &m, const T *__restri
 
 template <class T, int NV, int NCH>
 __global__ void __launch_bounds__(512)
-    __attribute__((amdgpu_waves_per_eu(colv_waves<NCH>(), colv_waves<NCH>())))
+    __attribute__((amdgpu_waves_per_eu(colv_dc_waves<T, NV, NCH>(), colv_dc_waves<T, NV, NCH>())))
     k_colv_dc(DevMesh m, const T *__restrict__ in, T *__restrict__ out_d,
               T *__restrict__ out_c, int nlev, int npb, int per_xcd) {
   const int nw = blockDim.x >> 6;
