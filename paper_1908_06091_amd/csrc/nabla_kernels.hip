@@ -726,17 +726,19 @@ __device__ __forceinline__ void colv_node(const DevMesh &m, const T *__restrict_
 // Same schedules as k_column (tiled, or persistent wave-cyclic).  The
 // occupancy hint lets the register allocator keep a node's whole load burst
 // in flight (at the default target it delays part of the burst to save
-// registers, and each delayed load is then waited for on its own).  Four
-// waves per SIMD where the burst fits 128 registers without spilling: up to
-// two chunks, and FP64 lanes of at most 16 bytes (the FP64 divergence at
-// 137 levels: 97 registers and 7.31 ms, against 169 and 7.73 ms at two
-// waves); otherwise two.
+// registers, and each delayed load is then waited for on its own).  The
+// most waves per SIMD at which the burst fits without spilling: five for
+// FP32 in one chunk (the FP32 divergence at 137 levels: 85 registers and
+// 4.55 ms, against 97 and 4.75 ms at four); four up to two chunks, and for
+// FP64 lanes of at most 16 bytes (the FP64 divergence: 97 registers and
+// 7.31 ms, against 169 and 7.73 ms at two); otherwise two.
 template <class T, int LB, int NCH> constexpr int colv_waves() {
-  return NCH <= 2 || (sizeof(T) == 8 && LB <= 16) ? 4 : 2;
+  return sizeof(T) == 4 && NCH == 1 ? 5 : NCH <= 2 || (sizeof(T) == 8 && LB <= 16) ? 4 : 2;
 }
 // The same for the one-pass divergence + curl (two states per level).
 template <class T, int NV, int NCH> constexpr int colv_dc_waves() {
-  return NCH <= 2 || (sizeof(T) == 8 && NV == 1 && NCH == 3) ? 4 : 2;
+  return sizeof(T) == 4 && NCH == 1 && NV <= 3 ? 5
+         : NCH <= 2 || (sizeof(T) == 8 && NV == 1 && NCH == 3) ? 4 : 2;
 }
 
 template <class T, int OP, int NV, int NCH>
