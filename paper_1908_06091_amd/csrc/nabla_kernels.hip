@@ -2199,7 +2199,7 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
 // positions (512 threads); from 24 levels the column form over blocks of 16
 // positions, one level per lane (FP64 divergence and curl: the automatic
 // lane-vector width), and on meshes of many tiles the level-vector sweep for
-// the FP32 gradient.
+// the FP32 gradient (up to 79 levels).
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   LaunchShape s;
   s.variant = nlev >= 24 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
@@ -2234,7 +2234,18 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
     }
     return s;
   }
-  if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) s.level_vec = 1;
+  if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) {
+    s.level_vec = 1;
+    // up to ~80 levels the sweep's single read of each column wins over the
+    // compensated sums' lane work (64 levels: 2.08 ms against 2.52 ms at
+    // O1280); beyond, one level per lane (91 levels: 3.02 against 3.30 ms)
+    if (nlev < 80 && sweep_fits) {
+      s.variant = ATLAS_VARIANT_SWEEP;
+      s.block = 768;
+      s.nodes_per_block = 0;
+      s.level_vec = 0;
+    }
+  }
   if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && sweep_fits) {
     s.variant = ATLAS_VARIANT_SWEEP;
     s.block = 768;
