@@ -42,6 +42,10 @@
  *                     median-dual polygons built independently in the tests
  *   gradient       -> exact for linear data (interior), zero for constants,
  *                     Galerkin identity sum_T |T|/3 grad(phi_T) (brute force)
+ *   polar nodes    -> pole-face value recovered from the output against
+ *                     brute-force polar cells: exact for fields vanishing at
+ *                     the pole, the node value for even orders, second-order
+ *                     convergence to the analytic pole value
  *   divergence     -> exact special cases, telescoping sum(V div) = 0
  *   curl           -> exact special cases, telescoping sum(V curl) = 0
  *   Laplacian      -> spherical-harmonic eigenvalue convergence
