@@ -70,6 +70,10 @@ def _load():
                      "orc_laplacian_at"):
             getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_int, _c_dp,
                                            ctypes.c_int64, _c_i64p, _c_dp]
+        lib.orc_remap_weights.argtypes = [ctypes.c_void_p, ctypes.c_int64, _c_dp, _c_dp,
+                                          _c_i32p, _c_dp]
+        lib.orc_remap_apply.argtypes = [ctypes.c_int64, ctypes.c_int64, _c_i32p, _c_dp,
+                                        ctypes.c_int, _c_dp, _c_dp]
         _lib = lib
         return lib
 
@@ -230,3 +234,44 @@ class Mesh:
         if rc != 0:
             raise ValueError("orc_laplacian_at failed")
         return out
+
+    # -- remap to other points (Section 1: interpolation between grids) -----
+    def remap_weights(self, lon, lat):
+        """Source nodes and weights of the P1 interpolant on this mesh's
+        triangles at the target points (lon, lat in radians): two arrays of
+        shape [nt][3] (int32 node ids, FP64 weights).  Targets poleward of
+        the polar parallels take the linear interpolant along that parallel
+        (two nonzero weights)."""
+        lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
+        lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
+        if lon.size != lat.size:
+            raise ValueError("lon and lat must have the same size")
+        idx = np.empty((lon.size, 3), np.int32)
+        w = np.empty((lon.size, 3), np.float64)
+        rc = self._lib.orc_remap_weights(self._h, lon.size, _dp(lon), _dp(lat),
+                                         idx.ctypes.data_as(_c_i32p), _dp(w))
+        if rc != 0:
+            raise ValueError("a target latitude is outside [-pi/2, pi/2] or not finite")
+        return idx, w
+
+    def remap(self, x, ncol: int, lon, lat) -> np.ndarray:
+        """Field x [V][ncol] of this mesh (ncol values per node: levels, or
+        levels x components) interpolated to the target points: [nt][ncol]."""
+        idx, w = self.remap_weights(lon, lat)
+        return remap_apply(idx, w, x, ncol, self.V)
+
+
+def remap_apply(idx, w, x, ncol: int, nsrc: int) -> np.ndarray:
+    """out[t] = sum_k w[t][k] x[idx[t][k]] (k = 0, 1, 2 in that order), for
+    x of nsrc nodes with ncol values each."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.size != nsrc * ncol or idx.shape != w.shape or idx.ndim != 2 or idx.shape[1] != 3:
+        raise ValueError("shapes: idx, w [nt][3]; x [nsrc][ncol]")
+    out = np.empty((idx.shape[0], ncol), np.float64)
+    rc = _load().orc_remap_apply(nsrc, idx.shape[0], idx.ctypes.data_as(_c_i32p), _dp(w),
+                                 int(ncol), _dp(x), _dp(out))
+    if rc != 0:
+        raise ValueError("source index out of range")
+    return out

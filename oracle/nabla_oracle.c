@@ -708,3 +708,130 @@ int orc_laplacian_at(const orc_mesh *m, int nlev, const double *f,
   free(slot); free(nodes); free(g);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Remap: interpolation of a nodal field of this mesh to other points       */
+/* (Section 1 lists remapping / interpolation of fields between different   */
+/* grids among the mathematical operations; the paper gives no method).     */
+/* Reading taken here: the value at a target point is the piecewise-linear  */
+/* (P1) interpolant of the nodal values on this mesh's triangles, in the    */
+/* (lon, lat) plane with longitudes unwrapped round the target:             */
+/*   out(t) = sum over the three vertices k of the containing triangle of   */
+/*            w_k(t) * in(vertex k),                                        */
+/* w_k the barycentric coordinates of t.  A target poleward of the first    */
+/* (last) parallel takes the linear interpolant along that parallel at its  */
+/* longitude (the field continued to the pole unchanged in latitude): the   */
+/* two bracketing nodes of the parallel, weights (1 - s, s).  Levels are    */
+/* independent (vertical extrusion, Section 4.3), so the same weights serve */
+/* every level.                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Twice the signed area of (p, q, r). */
+static double cross3(double px, double py, double qx, double qy, double rx, double ry) {
+  return (qx - px) * (ry - py) - (qy - py) * (rx - px);
+}
+
+/* Barycentric coordinates of (x, y) in the triangle (X[k], Y[k]): each
+ * coordinate is the area of the sub-triangle opposite vertex k over the
+ * triangle's area, the latter taken from vertex k itself (so a target on a
+ * vertex gets exactly 1 there and 0 elsewhere). */
+static void barycentric(const double *X, const double *Y, double x, double y, double *w) {
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    const double whole = cross3(X[k], Y[k], X[k1], Y[k1], X[k2], Y[k2]);
+    const double part = cross3(x, y, X[k1], Y[k1], X[k2], Y[k2]);
+    w[k] = part / whole;
+  }
+}
+
+/* Weights of one target; returns 0, or -1 for a latitude outside
+ * [-pi/2, pi/2] or a non-finite coordinate. */
+static int remap_one(const orc_mesh *m, const int64_t *toff, double lon, double lat,
+                     int32_t *idx, double *w) {
+  if (!isfinite(lon) || !isfinite(lat) || lat > 0.5 * ORC_PI || lat < -0.5 * ORC_PI) return -1;
+  double x = fmod(lon, 2.0 * ORC_PI);
+  if (x < 0.0) x += 2.0 * ORC_PI;
+  if (x >= 2.0 * ORC_PI) x = 0.0;
+  const int nr = m->nrings;
+  const double lat_first = m->lat[m->ring_off[0]];
+  const double lat_last = m->lat[m->ring_off[nr - 1]];
+  if (lat > lat_first || lat < lat_last) {
+    /* polar cap: along the polar parallel */
+    const int j = lat > lat_first ? 0 : nr - 1;
+    const int64_t o = m->ring_off[j];
+    const int n = m->nx[j];
+    int i = 0;
+    while (i + 1 < n && m->lon[o + i + 1] <= x) ++i;
+    const double x0 = m->lon[o + i];
+    const double x1 = (i + 1 < n) ? m->lon[o + i + 1] : m->lon[o] + 2.0 * ORC_PI;
+    const double s = (x - x0) / (x1 - x0);
+    idx[0] = (int32_t)(o + i);
+    idx[1] = (int32_t)(o + (i + 1) % n);
+    idx[2] = (int32_t)(o + i);
+    w[0] = 1.0 - s;
+    w[1] = s;
+    w[2] = 0.0;
+    return 0;
+  }
+  /* the first strip whose lower parallel is at or below the target */
+  int j = 0;
+  while (j + 2 < nr && m->lat[m->ring_off[j + 1]] > lat) ++j;
+  /* the strip's triangle that contains the target most clearly: the one
+   * whose smallest barycentric coordinate is largest (first on ties) */
+  double best = -HUGE_VAL;
+  for (int64_t t = toff[j]; t < toff[j + 1]; ++t) {
+    /* the triangle kept whole: its first vertex unwrapped round the
+     * target, the other two round the first vertex */
+    double X[3], Y[3], wt[3];
+    for (int k = 0; k < 3; ++k) {
+      const int32_t v = m->tri[3 * t + k];
+      X[k] = k == 0 ? unwrap(m->lon[v], x) : unwrap(m->lon[v], X[0]);
+      Y[k] = m->lat[v];
+    }
+    barycentric(X, Y, x, lat, wt);
+    double mn = wt[0];
+    if (wt[1] < mn) mn = wt[1];
+    if (wt[2] < mn) mn = wt[2];
+    if (mn > best) {
+      best = mn;
+      for (int k = 0; k < 3; ++k) {
+        idx[k] = m->tri[3 * t + k];
+        w[k] = wt[k];
+      }
+    }
+  }
+  return 0;
+}
+
+int orc_remap_weights(const orc_mesh *m, int64_t nt, const double *lon, const double *lat,
+                      int32_t *idx, double *w) {
+  const int nr = m->nrings;
+  int64_t *toff = (int64_t *)malloc(sizeof(int64_t) * nr);
+  if (!toff) return -2;
+  toff[0] = 0;
+  for (int j = 0; j + 1 < nr; ++j) toff[j + 1] = toff[j] + m->nx[j] + m->nx[j + 1];
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+  for (int64_t t = 0; t < nt; ++t)
+    bad |= remap_one(m, toff, lon[t], lat[t], idx + 3 * t, w + 3 * t) != 0;
+  free(toff);
+  return bad ? -1 : 0;
+}
+
+/* out[t][k] = w[t][0] in[idx[t][0]][k] + w[t][1] in[idx[t][1]][k]
+ *           + w[t][2] in[idx[t][2]][k], summed in that order.  ncol values
+ * per node (levels, or levels x components). */
+int orc_remap_apply(int64_t nsrc, int64_t nt, const int32_t *idx, const double *w, int ncol,
+                    const double *in, double *out) {
+  for (int64_t t = 0; t < 3 * nt; ++t)
+    if (idx[t] < 0 || idx[t] >= nsrc) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nt; ++t) {
+    const double *a = in + (int64_t)idx[3 * t] * ncol;
+    const double *b = in + (int64_t)idx[3 * t + 1] * ncol;
+    const double *c = in + (int64_t)idx[3 * t + 2] * ncol;
+    double *o = out + t * ncol;
+    for (int k = 0; k < ncol; ++k) o[k] = w[3 * t] * a[k] + w[3 * t + 1] * b[k] + w[3 * t + 2] * c[k];
+  }
+  return 0;
+}
