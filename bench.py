@@ -43,6 +43,9 @@ def parse_args():
     ap.add_argument("--nlev", type=int, default=137)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-ops", action="store_true")
+    ap.add_argument("--ops", type=str, default="",
+                    help="comma list of the extra operators to time (default: all)")
+    ap.add_argument("--no-other-grids", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=137,
                     help="levels of the workload the CPU oracle sample covers")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -104,7 +107,11 @@ def make_field(om_lon, om_lat, nlev, dtype, device, torch):
     return f.to(dtype), uv.to(dtype), np
 
 
-def time_op(fn, steps, warmup, torch):
+def time_op(fn, steps, warmup, torch, stats=None):
+    """Mean ms per call over `steps` back-to-back calls, bracketed by two
+    events on the launch stream.  With `stats` (a dict), each call is also
+    timed on its own between two events, and the median, min and max of
+    those per-call times are stored in it."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -115,7 +122,19 @@ def time_op(fn, steps, warmup, torch):
         fn()
     end.record()
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps  # ms per launch sequence
+    mean = start.elapsed_time(end) / steps  # ms per launch sequence
+    if stats is not None:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(max(steps, 20))]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        per = sorted(a.elapsed_time(b) for a, b in ev)
+        stats.update({"median_ms": round(per[len(per) // 2], 4), "min_ms": round(per[0], 4),
+                      "max_ms": round(per[-1], 4), "reps": len(per)})
+    return mean
 
 
 def _cpu_model():
@@ -467,7 +486,8 @@ def main():
 
     # headline: FP64 gradient
     out = torch.empty(V, nlev, 2, dtype=torch.float64, device=dev)
-    ms = time_op(lambda: gm.gradient(f64, out=out), args.steps, args.warmup, torch)
+    head_stats = {}
+    ms = time_op(lambda: gm.gradient(f64, out=out), args.steps, args.warmup, torch, head_stats)
     value = E * nlev / (ms * 1e-3)
     achieved = alg_bytes("grad", 8) / (ms * 1e-3) / 1e9
 
@@ -476,12 +496,15 @@ def main():
     ceiling = 3 * V * nlev * 8 / (ceil_ms * 1e-3) / 1e9
 
     ops = {}
+    want = set(x for x in args.ops.split(",") if x)
     if not args.no_extra_ops:
         f32, uv32 = f64.float(), uv64.float()
         for name, dt, fn_in, w in (("div_f64", "f64", uv64, 8), ("lapl_f64", "f64", f64, 8),
                                    ("curl_f64", "f64", uv64, 8), ("divcurl_f64", "f64", uv64, 8),
                                    ("grad_f32", "f32", f32, 4), ("div_f32", "f32", uv32, 4),
                                    ("lapl_f32", "f32", f32, 4), ("divcurl_f32", "f32", uv32, 4)):
+            if want and name not in want:
+                continue
             opname = name.split("_")[0]
             if opname == "divcurl":
                 o = (torch.empty(V, nlev, dtype=fn_in.dtype, device=dev),
@@ -499,25 +522,30 @@ def main():
             else:
                 o = torch.empty(V, nlev, dtype=fn_in.dtype, device=dev)
                 fn = lambda o=o, x=fn_in: gm.laplacian(x, out=o)
-            t = time_op(fn, max(5, args.steps // 2), 2, torch)
-            b = alg_bytes(opname, w)
+            st = {}
+            t = time_op(fn, max(5, args.steps // 2), 2, torch, st)
             napp = 2 if opname == "divcurl" else 1  # operator applications per call
-            ops[name] = {"ms": round(t, 4), "edge_level_per_s": napp * E * nlev / (t * 1e-3),
+            fused = opname == "lapl" and gm.shape_of(P.ATLAS_OP_LAPLACIAN, nlev, fn_in)["variant"] \
+                == P.VARIANT_FUSED
+            # the bytes of the form that runs: the fused Laplacian reads the
+            # field once and writes the result (2 V L w + G)
+            b = 2 * V * nlev * w + geo if fused else alg_bytes(opname, w)
+            ops[name] = {"ms": round(t, 4), **st,
+                         "edge_level_per_s": napp * E * nlev / (t * 1e-3),
                          "GBps": round(b / (t * 1e-3) / 1e9, 1),
                          "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             if opname == "lapl":
-                # GBps above: the two passes' bytes (6 V L w + 2 G); the fused
-                # one-pass form (the FP64 default) needs only 2 V L w + G
-                b1 = 2 * V * nlev * w + geo
-                ops[name]["bytes_model"] = "two passes: 6*V*L*w + 2*G"
-                ops[name]["one_pass_GBps"] = round(b1 / (t * 1e-3) / 1e9, 1)
-                ops[name]["one_pass_hbm_frac"] = round(b1 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                ops[name]["form"] = "fused one pass" if fused else "two passes"
+                ops[name]["bytes_model"] = ("2*V*L*w + G" if fused else "6*V*L*w + 2*G")
+                if fused:
+                    b2 = alg_bytes("lapl", w)
+                    ops[name]["two_pass_equiv_frac"] = round(b2 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             del o
 
     # another reduced Gaussian grid: the regular grid F640 (nx = 2560 on all
     # 1280 parallels, 3.28 M nodes), default shapes
     grids = {}
-    if not args.no_extra_ops:
+    if not args.no_extra_ops and not args.no_other_grids:
         nxF = P.regular_gaussian_nx(640)
         gF = P.Mesh(nx=nxF)
         VF, EF, geoF = gF.nnodes, gF.nedges, gF.info.geometry_bytes_per_call
@@ -540,7 +568,7 @@ def main():
     # one GPU's share when the levels are split over eight GPUs (the larger
     # share: ceil(nlev / 8) levels, 18 of 137), FP64 gradient, default shape
     slab = {}
-    if not args.no_extra_ops:
+    if not args.no_extra_ops and not args.no_other_grids:
         ls = (nlev + 7) // 8
         xs = f64[:, :ls].contiguous()
         os_ = torch.empty(V, ls, 2, dtype=torch.float64, device=dev)
@@ -594,6 +622,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "per_launch_ms": head_stats,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -292,6 +292,16 @@ atlas_status atlas_nabla_apply(atlas_mesh_t mesh, atlas_op op, const void *in,
 size_t atlas_flux_workspace_bytes(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
                                   atlas_dtype dtype);
 
+/* The launch shape the named entry point of `op` runs with `nlev` levels and
+ * `dtype` on this mesh (the autotuned shape if one is stored, else the
+ * built-in one).  For the Laplacian, variant ATLAS_VARIANT_FUSED means the
+ * one-pass form runs; otherwise the two passes run and `out` is the
+ * gradient pass's shape (the divergence pass is what ATLAS_OP_DIVERGENCE
+ * reports).  `out`: host struct, written on success.  Errors: ATLAS_EINVAL
+ * for a NULL argument, an unknown op or dtype, nlev < 1. */
+atlas_status atlas_nabla_get_shape(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
+                                   atlas_dtype dtype, atlas_launch *out);
+
 /* Streaming reference with the gradient's byte pattern: reads n elements of
  * `in` and writes each twice into `out` (2n elements), fully coalesced.
  * Used to report the practically reachable HBM bandwidth next to the

@@ -307,6 +307,15 @@ class Mesh:
     def laplacian_workspace_bytes(self, nlev: int, dtype_code: int) -> int:
         return int(self._lib.atlas_laplacian_workspace_bytes(self._h, int(nlev), int(dtype_code)))
 
+    def shape_of(self, op: int, nlev: int, like) -> dict:
+        """The launch shape the named entry point of `op` runs for `nlev`
+        levels in the dtype of tensor `like` (or a dtype code)."""
+        dc = like if isinstance(like, int) else _dtype_code(like)
+        sh = Launch()
+        _check(self._lib.atlas_nabla_get_shape(self._h, int(op), int(nlev), int(dc),
+                                               ctypes.byref(sh)))
+        return {k: getattr(sh, k) for k, _ in Launch._fields_}
+
     def flux_workspace_bytes(self, op: int, nlev: int, dtype_code: int) -> int:
         return int(self._lib.atlas_flux_workspace_bytes(self._h, int(op), int(nlev),
                                                         int(dtype_code)))

@@ -155,6 +155,8 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_float)]),
     "atlas_flux_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int,
                                                      ctypes.c_int32, ctypes.c_int]),
+    "atlas_nabla_get_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32,
+                                             ctypes.c_int, ctypes.POINTER(Launch)]),
     "atlas_diag_volume_integral": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                   ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
                                                   ctypes.c_void_p]),

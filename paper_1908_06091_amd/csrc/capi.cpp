@@ -311,6 +311,33 @@ atlas_status atlas_nabla_laplacian(atlas_mesh_t mesh, const void *f, int32_t nle
   return apply(mesh, ATLAS_OP_LAPLACIAN, f, nlev, dtype, out, workspace, nullptr, stream);
 }
 
+atlas_status atlas_nabla_get_shape(atlas_mesh_t mesh, atlas_op op, int32_t nlev,
+                                   atlas_dtype dtype, atlas_launch *out) {
+  if (!mesh || !mesh->store || !out) return fail(ATLAS_EINVAL, "NULL argument");
+  if (op < ATLAS_OP_GRADIENT || op > ATLAS_OP_LAPLACIAN) return fail(ATLAS_EINVAL, "unknown operator");
+  if (dtype != ATLAS_F32 && dtype != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
+  if (nlev < 1) return fail(ATLAS_EINVAL, "nlev must be >= 1");
+  const MeshStore &m = *mesh->store;
+  LaunchShape s = shape_from(nullptr, m, op, nlev, dtype);
+  if (op == ATLAS_OP_LAPLACIAN) {
+    if (lapl_fused_runs(m, nlev, dtype, s)) {
+      s.variant = ATLAS_VARIANT_FUSED;
+    } else {
+      // two passes: report the gradient pass (the divergence pass is what
+      // ATLAS_OP_DIVERGENCE reports)
+      if (s.variant == ATLAS_VARIANT_FUSED || s.per_pass)
+        s = shape_from(nullptr, m, ATLAS_OP_GRADIENT, nlev, dtype);
+    }
+  }
+  out->variant = s.variant;
+  out->block_threads = s.block;
+  out->nodes_per_block = s.nodes_per_block;
+  out->level_chunk = s.level_chunk;
+  out->blocks_per_cu = s.blocks_per_cu;
+  out->level_vec = s.level_vec;
+  return ATLAS_OK;
+}
+
 size_t atlas_laplacian_workspace_bytes(atlas_mesh_t mesh, int32_t nlev, atlas_dtype dtype) {
   if (!mesh || !mesh->store || nlev < 1) return 0;
   return lapl_ws_bytes(*mesh->store, nlev, dtype);

@@ -122,3 +122,84 @@ def test_batch_validation(P, meshes):
         P.Batch([(gm, 9, x32, torch.empty(gm.nnodes, 3, device="cuda"))])
     with pytest.raises(P.AtlasError):  # input and output overlap
         P.Batch([(gm, P.ATLAS_OP_LAPLACIAN, x32, x32)])
+
+
+def _mixed_grid_items(P, meshes, n, seed):
+    """n seeded FP32 items over O80/O160/O320 with nlev from {1, 10, 91,
+    137} and operators from {grad, div, lapl}: each level a harmonic field
+    of degree <= 16 (four per grid, cycled over the levels, times
+    (1 + k/137)); divergence inputs are gradients of such fields."""
+    import synthetic as sy
+    rng = np.random.default_rng(seed)
+    fields, items = {}, []
+    for _ in range(n):
+        N = int(rng.choice([80, 160, 320]))
+        nlev = int(rng.choice([1, 10, 91, 137]))
+        op = ("grad", "div", "lapl")[int(rng.integers(0, 3))]
+        gm = meshes[N]
+        if N not in fields:
+            d = P.mesh_desc_octahedral(N)
+            co = sy.random_coeffs(16, [sy.seed_rng(4, N, j) for j in range(4)])
+            fields[N] = (torch.from_numpy(sy.synthesize(d["lon"], d["lat"], co)).cuda(),
+                         torch.from_numpy(sy.synthesize_gradient(d["lon"], d["lat"], co)).cuda())
+        H, G = fields[N]
+        k = torch.arange(nlev, device="cuda", dtype=torch.float64)
+        fac = 1.0 + k / 137.0
+        if op == "div":
+            x = (G[k.long() % 4].permute(1, 0, 2) * fac[None, :, None]).float().contiguous()
+            out = torch.full((gm.nnodes, nlev), float("nan"), device="cuda")
+        else:
+            x = (H[k.long() % 4].t() * fac[None, :]).float().contiguous()
+            shape = (gm.nnodes, nlev, 2) if op == "grad" else (gm.nnodes, nlev)
+            out = torch.full(shape, float("nan"), device="cuda")
+        items.append((gm, _op_code(P, op), x, out, N, op))
+    return items
+
+
+def test_mixed_grid_batch_forms_match_oracle(P):
+    """The 64-item FP32 batch over O80/O160/O320 and 1-137 levels in three
+    forms -- large items as their own launches beside the persistent kernel
+    (the default), every item inside the persistent kernel, and autotuned
+    tile shapes -- gives the same bits in each form and for each item alone,
+    and every item matches the FP64 oracle on its own (FP32) inputs at
+    sampled nodes within 1e-5 of the output scale."""
+    import oracle
+    from gpu_util import TOL, normwise_error, oracle_apply_at
+    meshes = {N: P.Mesh(N) for N in (80, 160, 320)}
+    items = _mixed_grid_items(P, meshes, 64, seed=64)
+    kinds = [("hybrid", dict()), ("persistent", dict(solo_min_elems=-1)),
+             ("autotuned", dict(autotune=True))]
+    results = {}
+    for name, kw in kinds:
+        print(f"mixed-grid batch form {name}", flush=True)
+        for it in items:
+            it[3].fill_(float("nan"))
+        b = P.Batch([it[:4] for it in items], use_graph=True, **kw)
+        if name == "persistent":
+            assert b.info.solo_items == 0
+        b.launch()
+        b.check()
+        torch.cuda.synchronize()
+        results[name] = [it[3].clone() for it in items]
+        b.close()
+    for name in ("persistent", "autotuned"):
+        for a, c in zip(results["hybrid"], results[name]):
+            assert torch.equal(a, c), name
+    oms = {N: oracle.Mesh(N) for N in meshes}
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for (gm, code, x, out, N, op), got_all in zip(items, results["hybrid"]):
+        solo = gm.apply(code, x)
+        torch.cuda.synchronize()
+        assert torch.equal(solo, got_all), (N, op, x.shape)
+        om = oms[N]
+        nodes = np.sort(rng.choice(om.V, size=256, replace=False)).astype(np.int64)
+        nodes[:8] = np.arange(8)  # a polar cap
+        nodes = np.unique(nodes)
+        nlev = x.shape[1]
+        ref = oracle_apply_at(om, op, x.double().cpu().numpy(), nlev, nodes)
+        got = got_all.double().cpu().numpy()[nodes]
+        emax, _ = normwise_error(got, ref)
+        worst = max(worst, emax)
+        assert emax <= TOL["f32"], (N, op, nlev, emax)
+    print(f"mixed-grid batch: worst max_rel vs oracle {worst:.3e}", flush=True)

@@ -12,14 +12,11 @@ torch = pytest.importorskip("torch")
 N, NLEV = 1280, 137
 
 
-@pytest.fixture(scope="module")
-def big():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+def _build(N, nrandom):
     import oracle
     import paper_1908_06091_amd as P
     import synthetic as sy
-    print("fullsize: building O1280 meshes", flush=True)
+    print(f"fullsize: building O{N} meshes", flush=True)
     om = oracle.Mesh(N)
     gm = P.Mesh(N)
     dev = torch.device("cuda")
@@ -38,14 +35,14 @@ def big():
     uvr = (Gr[idx].permute(1, 0, 2) * fac[None, :, None]).contiguous()
     del H, G, Gr
     g = torch.Generator(device=dev)
-    g.manual_seed(1280)
+    g.manual_seed(N)
     for t in (f, uv, uvr):
         t += 1e-2 * (2.0 * torch.rand(t.shape, dtype=torch.float64, device=dev, generator=g) - 1.0)
     torch.cuda.synchronize()
     f_h, uv_h, uvr_h = f.cpu().numpy(), uv.cpu().numpy(), uvr.cpu().numpy()
     # sampled nodes: random, polar caps, ring starts/ends, seams
     rng = np.random.default_rng(137)
-    pick = set(rng.choice(om.V, size=3000, replace=False).tolist())
+    pick = set(rng.choice(om.V, size=nrandom, replace=False).tolist())
     pick.update(range(0, 64))
     pick.update(range(om.V - 64, om.V))
     ro, nx = np.asarray(om.ring_off), np.asarray(om.nx)
@@ -54,10 +51,16 @@ def big():
             pick.add(int(ro[j] + q * nx[j] // 4))
         pick.add(int(ro[j] + nx[j] - 1))
     nodes = np.array(sorted(pick), dtype=np.int64)
-    print(f"fullsize: {len(nodes)} sampled nodes", flush=True)
-    return dict(P=P, om=om, gm=gm, f=f, uv=uv, uvr=uvr, f_h=f_h, uv_h=uv_h, uvr_h=uvr_h,
-                nodes=nodes,
-                nodes_d=torch.from_numpy(nodes).to(dev), refs={})
+    print(f"fullsize: O{N}, {len(nodes)} sampled nodes", flush=True)
+    return dict(N=N, P=P, om=om, gm=gm, f=f, uv=uv, uvr=uvr, f_h=f_h, uv_h=uv_h, uvr_h=uvr_h,
+                nodes=nodes, nodes_d=torch.from_numpy(nodes).to(dev), refs={})
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return _build(N, 3000)
 
 
 def _ref(big, op, dtype="f64"):
@@ -100,6 +103,8 @@ def test_o1280_l137_sampled(big, op, dtype):
     print(msg, flush=True)
     assert np.isfinite(got).all()
     assert emax <= TOL[dtype], (op, dtype, emax)
+    if dtype == "f64" and op != "lapl":
+        _assert_local(big, op, got, _ref(big, op, dtype), NLEV)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -168,28 +173,105 @@ def test_o1280_longest_columns_allowed(big, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nlev", [1, 17])
+@pytest.mark.parametrize("nlev", [1, 17, 24, 37, 48, 64, 72, 79, 80, 91])
 def test_o1280_short_columns_sampled(big, nlev, dtype):
-    """O1280 with one level and with 17 levels (one GPU's slab when 137
-    levels are split over eight GPUs), in the default shapes of those sizes,
-    against the oracle at the sampled nodes (the first nlev levels of the
-    benchmark fields)."""
+    """O1280 with the first nlev levels of the benchmark fields, in the
+    default shapes of those sizes, against the oracle at the sampled nodes.
+    The sizes cover every built-in shape switch: the flat form (1, 17: one
+    GPU's slab when 137 levels are split over eight GPUs), the column forms
+    from 24 levels, the FP32 gradient's sweep (24-79 levels, lane vectors of
+    1 or 2 levels), the level-vector forms from 48 levels and one level per
+    lane for the FP32 gradient from 80.  The oracle treats every level on
+    its own, so its values for the first nlev levels are the first nlev
+    levels of its 137-level values."""
+    _sampled(big, nlev, dtype)
+
+
+def _sampled(big, nlev, dtype):
     from gpu_util import TOL, normwise_error
-    P, gm, om, nodes = big["P"], big["gm"], big["om"], big["nodes"]
+    gm = big["gm"]
     dt = torch.float64 if dtype == "f64" else torch.float32
-    print(f"fullsize short columns nlev={nlev} {dtype}", flush=True)
+    print(f"fullsize O{big['N']} nlev={nlev} {dtype}", flush=True)
     for op, name in (("grad", "f"), ("div", "uv"), ("curl", "uvr"), ("lapl", "f")):
         x = big[name][:, :nlev].contiguous().to(dt)
         fn = {"grad": gm.gradient, "div": gm.divergence, "curl": gm.curl,
               "lapl": gm.laplacian}[op]
         got = fn(x).index_select(0, big["nodes_d"]).double().cpu().numpy()
-        xh = x.double().cpu().numpy()
-        ofn = {"grad": om.gradient_at, "div": om.divergence_at, "curl": om.curl_at,
-               "lapl": om.laplacian_at}[op]
-        ref = ofn(xh, nlev, nodes)
-        del x, xh
+        del x
+        ref = _ref(big, op, dtype)[:, :nlev]
         emax, erms = normwise_error(got, ref)
-        print(f"O1280 L{nlev} {op} {dtype}: max_rel={emax:.3e} rms_rel={erms:.3e}", flush=True)
+        print(f"O{big['N']} L{nlev} {op} {dtype}: max_rel={emax:.3e} rms_rel={erms:.3e}",
+              flush=True)
         assert np.isfinite(got).all()
         assert emax <= TOL[dtype], (op, nlev, dtype, emax)
+        if dtype == "f64" and op != "lapl":
+            _assert_local(big, op, got, ref, nlev)
     torch.cuda.empty_cache()
+
+
+def _assert_local(big, op, got, ref, nlev):
+    """FP64 error node by node: each sampled node's error stays within a
+    bound set by the size of that node's own terms (sum over its edges of
+    |S| times the edge values, times its scale), so a wrong term at a node
+    whose result is small cannot hide under the normwise bar."""
+    bound = _local_scale(big, op, nlev)
+    d = np.abs(got - ref)
+    if d.ndim == 3:
+        d = d.max(axis=2)
+    worst = float((d / bound).max())
+    assert worst <= 64 * 2.0 ** -52, (op, nlev, worst)
+
+
+def _local_scale(big, op, nlev):
+    """alpha_i (R / V_i, the larger of the node's two scales) times the sum
+    over its edges of (|S_lon| + |S_lat|) (|x_a| + |x_b|), plus the polar
+    face's |S| (|x_i| + |x_partner|) at polar nodes: the size of the terms
+    the node sums, level by level (|x| the larger component of a vector)."""
+    key = ("local", op)
+    if key not in big["refs"]:
+        P, nodes = big["P"], big["nodes"]
+        d = big.get("desc")
+        if d is None:
+            d = big["desc"] = P.mesh_desc_octahedral(big["N"])
+        ptr, inc, e2n = d["node2edge_ptr"], d["node2edge"], d["edge2node"]
+        S = np.abs(d["dual_normals"]).sum(axis=1)
+        name = {"grad": "f", "div": "uv", "curl": "uvr"}[op]
+        x = big[name + "_h"]
+        partner = {}
+        for (a, b), sn in zip(d["pole_edges"], d["pole_normals"]):
+            partner[int(a)] = (int(b), abs(sn))
+            partner[int(b)] = (int(a), abs(sn))
+        out = np.empty((len(nodes), NLEV))
+        for q, i in enumerate(nodes):
+            es = inc[ptr[i]:ptr[i + 1]]
+            a, b = e2n[es, 0], e2n[es, 1]
+            xa, xb = np.abs(x[a]), np.abs(x[b])
+            if xa.ndim == 3:
+                xa, xb = xa.max(axis=2), xb.max(axis=2)
+            t = (S[es][:, None] * (xa + xb)).sum(axis=0)
+            if int(i) in partner:
+                p_, sn = partner[int(i)]
+                xi, xp = np.abs(x[i]), np.abs(x[p_])
+                if xi.ndim == 2:
+                    xi, xp = xi.max(axis=1), xp.max(axis=1)
+                t = t + sn * (xi + xp)
+            out[q] = t / d["dual_volumes"][i] * d["radius"]
+        big["refs"][key] = out
+    return big["refs"][key][:, :nlev]
+
+
+@pytest.fixture(scope="module")
+def mid():
+    """O640 (1,661,440 nodes, 4,984,280 edges)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return _build(640, 2000)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nlev", [1, 37, 64, 137])
+def test_o640_sampled(mid, nlev, dtype):
+    """O640, the serving mix's second largest grid, at its level counts (1,
+    37, 137) and at 64 levels, default shapes, against the oracle at the
+    sampled nodes."""
+    _sampled(mid, nlev, dtype)

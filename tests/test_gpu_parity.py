@@ -77,7 +77,7 @@ def test_parity_small_meshes(P, N, nlev, op, dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("op", OPS)
-@pytest.mark.parametrize("nlev", [1, 7, 137])
+@pytest.mark.parametrize("nlev", [1, 7, 72, 137])
 def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
     print(f"shapes nlev={nlev} op={op} dtype={dtype}", flush=True)
     N = 16
@@ -96,6 +96,7 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
     for block in (64, 256, 512, 1024):
         for kc in (0, 1, 5, 32):
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))      # lane vectors
+            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 2))
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 3))
             if block <= 512:
                 shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 1))  # one level per lane
