@@ -32,6 +32,29 @@ atlas_status atlas_diag_volume_integral(atlas_mesh_t mesh, const void *field, in
                                         int32_t ncomp, atlas_dtype dtype, double *out,
                                         hipStream_t stream);
 
+/* The most columns (nlev * ncomp) the variant below takes. */
+#define ATLAS_DIAG_NOALLOC_MAX_COLS 512
+
+/* The volume integral above for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, kernels and result bits, but the partials live
+ * in one static device array of 1024 * ATLAS_DIAG_NOALLOC_MAX_COLS doubles
+ * (4 MiB) that the library holds on every GPU it runs on until the process
+ * ends.  No hipMalloc, hipFree or allocating library call is made.  The first
+ * call on a device looks up that device's copy of the array (the device that
+ * is current, which must be the mesh's).
+ * Calls on one GPU share its array: calls that overlap on that GPU (on
+ * different streams, or from different threads without ordering) race and
+ * may return wrong sums.  Calls ordered on one stream are safe.  Every
+ * partial is written before it is read, so nothing carries over between
+ * calls.
+ * Errors: those of atlas_diag_volume_integral, plus ATLAS_EINVAL when
+ * nlev * ncomp exceeds ATLAS_DIAG_NOALLOC_MAX_COLS or the current device is
+ * not the mesh's, ATLAS_EDEVICE when the array's address cannot be found. */
+atlas_status atlas_diag_volume_integral_noalloc(atlas_mesh_t mesh, const void *field,
+                                                int32_t nlev, int32_t ncomp, atlas_dtype dtype,
+                                                double *out, hipStream_t stream);
+
 /* Error norms of `got` against `ref`, n rows of ncomp interleaved
  * components (both device arrays, each of its own dtype).  out (device,
  * 4 * ncomp doubles): for component c,

@@ -160,6 +160,10 @@ SIGNATURES = {
     "atlas_diag_volume_integral": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                   ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
                                                   ctypes.c_void_p]),
+    "atlas_diag_volume_integral_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                          ctypes.c_int32, ctypes.c_int32,
+                                                          ctypes.c_int, ctypes.c_void_p,
+                                                          ctypes.c_void_p]),
     "atlas_diag_error_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                               ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
                                               ctypes.c_void_p, ctypes.c_void_p]),

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "atlas_diag.h"
 #include "internal.h"
@@ -18,6 +19,30 @@ namespace {
 
 constexpr int kParts = 1024;  // row partition of both reductions
 constexpr int kBlock = 256;
+
+// Partials of the volume integral that allocates nothing: one static array
+// per GPU, held until the process ends (4 MiB).  Host code never names it
+// in a launch: its device address is looked up once per device below.
+static __device__ __align__(256) double scratch[kParts * ATLAS_DIAG_NOALLOC_MAX_COLS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current).
+atlas_status scratch_on_current_device(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ATLAS_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return ATLAS_OK;
+}
 
 // max that keeps a NaN (fmax would drop it)
 __device__ __forceinline__ double nanmax(double a, double b) {
@@ -115,6 +140,35 @@ atlas_status launch_norms(const void *got, const void *ref, int64_t n, int ncomp
   return ATLAS_OK;
 }
 
+atlas_status check_volume_args(atlas_mesh_t mesh, const void *field, int32_t nlev,
+                               int32_t ncomp, atlas_dtype dtype, const double *out) {
+  if (!mesh || !mesh->store || !field || !out) return fail(ATLAS_EINVAL, "NULL argument");
+  if (nlev < 1) return fail(ATLAS_EINVAL, "nlev must be >= 1");
+  if (ncomp != 1 && ncomp != 2) return fail(ATLAS_EINVAL, "ncomp must be 1 or 2");
+  if (dtype != ATLAS_F32 && dtype != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
+  const size_t w = dtype == ATLAS_F64 ? 8 : 4;
+  if ((uintptr_t)field % w || (uintptr_t)out % 8)
+    return fail(ATLAS_EINVAL, "pointer not aligned to its element size");
+  if ((int64_t)mesh->store->d.V * nlev * ncomp >= ((int64_t)1 << 40))
+    return fail(ATLAS_EINVAL, "field too large");
+  return ATLAS_OK;
+}
+
+// Partials into part[kParts][cols], then their sum in part order into out.
+hipError_t launch_volume(const DevMesh &m, const void *field, int cols, atlas_dtype dtype,
+                         double *part, double *out, hipStream_t stream) {
+  const dim3 grid(kParts, (cols + kBlock - 1) / kBlock);
+  if (dtype == ATLAS_F64)
+    hipLaunchKernelGGL(k_vol_partial<double>, grid, dim3(kBlock), 0, stream, m.perm, m.vol,
+                       static_cast<const double *>(field), m.V, cols, part);
+  else
+    hipLaunchKernelGGL(k_vol_partial<float>, grid, dim3(kBlock), 0, stream, m.perm, m.vol,
+                       static_cast<const float *>(field), m.V, cols, part);
+  hipLaunchKernelGGL(k_parts_sum, dim3((cols + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                     (const double *)part, cols, out);
+  return hipGetLastError();
+}
+
 }  // namespace
 }  // namespace atlasx
 
@@ -125,30 +179,37 @@ extern "C" {
 atlas_status atlas_diag_volume_integral(atlas_mesh_t mesh, const void *field, int32_t nlev,
                                         int32_t ncomp, atlas_dtype dtype, double *out,
                                         hipStream_t stream) {
-  if (!mesh || !mesh->store || !field || !out) return fail(ATLAS_EINVAL, "NULL argument");
-  if (nlev < 1) return fail(ATLAS_EINVAL, "nlev must be >= 1");
-  if (ncomp != 1 && ncomp != 2) return fail(ATLAS_EINVAL, "ncomp must be 1 or 2");
-  if (dtype != ATLAS_F32 && dtype != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
-  const size_t w = dtype == ATLAS_F64 ? 8 : 4;
-  if ((uintptr_t)field % w || (uintptr_t)out % 8)
-    return fail(ATLAS_EINVAL, "pointer not aligned to its element size");
-  const DevMesh &m = mesh->store->d;
+  const atlas_status c = check_volume_args(mesh, field, nlev, ncomp, dtype, out);
+  if (c != ATLAS_OK) return c;
   const int cols = nlev * ncomp;
-  if ((int64_t)m.V * cols >= ((int64_t)1 << 40)) return fail(ATLAS_EINVAL, "field too large");
   double *part = nullptr;
   if (hipMallocAsync((void **)&part, sizeof(double) * kParts * (size_t)cols, stream) != hipSuccess)
     return fail(ATLAS_ENOMEM, "diagnostics temporary");
-  const dim3 grid(kParts, (cols + kBlock - 1) / kBlock);
-  if (dtype == ATLAS_F64)
-    hipLaunchKernelGGL(k_vol_partial<double>, grid, dim3(kBlock), 0, stream, m.perm, m.vol,
-                       static_cast<const double *>(field), m.V, cols, part);
-  else
-    hipLaunchKernelGGL(k_vol_partial<float>, grid, dim3(kBlock), 0, stream, m.perm, m.vol,
-                       static_cast<const float *>(field), m.V, cols, part);
-  hipLaunchKernelGGL(k_parts_sum, dim3((cols + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
-                     (const double *)part, cols, out);
-  const hipError_t e = hipGetLastError();
+  const hipError_t e = launch_volume(mesh->store->d, field, cols, dtype, part, out, stream);
   (void)hipFreeAsync(part, stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+  return ATLAS_OK;
+}
+
+atlas_status atlas_diag_volume_integral_noalloc(atlas_mesh_t mesh, const void *field,
+                                                int32_t nlev, int32_t ncomp, atlas_dtype dtype,
+                                                double *out, hipStream_t stream) {
+  const atlas_status c = check_volume_args(mesh, field, nlev, ncomp, dtype, out);
+  if (c != ATLAS_OK) return c;
+  const int64_t cols = (int64_t)nlev * ncomp;
+  if (cols > ATLAS_DIAG_NOALLOC_MAX_COLS)
+    return fail(ATLAS_EINVAL, "nlev * ncomp = " + std::to_string(cols) +
+                                  " exceeds the static workspace's " +
+                                  std::to_string(ATLAS_DIAG_NOALLOC_MAX_COLS) + " columns");
+  int dev = -1;
+  ATLASX_HIP(hipGetDevice(&dev));
+  if (dev != mesh->store->device) return fail(ATLAS_EINVAL, "mesh lives on another device");
+  double *part = nullptr;
+  const atlas_status sp = scratch_on_current_device(dev, &part);
+  if (sp != ATLAS_OK) return sp;
+  // every partial the sum reads is written by the partial kernel first:
+  // nothing to clear
+  const hipError_t e = launch_volume(mesh->store->d, field, (int)cols, dtype, part, out, stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
   return ATLAS_OK;
 }
