@@ -49,6 +49,9 @@ def parse_args():
     ap.add_argument("--cpu-levels", type=int, default=137,
                     help="levels of the workload the CPU oracle sample covers")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-remap", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the GPU and oracle timings of the O16 L1 and O320 L137 configs")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -456,6 +459,124 @@ def serve_bench(P, torch, np, dev, gm1280, nreq, qps_factors):
     }
 
 
+def remap_bench(P, torch, dev, gm, f64, steps):
+    """Remap (P1 interpolation) of a 137-level field between O1280 and O640
+    node sets, FP64 and FP32, apply kernel only (weights built once).  Bytes:
+    touched source rows read once, target rows written once, plus 36 B of
+    weights per target."""
+    nlev = f64.shape[1]
+    g640 = P.Mesh(640)
+    x640 = torch.randn(g640.nnodes, nlev, dtype=torch.float64, device=dev)
+    rows = {}
+    for name, src, dst, x in (("O1280_to_O640", gm, g640, f64), ("O640_to_O1280", g640, gm, x640)):
+        r = P.Remap(src, dst)
+        info = r.info
+        for dname, dt, w in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            xi = x.to(dt)
+            o = torch.empty(r.ntarget, nlev, dtype=dt, device=dev)
+            st = {}
+            t = time_op(lambda: r.apply(xi, out=o), max(10, steps // 2), 3, torch, st)
+            b = info.values_per_column * nlev * w + info.table_bytes
+            rows[f"{name}_{dname}"] = {
+                "ms": round(t, 4), **st, "targets": r.ntarget,
+                "sources_touched": int(info.nsource_touched),
+                "target_values_per_s": r.ntarget * nlev / (t * 1e-3),
+                "GBps": round(b / (t * 1e-3) / 1e9, 1),
+                "hbm_frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_model": "(touched + targets) * L * w + 36 * targets"}
+            del xi, o
+        r.close()
+        torch.cuda.empty_cache()
+    del x640
+    g640.close()
+    torch.cuda.empty_cache()
+    return rows
+
+
+def config_bench(P, torch, np, dev, steps):
+    """The O16 L1 FP64 gradient and the O320 L137 FP64 gradient, divergence
+    and Laplacian: GPU time per call (median of >= 20, min, max) next to the
+    FP64 oracle on all host threads and, for O320, on one thread (median of
+    3 runs, one run if a run takes over 30 s)."""
+    import oracle
+    import synthetic as sy
+    rows = {}
+    for cfg, N, nlev, lmax, ops in ((1, 16, 1, 4, ("grad",)),
+                                    (2, 320, 137, 32, ("grad", "div", "lapl"))):
+        om, gm = oracle.Mesh(N), P.Mesh(N)
+        if cfg == 1:
+            f = sy.level_field_stack(om.lon, om.lat, 1, lmax, 1, 0, noise_eps=1e-3)
+            co2 = sy.random_coeffs(lmax, [sy.seed_rng(1, 1, 0)])
+        else:  # eight seeded degree-32 fields cycled over the levels, scaled
+            co = sy.random_coeffs(lmax, [sy.seed_rng(2, 0, j) for j in range(8)])
+            H = sy.synthesize(om.lon, om.lat, co)
+            f = np.stack([H[k % 8] * (k + 1) for k in range(nlev)], axis=1)
+            co2 = sy.random_coeffs(lmax, [sy.seed_rng(2, 1, j) for j in range(8)])
+        G = sy.synthesize_gradient(om.lon, om.lat, co2)
+        uv = np.stack([G[k % G.shape[0]] for k in range(nlev)], axis=1)
+        f = np.ascontiguousarray(f)
+        uv = np.ascontiguousarray(uv)
+        xf, xuv = torch.from_numpy(f).to(dev), torch.from_numpy(uv).to(dev)
+        for op in ops:
+            x = xuv if op == "div" else xf
+            shape = (gm.nnodes, nlev, 2) if op == "grad" else (gm.nnodes, nlev)
+            o = torch.empty(shape, dtype=torch.float64, device=dev)
+            fn = {"grad": lambda: gm.gradient(x, out=o), "div": lambda: gm.divergence(x, out=o),
+                  "lapl": lambda: gm.laplacian(x, out=o)}[op]
+            st = {}
+            t = time_op(fn, max(20, steps), 3, torch, st)
+            ofn = {"grad": om.gradient, "div": om.divergence, "lapl": om.laplacian}[op]
+            xh = uv if op == "div" else f
+
+            def cpu_time(threads):
+                old = oracle.set_threads(threads)
+                try:
+                    times = []
+                    for _ in range(3):
+                        t0 = time.perf_counter()
+                        ofn(xh, nlev)
+                        times.append(time.perf_counter() - t0)
+                        if times[-1] > 30.0:
+                            break
+                finally:
+                    oracle.set_threads(old)
+                return float(np.median(times)), len(times)
+
+            t_all, n_all = cpu_time(os.cpu_count() or 1)
+            row = {"gpu_ms": round(t, 4), **{"gpu_" + k: v for k, v in st.items()},
+                   "gpu_edge_level_per_s": gm.nedges * nlev / (t * 1e-3),
+                   "oracle_ms": round(t_all * 1e3, 3), "oracle_runs": n_all,
+                   "oracle_threads": oracle.threads_used(nlev),
+                   "oracle_edge_level_per_s": om.E * nlev / t_all}
+            if cfg == 2:
+                t1, n1 = cpu_time(1)
+                row.update({"oracle_1thread_ms": round(t1 * 1e3, 3), "oracle_1thread_runs": n1,
+                            "oracle_1thread_edge_level_per_s": om.E * nlev / t1})
+            rows[f"cfg{cfg}_O{N}_L{nlev}_{op}_f64"] = row
+            del o
+        del xf, xuv
+        gm.close()
+        torch.cuda.empty_cache()
+    return rows
+
+
+def cpu_ops_o1280(om, f_host, uv_host, nlev):
+    """The oracle's divergence and Laplacian at O1280 on all host threads,
+    one run each (the gradient is the cpu_baseline figure)."""
+    import numpy as np
+    import oracle
+    rows = {}
+    for op, fn, x in (("div", om.divergence, uv_host), ("lapl", om.laplacian, f_host)):
+        t0 = time.perf_counter()
+        fn(x, nlev)
+        dt = time.perf_counter() - t0
+        rows[f"O1280_L{nlev}_{op}_f64"] = {"oracle_ms": round(dt * 1e3, 1), "runs": 1,
+                                           "threads": oracle.threads_used(nlev),
+                                           "edge_level_per_s": om.E * nlev / dt}
+    del np
+    return rows
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -581,6 +702,15 @@ def main():
         del xs, os_
         torch.cuda.empty_cache()
 
+    remap = None
+    if not args.no_remap:
+        remap = remap_bench(P, torch, dev, gm, f64, args.steps)
+        print("# remap done", file=sys.stderr, flush=True)
+    configs = None
+    if not args.no_configs:
+        configs = config_bench(P, torch, np, dev, args.steps)
+        print("# configs done", file=sys.stderr, flush=True)
+
     sha = kernel_source_sha()
     rec = counters_for(sha)
     traffic = None
@@ -593,6 +723,11 @@ def main():
         f_host = f64[:, :args.cpu_levels].cpu().numpy()
         cpu, om = cpu_baseline(N, nlev, args.cpu_levels, np.ascontiguousarray(f_host))
         print(f"# cpu baseline done: {cpu['sample']}", file=sys.stderr, flush=True)
+        if not args.no_configs and args.cpu_levels == nlev:
+            cpu["other_ops"] = cpu_ops_o1280(om, np.ascontiguousarray(f_host),
+                                             np.ascontiguousarray(uv64.cpu().numpy()), nlev)
+            print("# cpu div/lapl done", file=sys.stderr, flush=True)
+        del f_host
     acc = None
     if not args.no_accuracy:
         if om is None:
@@ -640,6 +775,8 @@ def main():
         "ops": ops,
         "other_grids": grids,
         "level_slab_share": slab,
+        "remap": remap,
+        "configs": configs,
         "accuracy_vs_oracle": acc,
         "batch": batch,
         "serving": serving,

@@ -3,7 +3,9 @@
  *
  * Meshes stay resident on the device (Section 5: data structures live on
  * the accelerator and are copied once); requests (mesh, operator, dtype,
- * levels, field) arrive at any time.  A scheduler thread admits requests in
+ * levels, field) arrive at any time.  Besides the four operators a request
+ * can remap a field from one grid to another (atlas_remap.h) with weights
+ * registered once.  A scheduler thread admits requests in
  * arrival order while their device footprint fits an HBM budget, and each
  * time one of its launch slots (HIP streams) frees up it launches the
  * admitted requests: small ones merged into one persistent batch launch
@@ -32,6 +34,11 @@
 #define ATLAS_SERVE_H
 
 #include "atlas_nabla.h"
+#include "atlas_remap.h"
+
+/* Request operator value of a remap (the atlas_op values name the four
+ * nabla operators). */
+#define ATLAS_SERVE_OP_REMAP 4
 
 #ifdef __cplusplus
 extern "C" {
@@ -57,8 +64,11 @@ typedef struct {
 } atlas_serve_config;
 
 typedef struct {
-  int32_t mesh_id;  /* from atlas_serve_register_mesh                     */
-  int32_t op;       /* atlas_op                                           */
+  int32_t mesh_id;  /* from atlas_serve_register_mesh; for a remap, the id
+                       from atlas_serve_register_remap                    */
+  int32_t op;       /* atlas_op, or ATLAS_SERVE_OP_REMAP: input
+                       [nsource][nlev], output [ntarget][nlev] (nlev: the
+                       columns per node, 2 x levels for a vector field)   */
   int32_t dtype;    /* atlas_dtype                                        */
   int32_t nlev;
   const void *in;   /* device input, caller-owned, valid until done      */
@@ -98,7 +108,20 @@ atlas_status atlas_serve_register_mesh(atlas_server_t srv, atlas_mesh_t mesh,
 atlas_status atlas_serve_register_sim_mesh(atlas_server_t srv, int64_t nnodes,
                                            int32_t *mesh_id);
 
-/* Non-blocking.  Errors: ATLAS_EINVAL (unknown mesh, bad op/dtype/nlev,
+/* Make a remap's weights known to the server; remap requests then name
+ * the returned id.  The remap cannot be freed (ATLAS_EBUSY) until
+ * atlas_serve_destroy.  Remaps always launch alone (no batching).
+ * Errors: ATLAS_EINVAL (NULL argument, a simulation server, the remap on
+ * another device). */
+atlas_status atlas_serve_register_remap(atlas_server_t srv, atlas_remap_t remap,
+                                        int32_t *remap_id);
+
+/* Simulation servers only: a remap from `nsource` to `ntarget` nodes that
+ * exists on paper. */
+atlas_status atlas_serve_register_sim_remap(atlas_server_t srv, int64_t nsource,
+                                            int64_t ntarget, int32_t *remap_id);
+
+/* Non-blocking.  Errors: ATLAS_EINVAL (unknown mesh or remap, bad op/dtype/nlev,
  * NULL input), ATLAS_ENOMEM (footprint above the whole budget),
  * ATLAS_ESTATE (server shutting down). */
 atlas_status atlas_serve_submit(atlas_server_t srv, const atlas_request *req,

@@ -64,6 +64,7 @@ def _load():
                                       _c_dp, _c_i32p, _c_i32p, _c_dp, _c_dp,
                                       _c_dp, _c_i32p, _c_dp]
         lib.orc_threads_used.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         for name in ("orc_gradient", "orc_divergence", "orc_curl", "orc_laplacian"):
             getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_int, _c_dp, _c_dp]
         for name in ("orc_gradient_at", "orc_divergence_at", "orc_curl_at",
@@ -93,6 +94,12 @@ def gauss_mu(N: int) -> np.ndarray:
 def threads_used(nlev: int) -> int:
     """Number of OpenMP threads the dense operators use for ``nlev`` levels."""
     return int(_load().orc_threads_used(int(nlev)))
+
+
+def set_threads(n: int) -> int:
+    """Threads the oracle's later calls may use (timing only: results do not
+    depend on it); returns the previous maximum."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def regular_gaussian_nx(N: int) -> np.ndarray:

@@ -447,6 +447,19 @@ static int n_chunks(int nlev) {
 
 int orc_threads_used(int nlev) { return n_chunks(nlev); }
 
+/* Threads later calls may use (results do not depend on it); returns the
+ * previous maximum.  Timing aid only. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  const int old = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return old;
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gradient.  For every edge e = (a, b) and level k the edge value is        */
 /* phi_e = (phi_a + phi_b)/2; the flux S_e phi_e is added to a and taken     */

@@ -321,6 +321,75 @@ class Mesh:
                                                         int(dtype_code)))
 
 
+class Remap:
+    """Interpolation of nodal fields from `source` (a Mesh) to other points
+    (``atlas_remap.h``): the nodes of another Mesh (`target`) or the points
+    (lon, lat) in radians.  P1 interpolation on the source triangles;
+    targets poleward of the polar parallels interpolate along them."""
+
+    def __init__(self, source: Mesh, target: Mesh | None = None, *, lon=None, lat=None):
+        import numpy as _np
+        L = lib()
+        self._lib = L
+        self._h = ctypes.c_void_p()
+        if target is not None:
+            _check(L.atlas_remap_create_to_mesh(source.handle, target.handle,
+                                                ctypes.byref(self._h)))
+        else:
+            lo = _np.ascontiguousarray(lon, dtype=_np.float64).ravel()
+            la = _np.ascontiguousarray(lat, dtype=_np.float64).ravel()
+            if lo.size != la.size:
+                raise ValueError("lon and lat must have the same size")
+            _check(L.atlas_remap_create(source.handle, lo.size,
+                                        lo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        la.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        ctypes.byref(self._h)))
+        info = _abi.RemapInfo()
+        _check(L.atlas_remap_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+        self.nsource = int(info.nsource)
+        self.ntarget = int(info.ntarget)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def weights(self):
+        """(idx [nt][3] int32, w [nt][3] float64), copied to the host."""
+        import numpy as _np
+        idx = _np.empty((self.ntarget, 3), _np.int32)
+        w = _np.empty((self.ntarget, 3), _np.float64)
+        _check(self._lib.atlas_remap_get_weights(
+            self._h, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return idx, w
+
+    def apply(self, x, out=None, stream=None):
+        """x: device [nsource, ...] (any trailing shape: levels, components);
+        returns [ntarget, ...] of x's dtype."""
+        if x.shape[0] != self.nsource:
+            raise ValueError(f"field has {x.shape[0]} nodes, the source mesh has {self.nsource}")
+        ncol = math.prod(x.shape[1:]) if x.dim() > 1 else 1
+        shape = (self.ntarget,) + tuple(x.shape[1:])
+        if out is None:
+            out = _torch().empty(shape, dtype=x.dtype, device=x.device)
+        op_ = _out_ptr(out, x, self.ntarget * ncol, "out")
+        _check(self._lib.atlas_remap_apply(self._h, _dev_ptr(x, "x"), int(ncol), _dtype_code(x),
+                                           op_, _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(self._lib.atlas_remap_free(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autotune(mesh, op: int, x, out, workspace=None, stream=None):
     """Time the candidate launch shapes for (mesh, op, dtype, nlev) on these
     buffers; the mesh remembers the fastest.  Returns (Launch, ms)."""
@@ -428,6 +497,9 @@ def error_norms(got, ref, stream=None) -> dict:
             "rms_rel": max(c["rms_rel"] for c in comps)}
 
 
+ATLAS_SERVE_OP_REMAP = 4
+
+
 class Server:
     """Request server (atlas_serve.h): HBM-budget admission, resident meshes,
     continuous batching over `nstreams` HIP streams.  With simulate=True no
@@ -442,7 +514,9 @@ class Server:
         self._h = ctypes.c_void_p()
         self._keep = {}
         self._meshes = []
+        self._remaps = []
         self._nnodes = {}  # mesh id -> nodes, to check request buffers
+        self._remap_nodes = {}  # remap id -> (source nodes, target nodes)
         _check(self._lib.atlas_serve_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self.simulate = bool(simulate)
 
@@ -459,12 +533,39 @@ class Server:
         self._nnodes[mid.value] = int(nnodes)
         return mid.value
 
+    def register_remap(self, remap) -> int:
+        """A Remap whose weights remap requests (op ATLAS_SERVE_OP_REMAP) use."""
+        rid = ctypes.c_int32()
+        _check(self._lib.atlas_serve_register_remap(self._h, remap.handle, ctypes.byref(rid)))
+        self._remaps.append(remap)
+        self._remap_nodes[rid.value] = (remap.nsource, remap.ntarget)
+        return rid.value
+
+    def register_sim_remap(self, nsource: int, ntarget: int) -> int:
+        rid = ctypes.c_int32()
+        _check(self._lib.atlas_serve_register_sim_remap(self._h, int(nsource), int(ntarget),
+                                                        ctypes.byref(rid)))
+        self._remap_nodes[rid.value] = (int(nsource), int(ntarget))
+        return rid.value
+
     def submit(self, mesh_id: int, op: int, x=None, out=None, *, nlev=None, dtype=None) -> int:
         """Device request: x (and out, or None for a server-owned output) are
         device tensors [V][nlev] or [V][nlev][2].  Simulation request: x is
-        None and nlev, dtype (ATLAS_F32/ATLAS_F64) are given."""
+        None and nlev, dtype (ATLAS_F32/ATLAS_F64) are given.  A remap
+        request (op ATLAS_SERVE_OP_REMAP, mesh_id a remap id): x is
+        [nsource, ...], out [ntarget, ...] with the same trailing shape."""
         if x is None:
             req = _abi.Request(int(mesh_id), int(op), int(dtype), int(nlev), None, None)
+        elif op == ATLAS_SERVE_OP_REMAP:
+            ns, nt = self._remap_nodes[int(mesh_id)]
+            if x.shape[0] != ns:
+                raise ValueError(f"input has {x.shape[0]} nodes, remap {mesh_id} reads {ns}")
+            ncol = x.numel() // ns
+            o = None
+            if out is not None:
+                o = _out_ptr(out, x, nt * ncol, "output").value
+            req = _abi.Request(int(mesh_id), int(op), _dtype_code(x), int(ncol),
+                               _dev_ptr(x, "input").value, o)
         else:
             vec_in = op in (ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL)
             lev = x.shape[1] if x.dim() >= 2 else 1

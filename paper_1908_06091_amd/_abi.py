@@ -79,6 +79,13 @@ class BatchInfo(ctypes.Structure):
                 ("solo_items", ctypes.c_int32)]
 
 
+class RemapInfo(ctypes.Structure):
+    _fields_ = [("nsource", ctypes.c_int64), ("ntarget", ctypes.c_int64),
+                ("nsource_touched", ctypes.c_int64), ("npolar", ctypes.c_int64),
+                ("device_bytes", ctypes.c_size_t), ("values_per_column", ctypes.c_double),
+                ("table_bytes", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); every symbol the headers declare
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("nstreams", ctypes.c_int32),
@@ -167,12 +174,26 @@ SIGNATURES = {
     "atlas_diag_error_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                               ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_remap_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_remap_create_to_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "atlas_remap_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_remap_get_weights": (ctypes.c_int, [ctypes.c_void_p, _i32p, _dp]),
+    "atlas_remap_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RemapInfo)]),
+    "atlas_remap_free": (ctypes.c_int, [ctypes.c_void_p]),
     "atlas_serve_create": (ctypes.c_int, [ctypes.POINTER(ServeConfig),
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "atlas_serve_register_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.POINTER(ctypes.c_int32)]),
     "atlas_serve_register_sim_mesh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
                                                      ctypes.POINTER(ctypes.c_int32)]),
+    "atlas_serve_register_remap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_int32)]),
+    "atlas_serve_register_sim_remap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                                      ctypes.c_int64,
+                                                      ctypes.POINTER(ctypes.c_int32)]),
     "atlas_serve_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request),
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "atlas_serve_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,

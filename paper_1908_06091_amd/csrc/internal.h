@@ -164,9 +164,28 @@ struct TuneKey {
   }
 };
 
+// Source side of a remap (atlas_remap.h): the parallels of a mesh
+// triangulated strip by strip by the library's rule, first point of every
+// parallel at lon 0.  ok == 0 for any other mesh.
+struct RemapSource {
+  int ok = 0;
+  int32_t nrings = 0;
+  const int64_t *ring_off = nullptr;  // device [nrings+1]
+  const double *ring_lat = nullptr;   // device [nrings]
+};
+
+// True if the description's edges are exactly those of the strip-by-strip
+// triangulation of its parallels `off` (see atlas_remap.h), its parallels
+// have constant, strictly decreasing latitudes and their longitudes start
+// at 0 and increase below 2 pi.
+bool zipper_conforming(const atlas_mesh_desc *d, const std::vector<int64_t> &off);
+
 struct MeshStore {
   DevMesh d;
   int device = 0;
+  RemapSource rs;
+  const double *node_lon = nullptr;  // device [V], by node id
+  const double *node_lat = nullptr;  // device [V], by node id
   int64_t nincid = 0;
   int32_t nrings = 0, max_degree = 0;
   size_t bytes = 0;
@@ -206,9 +225,38 @@ atlas_status pack_lapl_geometry(MeshStore &m, int64_t ngrec);
 LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
                        atlas_dtype dt);
 
+// ------------------------------------------------------------- remaps
+// One target of a remap: its three source nodes and weights (the fourth
+// slot pads the record to 48 bytes; its weight is 0 and its node valid).
+struct __align__(16) RemapRec {
+  int32_t i[4];
+  double w[4];
+};
+
+struct RemapPlan {
+  int device = 0;
+  int64_t nsrc = 0, nt = 0, touched = 0, npolar = 0;
+  RemapRec *rec = nullptr;  // device [nt]
+  size_t bytes = 0;
+  int serve_refs = 0;       // servers holding the remap
+  ~RemapPlan() {
+    if (rec) (void)hipFree(rec);
+  }
+};
+
+// Enqueues out[t][c] = sum_k w_k in[i_k][c] for every target t and column c
+// (arguments already validated).
+atlas_status remap_launch(const RemapPlan &p, const void *in, int32_t ncol, atlas_dtype dt,
+                          void *out, hipStream_t st);
+
 }  // namespace atlasx
 
 // the opaque mesh handle of the C ABI
 struct atlas_mesh_s {
   atlasx::MeshStore *store;
+};
+
+// the opaque remap handle of the C ABI
+struct atlas_remap_s {
+  atlasx::RemapPlan *plan;
 };

@@ -101,6 +101,51 @@ std::vector<int64_t> rings_of(const atlas_mesh_desc *d) {
 
 }  // namespace
 
+bool zipper_conforming(const atlas_mesh_desc *d, const std::vector<int64_t> &off) {
+  const int64_t nr = (int64_t)off.size() - 1;
+  if (nr < 2) return false;
+  const double twopi = 6.283185307179586476925;
+  for (int64_t j = 0; j < nr; ++j) {
+    const int64_t o = off[j], n = off[j + 1] - o;
+    if (n < 3 || d->lon[o] != 0.0) return false;
+    if (j > 0 && !(d->lat[o] < d->lat[off[j - 1]])) return false;
+    for (int64_t i = 0; i < n; ++i) {
+      if (d->lat[o + i] != d->lat[o]) return false;
+      if (!(d->lon[o + i] < twopi) || (i > 0 && !(d->lon[o + i] > d->lon[o + i - 1])))
+        return false;
+    }
+  }
+  // is {p, q} an edge?  (scan the smaller node's CSR row)
+  auto has_edge = [&](int64_t p, int64_t q) {
+    const int64_t a = std::min(p, q), b = std::max(p, q);
+    for (int64_t r = d->node2edge_ptr[a]; r < d->node2edge_ptr[a + 1]; ++r) {
+      const int32_t e = d->node2edge[r];
+      if (d->edge2node[2 * e] == a && d->edge2node[2 * e + 1] == b) return true;
+    }
+    return false;
+  };
+  int64_t count = 0;
+  for (int64_t j = 0; j < nr; ++j) {  // edges along each parallel
+    const int64_t o = off[j], n = off[j + 1] - o;
+    for (int64_t i = 0; i < n; ++i)
+      if (!has_edge(o + i, o + (i + 1) % n)) return false;
+    count += n;
+  }
+  for (int64_t j = 0; j + 1 < nr; ++j) {  // edges across each strip, walked
+    const int64_t ou = off[j], nu = off[j + 1] - ou;
+    const int64_t ol = off[j + 1], nl = off[j + 2] - ol;
+    int64_t a = 0, b = 0;
+    while (a + b < nu + nl) {
+      if (!has_edge(ou + a % nu, ol + b % nl)) return false;
+      const bool up = a < nu && (b == nl || (a + 1) * nl < (b + 1) * nu ||
+                                 ((a + 1) * nl == (b + 1) * nu && nu > nl));
+      if (up) ++a; else ++b;
+    }
+    count += nu + nl;
+  }
+  return count == d->nedges;
+}
+
 // Processing order: bands of `band` parallels; each band is cut into
 // longitude sectors holding about `width` nodes of its widest parallel;
 // a tile is one sector of one band, listed parallel by parallel.  Meshes
@@ -573,6 +618,28 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   if (l2_ok && (st = pack_lapl_geometry(*m, (int64_t)lp.gnode.size())) != ATLAS_OK) {
     delete m;
     return st;
+  }
+  // node coordinates by node id (remap targets and sources), and the
+  // parallels of a mesh a remap can start from
+  {
+    std::vector<double> lon_n(d->lon, d->lon + V), lat_n(d->lat, d->lat + V);
+    if ((st = upload_array(*m, lon_n, &m->node_lon)) != ATLAS_OK ||
+        (st = upload_array(*m, lat_n, &m->node_lat)) != ATLAS_OK) {
+      delete m;
+      return st;
+    }
+    const std::vector<int64_t> off = rings_of(d);
+    if (zipper_conforming(d, off)) {
+      std::vector<double> rlat(off.size() - 1);
+      for (size_t j = 0; j + 1 < off.size(); ++j) rlat[j] = d->lat[off[j]];
+      if ((st = upload_array(*m, off, &m->rs.ring_off)) != ATLAS_OK ||
+          (st = upload_array(*m, rlat, &m->rs.ring_lat)) != ATLAS_OK) {
+        delete m;
+        return st;
+      }
+      m->rs.nrings = (int32_t)rlat.size();
+      m->rs.ok = 1;
+    }
   }
   // the volumes stay (diagnostics); cos by position was only for the scales
   m->d.vol = vol_d;

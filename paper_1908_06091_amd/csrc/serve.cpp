@@ -52,6 +52,8 @@ struct Req {
   uint64_t ticket = 0;
   atlas_request r{};
   MeshStore *m = nullptr;  // NULL on a simulation server
+  RemapPlan *rp = nullptr; // a remap request's weights (NULL when simulated)
+  bool remap = false;
   int64_t V = 0;
   size_t in_b = 0, out_b = 0, ws_b = 0;
   size_t out_off = SIZE_MAX, ws_off = SIZE_MAX;  // arena ranges (SIZE_MAX: none)
@@ -84,6 +86,11 @@ struct Slot {
 struct MeshEntry {
   atlas_mesh_t mesh;  // NULL for a simulated mesh
   int64_t V;
+};
+
+struct RemapEntry {
+  atlas_remap_t remap;  // NULL for a simulated remap
+  int64_t nsrc, nt;
 };
 
 constexpr size_t kTabAlign = 256;
@@ -143,6 +150,7 @@ struct Server {
   int device = 0;
   int grid_full[2] = {8, 8};  // persistent batch grid per dtype (F32, F64)
   std::vector<MeshEntry> meshes;
+  std::vector<RemapEntry> remaps;
   std::vector<Slot> slots;
   Arena arena;  // outputs and workspaces (under mu)
 
@@ -263,8 +271,9 @@ struct Server {
     }
   }
 
+  // Large requests and remaps launch alone.
   bool is_large(const Req &q) const {
-    return q.V * (int64_t)q.r.nlev > cfg.batch_max_elems || cfg.max_batch <= 1;
+    return q.remap || q.V * (int64_t)q.r.nlev > cfg.batch_max_elems || cfg.max_batch <= 1;
   }
 
   // Takes the next launch group from the admitted list: the front request,
@@ -302,6 +311,9 @@ struct Server {
       }
       s.sim_done = now + std::chrono::microseconds(
                              (int64_t)(bytes / std::max(1e-9, cfg.sim_bytes_per_us)));
+    } else if (n == 1 && reqs.at(run[0]).remap) {
+      Req &q = reqs.at(run[0]);
+      status = remap_launch(*q.rp, q.r.in, q.r.nlev, (atlas_dtype)q.r.dtype, q.r.out, s.stream);
     } else if (n == 1) {
       Req &q = reqs.at(run[0]);
       const atlas_op op = (atlas_op)q.r.op;
@@ -463,6 +475,8 @@ atlas_status release_server(Server *sv) {
   }
   for (MeshEntry &e : sv->meshes)
     if (e.mesh && e.mesh->store) e.mesh->store->serve_refs -= 1;
+  for (RemapEntry &e : sv->remaps)
+    if (e.remap && e.remap->plan) e.remap->plan->serve_refs -= 1;
   delete sv;
   return ATLAS_OK;
 }
@@ -562,6 +576,35 @@ atlas_status atlas_serve_register_sim_mesh(atlas_server_t srv, int64_t nnodes, i
   return ATLAS_OK;
 }
 
+atlas_status atlas_serve_register_remap(atlas_server_t srv, atlas_remap_t remap,
+                                        int32_t *remap_id) {
+  if (!srv || !srv->s || !remap || !remap->plan || !remap_id)
+    return fail(ATLAS_EINVAL, "NULL argument");
+  Server &sv = *srv->s;
+  if (sv.cfg.simulate)
+    return fail(ATLAS_EINVAL, "simulation server: use atlas_serve_register_sim_remap");
+  if (remap->plan->device != sv.device) return fail(ATLAS_EINVAL, "remap lives on another device");
+  std::lock_guard<std::mutex> g(sv.mu);
+  remap->plan->serve_refs += 1;
+  sv.remaps.push_back({remap, remap->plan->nsrc, remap->plan->nt});
+  *remap_id = (int32_t)sv.remaps.size() - 1;
+  return ATLAS_OK;
+}
+
+atlas_status atlas_serve_register_sim_remap(atlas_server_t srv, int64_t nsource,
+                                            int64_t ntarget, int32_t *remap_id) {
+  if (!srv || !srv->s || !remap_id) return fail(ATLAS_EINVAL, "NULL argument");
+  Server &sv = *srv->s;
+  if (!sv.cfg.simulate) return fail(ATLAS_EINVAL, "not a simulation server");
+  if (nsource < 1 || nsource >= ((int64_t)1 << 31) || ntarget < 1 ||
+      ntarget >= ((int64_t)1 << 31))
+    return fail(ATLAS_EINVAL, "nsource and ntarget must be in [1, 2^31)");
+  std::lock_guard<std::mutex> g(sv.mu);
+  sv.remaps.push_back({nullptr, nsource, ntarget});
+  *remap_id = (int32_t)sv.remaps.size() - 1;
+  return ATLAS_OK;
+}
+
 atlas_status atlas_serve_submit(atlas_server_t srv, const atlas_request *req, uint64_t *ticket) {
   if (!srv || !srv->s || !req || !ticket) return fail(ATLAS_EINVAL, "NULL argument");
   Server &sv = *srv->s;
@@ -571,41 +614,59 @@ atlas_status atlas_serve_submit(atlas_server_t srv, const atlas_request *req, ui
     return fail(s, msg);
   };
   if (sv.stopping) return reject(ATLAS_ESTATE, "server is shutting down");
-  if (req->mesh_id < 0 || req->mesh_id >= (int32_t)sv.meshes.size())
+  const bool remap = req->op == ATLAS_SERVE_OP_REMAP;
+  if (remap) {
+    if (req->mesh_id < 0 || req->mesh_id >= (int32_t)sv.remaps.size())
+      return reject(ATLAS_EINVAL, "unknown remap id");
+  } else if (req->mesh_id < 0 || req->mesh_id >= (int32_t)sv.meshes.size()) {
     return reject(ATLAS_EINVAL, "unknown mesh_id");
-  if (req->op < ATLAS_OP_GRADIENT || req->op > ATLAS_OP_LAPLACIAN)
+  }
+  if (!remap && (req->op < ATLAS_OP_GRADIENT || req->op > ATLAS_OP_LAPLACIAN))
     return reject(ATLAS_EINVAL, "unknown operator");
   if (req->dtype != ATLAS_F32 && req->dtype != ATLAS_F64) return reject(ATLAS_EINVAL, "unknown dtype");
   if (req->nlev < 1) return reject(ATLAS_EINVAL, "nlev must be >= 1");
-  const MeshEntry &me = sv.meshes[req->mesh_id];
-  if (me.V * req->nlev * 2 >= ((int64_t)1 << 31)) return reject(ATLAS_EINVAL, "nnodes * nlev too large");
   if (!sv.cfg.simulate && !req->in) return reject(ATLAS_EINVAL, "input pointer is NULL");
   const size_t w = req->dtype == ATLAS_F64 ? 8 : 4;
   const bool vin = req->op == ATLAS_OP_DIVERGENCE || req->op == ATLAS_OP_CURL;
-  const size_t base = (size_t)me.V * req->nlev * w;
   Req q;
   q.ticket = sv.next_ticket;
   q.r = *req;
-  q.m = me.mesh ? me.mesh->store : nullptr;
-  q.V = me.V;
-  q.in_b = base * (vin ? 2 : 1);
-  q.out_b = base * (req->op == ATLAS_OP_GRADIENT ? 2 : 1);
-  q.ws_b = req->op == ATLAS_OP_LAPLACIAN ? 2 * base : 0;
-  if (q.m && req->op == ATLAS_OP_LAPLACIAN &&
-      (me.V * req->nlev > sv.cfg.batch_max_elems || sv.cfg.max_batch <= 1)) {
-    // a large Laplacian launches alone: if its shape is the fused one-pass
-    // form it needs no workspace (the shape is kept for the launch)
-    LaunchShape sh = shape_from(nullptr, *q.m, ATLAS_OP_LAPLACIAN, req->nlev,
-                                (atlas_dtype)req->dtype);
-    if (lapl_fused_runs(*q.m, req->nlev, (atlas_dtype)req->dtype, sh)) {
-      q.ws_b = 0;
-      q.sh = sh;
-      q.sh_set = true;
+  if (remap) {
+    const RemapEntry &re = sv.remaps[req->mesh_id];
+    if (std::max(re.nsrc, re.nt) * req->nlev >= ((int64_t)1 << 40))
+      return reject(ATLAS_EINVAL, "nodes * columns too large");
+    q.remap = true;
+    q.rp = re.remap ? re.remap->plan : nullptr;
+    q.V = re.nt;
+    q.in_b = (size_t)re.nsrc * req->nlev * w;
+    q.out_b = (size_t)re.nt * req->nlev * w;
+  } else {
+    const MeshEntry &me = sv.meshes[req->mesh_id];
+    if (me.V * req->nlev * 2 >= ((int64_t)1 << 31))
+      return reject(ATLAS_EINVAL, "nnodes * nlev too large");
+    const size_t base = (size_t)me.V * req->nlev * w;
+    q.m = me.mesh ? me.mesh->store : nullptr;
+    q.V = me.V;
+    q.in_b = base * (vin ? 2 : 1);
+    q.out_b = base * (req->op == ATLAS_OP_GRADIENT ? 2 : 1);
+    q.ws_b = req->op == ATLAS_OP_LAPLACIAN ? 2 * base : 0;
+    if (q.m && req->op == ATLAS_OP_LAPLACIAN &&
+        (me.V * req->nlev > sv.cfg.batch_max_elems || sv.cfg.max_batch <= 1)) {
+      // a large Laplacian launches alone: if its shape is the fused one-pass
+      // form it needs no workspace (the shape is kept for the launch)
+      LaunchShape sh = shape_from(nullptr, *q.m, ATLAS_OP_LAPLACIAN, req->nlev,
+                                  (atlas_dtype)req->dtype);
+      if (lapl_fused_runs(*q.m, req->nlev, (atlas_dtype)req->dtype, sh)) {
+        q.ws_b = 0;
+        q.sh = sh;
+        q.sh_set = true;
+      }
     }
   }
   q.own_out = req->out == nullptr;
   if (!sv.cfg.simulate) {
     const size_t iw = vin ? 2 * w : w, ow = req->op == ATLAS_OP_GRADIENT ? 2 * w : w;
+    // (a remap's op is neither: element-aligned input and output)
     if ((uintptr_t)req->in % iw || (req->out && (uintptr_t)req->out % ow))
       return reject(ATLAS_EINVAL, "field pointer not aligned to its element size");
     if (req->out) {

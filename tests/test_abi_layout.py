@@ -17,7 +17,7 @@ STRUCTS = {
     "atlas_work_item": "WorkItem", "atlas_batch_config": "BatchConfig",
     "atlas_batch_info": "BatchInfo", "atlas_serve_config": "ServeConfig",
     "atlas_request": "Request", "atlas_result": "Result",
-    "atlas_serve_stats": "ServeStats",
+    "atlas_serve_stats": "ServeStats", "atlas_remap_info": "RemapInfo",
 }
 # binding field names that differ from the C names
 RENAMED = {("WorkItem", "in_"): "in", ("Request", "in_"): "in"}
@@ -30,7 +30,8 @@ def layouts(tmp_path_factory):
     if cc is None or not os.path.isdir("/opt/rocm/include"):
         pytest.skip("no host C compiler or HIP headers")
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "atlas_nabla.h"',
-             '#include "atlas_batch.h"', '#include "atlas_serve.h"', 'int main(void) {']
+             '#include "atlas_batch.h"', '#include "atlas_serve.h"', '#include "atlas_remap.h"',
+             'int main(void) {']
     for cname, pyname in STRUCTS.items():
         lines.append(f'  printf("{pyname} size %zu\\n", sizeof({cname}));')
         for fname, _ in getattr(_abi, pyname)._fields_:

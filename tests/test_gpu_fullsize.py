@@ -229,21 +229,27 @@ def _local_scale(big, op, nlev):
     the node sums, level by level (|x| the larger component of a vector)."""
     key = ("local", op)
     if key not in big["refs"]:
-        P, nodes = big["P"], big["nodes"]
-        d = big.get("desc")
-        if d is None:
-            d = big["desc"] = P.mesh_desc_octahedral(big["N"])
-        ptr, inc, e2n = d["node2edge_ptr"], d["node2edge"], d["edge2node"]
-        S = np.abs(d["dual_normals"]).sum(axis=1)
+        om, nodes = big["om"], big["nodes"]
+        inc = big.get("incidences")
+        if inc is None:  # each node's edges, from the oracle's edge table
+            E = om.E
+            ends = np.concatenate([om.edge[:, 0], om.edge[:, 1]]).astype(np.int64)
+            order = np.argsort(ends, kind="stable")
+            eid = (order % E).astype(np.int64)
+            lo = np.searchsorted(ends[order], nodes, "left")
+            hi = np.searchsorted(ends[order], nodes, "right")
+            inc = big["incidences"] = [eid[a:b] for a, b in zip(lo, hi)]
+        e2n = om.edge
+        S = np.abs(om.S).sum(axis=1)
         name = {"grad": "f", "div": "uv", "curl": "uvr"}[op]
         x = big[name + "_h"]
         partner = {}
-        for (a, b), sn in zip(d["pole_edges"], d["pole_normals"]):
+        for (a, b), sn in zip(om.pole_edge, om.pole_normal):
             partner[int(a)] = (int(b), abs(sn))
             partner[int(b)] = (int(a), abs(sn))
         out = np.empty((len(nodes), NLEV))
         for q, i in enumerate(nodes):
-            es = inc[ptr[i]:ptr[i + 1]]
+            es = inc[q]
             a, b = e2n[es, 0], e2n[es, 1]
             xa, xb = np.abs(x[a]), np.abs(x[b])
             if xa.ndim == 3:
@@ -255,9 +261,56 @@ def _local_scale(big, op, nlev):
                 if xi.ndim == 2:
                     xi, xp = xi.max(axis=1), xp.max(axis=1)
                 t = t + sn * (xi + xp)
-            out[q] = t / d["dual_volumes"][i] * d["radius"]
+            out[q] = t / om.vol[i] * om.R
         big["refs"][key] = out
     return big["refs"][key][:, :nlev]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_o1280_remap_to_o640_points_sampled(big, dtype):
+    """Remap of the 137-level benchmark field from O1280 to the 1,661,440
+    nodes of O640 (their coordinates from the oracle's O640 grid), in the
+    apply launch the benchmark times: the weights and the remapped values of
+    sampled targets (random, both polar caps, ring starts and quarter
+    points) against the oracle."""
+    import oracle
+    P, om, gm = big["P"], big["om"], big["gm"]
+    tgt = big.get("o640")
+    if tgt is None:
+        tgt = big["o640"] = oracle.Mesh(640)
+    print(f"fullsize remap O1280 -> O640 points {dtype}", flush=True)
+    r = P.Remap(gm, lon=tgt.lon, lat=tgt.lat)
+    assert r.ntarget == tgt.V
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    x = big["f"].to(dt)
+    out = r.apply(x)
+    rng = np.random.default_rng(640)
+    pick = set(rng.choice(tgt.V, size=3000, replace=False).tolist())
+    pick.update(range(0, 48))
+    pick.update(range(tgt.V - 48, tgt.V))
+    ro, nx = np.asarray(tgt.ring_off), np.asarray(tgt.nx)
+    for j in range(0, len(nx), 17):
+        for q in range(4):
+            pick.add(int(ro[j] + q * nx[j] // 4))
+    sel = np.array(sorted(pick), dtype=np.int64)
+    got = out.index_select(0, torch.from_numpy(sel).cuda()).double().cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    oidx, ow = om.remap_weights(tgt.lon[sel], tgt.lat[sel])
+    gidx, gw = r.weights()
+    from scipy.sparse import csr_matrix
+    rows = np.repeat(np.arange(sel.size), 3)
+    Wg = csr_matrix((gw[sel].ravel(), (rows, gidx[sel].ravel().astype(np.int64))),
+                    shape=(sel.size, om.V))
+    Wo = csr_matrix((ow.ravel(), (rows, oidx.ravel().astype(np.int64))), shape=(sel.size, om.V))
+    dW = Wg - Wo
+    assert (np.abs(dW.data).max() if dW.nnz else 0.0) <= 1e-13
+    xh = big["f_h"] if dtype == "f64" else x.double().cpu().numpy()
+    ref = oracle.remap_apply(oidx, ow, xh, NLEV, om.V)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"O1280 -> O640 remap L137 {dtype}: max_rel={err:.3e}", flush=True)
+    assert err <= (1e-12 if dtype == "f64" else 1e-5)
+    del x
 
 
 @pytest.fixture(scope="module")

@@ -152,3 +152,46 @@ def test_served_result_matches_oracle(P, meshes):
         emax, _ = normwise_error(out.cpu().numpy(), ref)
         assert emax <= TOL["f64"], (op, emax)
     srv.close()
+
+
+def test_remap_requests_in_the_mix(P, meshes):
+    """Remap requests (ATLAS_SERVE_OP_REMAP) between O48 and O16, FP64 and
+    FP32, submitted among operator requests: each result equals the same
+    remap run alone, bit for bit, and the FP64 one matches the oracle's
+    interpolation."""
+    import oracle
+    gs, gd = meshes[48], meshes[16]
+    r = P.Remap(gs, gd)
+    srv = P.Server(hbm_budget_bytes=1 << 30, nstreams=3, max_batch=16)
+    rid = srv.register_remap(r)
+    mid = srv.register_mesh(gd)
+    x64 = torch.randn(gs.nnodes, 37, dtype=torch.float64, device="cuda")
+    x32 = torch.randn(gs.nnodes, 5, 2, dtype=torch.float32, device="cuda")
+    y = torch.randn(gd.nnodes, 7, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(4):
+        ts.append(("r64", srv.submit(rid, P.ATLAS_SERVE_OP_REMAP, x64)))
+        ts.append(("g", srv.submit(mid, P.ATLAS_OP_GRADIENT, y)))
+        ts.append(("r32", srv.submit(rid, P.ATLAS_SERVE_OP_REMAP, x32)))
+    alone = {"r64": r.apply(x64), "r32": r.apply(x32), "g": gd.gradient(y)}
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.restype = ctypes.c_int
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    for kind, t in ts:
+        res = srv.wait(t, timeout_us=60_000_000)
+        assert res["status"] == P.ATLAS_OK
+        ref = alone[kind]
+        got = torch.empty_like(ref)
+        torch.cuda.synchronize()
+        assert hip.hipMemcpy(got.data_ptr(), res["out"], ref.numel() * ref.element_size(), 3) == 0
+        assert torch.equal(got, ref), kind
+        srv.release(t)
+    with pytest.raises(P.AtlasError):
+        r.close()  # registered with a live server
+    srv.close()
+    om_s, om_d = oracle.Mesh(48), oracle.Mesh(16)
+    want = om_s.remap(x64.cpu().numpy(), 37, om_d.lon, om_d.lat)
+    got = alone["r64"].cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    r.close()

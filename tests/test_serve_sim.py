@@ -257,3 +257,38 @@ def test_destroy_cancels_requests_that_can_no_longer_be_admitted():
     with pytest.raises(AtlasError, match="ETIMEOUT"):
         s.wait(t1, timeout_us=100_000)
     s.close()
+
+
+def test_remap_requests_launch_alone_and_charge_their_sizes():
+    """Remap requests (ATLAS_SERVE_OP_REMAP) footprint: source rows in,
+    target rows out, no workspace; they never merge into a batch, while the
+    operator requests around them still do."""
+    REMAP = P.ATLAS_SERVE_OP_REMAP
+    s = make(max_batch=64, nstreams=1, sim_bytes_per_us=2.0)  # the blocker: 1.6 s
+    m = s.register_sim_mesh(1000)
+    r = s.register_sim_remap(4000, 1000)
+    blocker = s.submit(m, GRAD, nlev=137, dtype=F64)
+    until_launched(s, 1)
+    ts = [s.submit(r, REMAP, nlev=10, dtype=F64) for _ in range(3)]
+    ts += [s.submit(m, GRAD, nlev=1, dtype=F32) for _ in range(3)]
+    want = footprint(1000, 137, GRAD, 8) + 3 * (4000 + 1000) * 10 * 8 + \
+        3 * footprint(1000, 1, GRAD, 4)
+    t0 = time.time()  # admission runs on the scheduler thread
+    while s.stats()["inflight_bytes"] != want and time.time() - t0 < 1.0:
+        time.sleep(1e-3)
+    assert s.stats()["inflight_bytes"] == want
+    for t in [blocker] + ts:
+        assert s.wait(t)["status"] == P.ATLAS_OK
+    for t in ts[:3]:
+        assert s.wait(t)["batch_size"] == 1
+    assert max(s.wait(t)["batch_size"] for t in ts[3:]) > 1
+    for t in [blocker] + ts:
+        s.release(t)
+    assert s.stats()["inflight_bytes"] == 0
+    with pytest.raises(AtlasError):
+        s.submit(r + 1, REMAP, nlev=1, dtype=F64)  # unknown remap id
+    with pytest.raises(AtlasError):
+        s.submit(m, 5, nlev=1, dtype=F64)  # unknown operator
+    with pytest.raises(AtlasError):
+        s.register_sim_remap(0, 10)
+    s.close()
