@@ -90,6 +90,12 @@ typedef struct atlas_mesh_s *atlas_mesh_t;
  *   pole_normals                [npole_edges] lat component of the pole-face
  *                               normal carried by each pole edge (+-2pi/nx)
  *   radius                      sphere radius R
+ *   ntriangles, triangles       optional element blocks (Section 4.3,
+ *   nquads, quads               Figure 27: one block per element type):
+ *                               [ntriangles][3] and [nquads][4] node ids,
+ *                               counter-clockwise in (lon, lat).  Filled by
+ *                               the library's generators; not read by
+ *                               atlas_mesh_upload (0 / NULL allowed)
  */
 typedef struct {
   int64_t nnodes;
@@ -107,6 +113,10 @@ typedef struct {
   const int32_t *pole_edges;
   const double *pole_normals;
   double radius;
+  int64_t ntriangles;
+  const int32_t *triangles;
+  int64_t nquads;
+  const int32_t *quads;
 } atlas_mesh_desc;
 
 /* Sizes of an uploaded mesh. */
@@ -140,6 +150,29 @@ atlas_status atlas_mesh_desc_octahedral(int32_t N, double radius,
  * ATLAS_ENOMEM. */
 atlas_status atlas_mesh_desc_reduced_gaussian(int32_t nrings, const int32_t *nx, double radius,
                                               atlas_mesh_desc **out);
+/* Flags of atlas_mesh_desc_grid. */
+#define ATLAS_MESH_SHIFTED 1 /* every point half a spacing east of lon 0 + i dlon */
+#define ATLAS_MESH_QUADS 2   /* strips between parallels of equal counts become
+                                quadrilaterals; the others stay triangles */
+
+/* Any grid of parallels: nx[j] points on parallel j (first point at lon 0,
+ * or half a spacing east of it with ATLAS_MESH_SHIFTED, which needs equal
+ * counts on all parallels), at latitude lat[j] in radians (strictly
+ * decreasing, inside (-pi/2, pi/2): no point on a pole), or at the Gaussian
+ * latitudes of degree nrings when lat is NULL (nrings even).  With
+ * ATLAS_MESH_QUADS a strip between two parallels of equal counts is meshed
+ * with quadrilaterals (U_a, L_a, L_a+1, U_a+1), the blocked quadrilaterals
+ * of Section 4.3, and the others with triangles as above: the description's
+ * element blocks then hold both types (Figure 27), and the median-dual
+ * cells of the quadrilaterals are built about their centres (the mean of
+ * the four corners).  The regular longitude-latitude grids of Section
+ * 4.2.3.8 without points on the poles: SLAT<nlon>x<nlat> is nx[j] = nlon,
+ * lat[j] = pi/2 - (j + 1/2) pi / nlat; S<nlon>x<nlat> adds
+ * ATLAS_MESH_SHIFTED.  Errors: as atlas_mesh_desc_reduced_gaussian, plus
+ * ATLAS_EINVAL for latitudes out of order or range, unknown flags, or
+ * ATLAS_MESH_SHIFTED with unequal counts. */
+atlas_status atlas_mesh_desc_grid(int32_t nrings, const int32_t *nx, const double *lat,
+                                  int32_t flags, double radius, atlas_mesh_desc **out);
 atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc);
 
 /* ---------------------------------------------------------------------- */
@@ -199,6 +232,14 @@ atlas_status atlas_nabla_divergence(atlas_mesh_t mesh, const void *uv,
                                     hipStream_t stream);
 atlas_status atlas_nabla_curl(atlas_mesh_t mesh, const void *uv, int32_t nlev,
                               atlas_dtype dtype, void *out, hipStream_t stream);
+/* The derivatives in the computational (lon, lat) plane instead of the
+ * physical components: out[i][k] = (d f/d lon, d f/d lat) =
+ * (R cos(lat_i) grad_lon, R grad_lat), both the node's edge sums divided by
+ * its dual area in the (lon, lat) plane.  Same layout, arguments and errors
+ * as atlas_nabla_gradient (plus ATLAS_ENOMEM: the first call on a mesh
+ * allocates 48 bytes per node of scales). */
+atlas_status atlas_nabla_gradient_lonlat(atlas_mesh_t mesh, const void *f, int32_t nlev,
+                                         atlas_dtype dtype, void *out, hipStream_t stream);
 /* Divergence and curl of the same (u, v) field in one pass (Section 4.7:
  * both operators of one Nabla object applied to one field): the field is
  * read once and each output is bitwise the result of its own entry point.
@@ -260,7 +301,13 @@ typedef struct {
                                the processing order together, one position
                                per wavefront per step, so the set of columns
                                in flight stays small enough for the L2;
-                               0 = one workgroup per tile                   */
+                               0 = one workgroup per tile.  Sweep form: 0 =
+                               wave-specialised workgroups (two waves load
+                               the next parallels straight into LDS, the
+                               others compute and store; 16-byte lane
+                               vectors, at least 256 threads, level_vec 0
+                               or the 16-byte width); > 0 = every wave
+                               stages loads through registers            */
   int32_t level_vec;        /* column, sweep and fused forms: levels per
                                lane.  0 = the level-vector kernels at the
                                automatic width: FP64 16-byte lanes (2

@@ -58,6 +58,10 @@ def _load():
         lib.orc_mesh_build.restype = ctypes.c_void_p
         lib.orc_mesh_build_pl.argtypes = [ctypes.c_int, _c_i32p, ctypes.c_double]
         lib.orc_mesh_build_pl.restype = ctypes.c_void_p
+        lib.orc_mesh_build_ex.argtypes = [ctypes.c_int, _c_i32p, _c_dp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double]
+        lib.orc_mesh_build_ex.restype = ctypes.c_void_p
+        lib.orc_mesh_copy_quads.argtypes = [ctypes.c_void_p, _c_i32p]
         lib.orc_mesh_free.argtypes = [ctypes.c_void_p]
         lib.orc_mesh_sizes.argtypes = [ctypes.c_void_p, _c_i64p]
         lib.orc_mesh_copy.argtypes = [ctypes.c_void_p, _c_i32p, _c_i64p, _c_dp,
@@ -65,7 +69,8 @@ def _load():
                                       _c_dp, _c_i32p, _c_dp]
         lib.orc_threads_used.argtypes = [ctypes.c_int]
         lib.orc_set_threads.argtypes = [ctypes.c_int]
-        for name in ("orc_gradient", "orc_divergence", "orc_curl", "orc_laplacian"):
+        for name in ("orc_gradient", "orc_gradient_lonlat", "orc_divergence", "orc_curl",
+                     "orc_laplacian"):
             getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_int, _c_dp, _c_dp]
         for name in ("orc_gradient_at", "orc_divergence_at", "orc_curl_at",
                      "orc_laplacian_at"):
@@ -102,6 +107,16 @@ def set_threads(n: int) -> int:
     return int(_load().orc_set_threads(int(n)))
 
 
+def shifted_lonlat(nlon: int, nlat: int):
+    """Points per parallel and latitudes of the regular lon-lat grid with
+    nlat parallels at lat = 90 deg - (j + 1/2) 180 deg / nlat (no point on
+    a pole) and nlon points on each (Section 4.2.3.8: the latitude-shifted
+    grid SLAT<nlon>x<nlat>; with ``shift=True`` in Mesh, the shifted grid
+    S<nlon>x<nlat>)."""
+    lat = 0.5 * np.pi - (np.arange(nlat) + 0.5) * np.pi / nlat
+    return np.full(nlat, int(nlon), np.int32), lat
+
+
 def regular_gaussian_nx(N: int) -> np.ndarray:
     """Points per parallel of the regular Gaussian grid F<N> (Section
     4.2.3.6: nx = 4N on each of the 2N parallels)."""
@@ -109,35 +124,50 @@ def regular_gaussian_nx(N: int) -> np.ndarray:
 
 
 class Mesh:
-    """A reduced Gaussian grid, its triangulation, edges and median-dual
-    geometry, built by the oracle: O<N> from (N, R) alone (Section 4.2.3.7,
-    Listing 6), or any grid from its points per parallel ``nx`` (2N even
-    entries' worth of parallels at the Gaussian latitudes of degree 2N;
-    ``regular_gaussian_nx(N)`` gives F<N>)."""
+    """A grid of parallels, its mesh, edges and median-dual geometry, built
+    by the oracle: O<N> from (N, R) alone (Section 4.2.3.7, Listing 6), or
+    any grid from its points per parallel ``nx`` (at the Gaussian latitudes
+    of degree len(nx), or at explicit latitudes ``lat``; ``shift`` puts the
+    first point of every parallel half a spacing east of lon 0, as the
+    shifted regular grids of Section 4.2.3.8; ``quads`` makes every strip
+    between two parallels of equal counts a row of quadrilaterals instead of
+    triangles, so the elements come in two blocks, ``tri`` and ``quad``)."""
 
-    def __init__(self, N: int = 0, R: float = 1.0, nx=None):
+    def __init__(self, N: int = 0, R: float = 1.0, nx=None, *, lat=None, shift=False,
+                 quads=False):
         lib = _load()
         self._lib = lib
-        if nx is None:
+        if nx is None and lat is None and not shift and not quads:
             self._h = lib.orc_mesh_build(int(N), float(R))
             what = f"O{N}"
         else:
+            if nx is None:
+                nx = np.array([20 + 4 * j for j in range(N)] +
+                              [20 + 4 * j for j in range(N - 1, -1, -1)], np.int32)
             nx = np.ascontiguousarray(nx, dtype=np.int32)
             N = len(nx) // 2
-            self._h = lib.orc_mesh_build_pl(len(nx), nx.ctypes.data_as(_c_i32p), float(R))
+            if lat is None and not shift and not quads:
+                self._h = lib.orc_mesh_build_pl(len(nx), nx.ctypes.data_as(_c_i32p), float(R))
+            else:
+                la = None if lat is None else np.ascontiguousarray(lat, dtype=np.float64)
+                self._h = lib.orc_mesh_build_ex(len(nx), nx.ctypes.data_as(_c_i32p),
+                                                None if la is None else _dp(la), int(bool(shift)),
+                                                int(bool(quads)), float(R))
             what = f"the grid with nx={nx.tolist()[:4]}..."
         if not self._h:
             raise ValueError(f"cannot build {what} with R={R}")
-        sz = np.zeros(6, dtype=np.int64)
+        sz = np.zeros(8, dtype=np.int64)
         lib.orc_mesh_sizes(self._h, sz.ctypes.data_as(_c_i64p))
         self.N = int(N)
         self.R = float(R)
         self.V, self.E, self.F, self.npole, self.nrings = (int(x) for x in sz[:5])
+        self.Q = int(sz[6])
         self.nx = np.empty(self.nrings, np.int32)
         self.ring_off = np.empty(self.nrings + 1, np.int64)
         self.lon = np.empty(self.V, np.float64)
         self.lat = np.empty(self.V, np.float64)
         self.tri = np.empty((self.F, 3), np.int32)
+        self.quad = np.empty((self.Q, 4), np.int32)
         self.edge = np.empty((self.E, 2), np.int32)
         self.S = np.empty((self.E, 2), np.float64)
         self.A = np.empty(self.V, np.float64)
@@ -151,6 +181,7 @@ class Mesh:
                           _dp(self.A), _dp(self.vol),
                           self.pole_edge.ctypes.data_as(_c_i32p),
                           _dp(self.pole_normal))
+        lib.orc_mesh_copy_quads(self._h, self.quad.ctypes.data_as(_c_i32p))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -176,6 +207,15 @@ class Mesh:
         out = np.empty((self.V, nlev, 2), np.float64)
         if self._lib.orc_gradient(self._h, nlev, _dp(f), _dp(out)) != 0:
             raise ValueError("orc_gradient failed")
+        return out
+
+    def gradient_lonlat(self, f, nlev: int = 1) -> np.ndarray:
+        """(d f/d lon, d f/d lat) at the nodes, [V][nlev][2]: the gradient's
+        edge sums divided by the dual area in the (lon, lat) plane."""
+        f = self._scalar_in(f, nlev)
+        out = np.empty((self.V, nlev, 2), np.float64)
+        if self._lib.orc_gradient_lonlat(self._h, nlev, _dp(f), _dp(out)) != 0:
+            raise ValueError("orc_gradient_lonlat failed")
         return out
 
     def divergence(self, uv, nlev: int = 1) -> np.ndarray:
@@ -257,6 +297,8 @@ class Mesh:
         w = np.empty((lon.size, 3), np.float64)
         rc = self._lib.orc_remap_weights(self._h, lon.size, _dp(lon), _dp(lat),
                                          idx.ctypes.data_as(_c_i32p), _dp(w))
+        if rc == -3:
+            raise ValueError("remap needs a triangulated mesh with parallels starting at lon 0")
         if rc != 0:
             raise ValueError("a target latitude is outside [-pi/2, pi/2] or not finite")
         return idx, w

@@ -16,8 +16,13 @@
  *     array is 20 + 4j up to the equator, mirrored about it); Section 4.2
  *     (points are equispaced along each parallel).
  *   - Mesh: Section 4.3 (triangles between the parallels, edges between
- *     nodes; Eq. 1) and Section 4.3 on vertical extrusion (levels are
- *     independent prisms, so every level is an independent 2-D problem).
+ *     nodes; Eq. 1; on request the blocked quadrilaterals of regular grids
+ *     between parallels of equal counts, the two element types kept in two
+ *     blocks as in Figure 27) and Section 4.3 on vertical extrusion (levels
+ *     are independent prisms, so every level is an independent 2-D
+ *     problem).  Grids: also the regular longitude-latitude grids of
+ *     Section 4.2.3.8 without points on the poles (latitude-shifted and
+ *     shifted variants).
  *   - Field layout: Section 4.5, Figure 31 (NodeColumns: one vertical column
  *     contiguous per node, i.e. [node][level]); Listing 12 (gradient output
  *     has two variables, stored [node][level][2]).
@@ -40,6 +45,7 @@
  *   triangulation  -> Euler counts, CCW areas, band area, edge multiplicity
  *   dual geometry  -> sum of areas = 2 pi^2; cell closure; brute-force
  *                     median-dual polygons built independently in the tests
+ *                     (triangles and quadrilaterals)
  *   gradient       -> exact for linear data (interior), zero for constants,
  *                     Galerkin identity sum_T |T|/3 grad(phi_T) (brute force)
  *   polar nodes    -> pole-face value recovered from the output against
@@ -76,6 +82,9 @@ typedef struct {
   double *coslat;        /* [V] cos(lat)                                    */
   int64_t F;             /* triangles                                       */
   int32_t *tri;          /* [F][3] counter-clockwise in (lon, lat)          */
+  int64_t Q;             /* quadrilaterals (second block of elements)       */
+  int32_t *quad;         /* [Q][4] counter-clockwise in (lon, lat)          */
+  int shift;             /* longitudes shifted by half a spacing            */
   int64_t E;             /* mesh edges                                      */
   int32_t *edge;         /* [E][2], edge[e][0] < edge[e][1]                 */
   double *S;             /* [E][2] dual-face normal (S_lon, S_lat), a -> b  */
@@ -169,7 +178,7 @@ static int64_t find_edge(const orc_mesh *m, const int64_t *first, int32_t p,
 void orc_mesh_free(orc_mesh *m) {
   if (!m) return;
   free(m->nx); free(m->ring_off); free(m->lon); free(m->lat); free(m->coslat);
-  free(m->tri); free(m->edge); free(m->S); free(m->A); free(m->vol);
+  free(m->tri); free(m->quad); free(m->edge); free(m->S); free(m->A); free(m->vol);
   free(m->pole_edge); free(m->pole_normal); free(m->adj_ptr);
   free(m->adj_edge); free(m->pole_of);
   free(m);
@@ -182,15 +191,36 @@ void orc_mesh_free(orc_mesh *m) {
 /* edges and median-dual geometry.  Needs nrings even, every nx >= 4 and     */
 /* the two polar parallels even (their nodes pair up across the pole).       */
 /* ------------------------------------------------------------------------ */
-orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
-  if (nrings < 2 || (nrings & 1) || !nx_in || !(R > 0.0)) return NULL;
+/* The general builder.  lat_in: the latitudes of the parallels (strictly
+ * decreasing, inside (-pi/2, pi/2)), or NULL for the Gaussian latitudes of
+ * degree nrings (nrings even).  shift: every longitude displaced by half its
+ * parallel's spacing (the shifted regular grids of Section 4.2.3.8; needs
+ * equal counts on all parallels).  quads: a strip between two parallels of
+ * equal counts becomes quadrilaterals (U_a, L_a, L_a+1, U_a+1) -- the
+ * blocked arrangement of quadrilaterals of Section 4.3 -- instead of
+ * triangles; other strips stay triangulated, so a mesh can hold both element
+ * types (two blocks, Section 4.3, Figure 27). */
+static orc_mesh *build_general(int nrings, const int32_t *nx_in, const double *lat_in,
+                               int shift, int quads, double R) {
+  if (nrings < 2 || !nx_in || !(R > 0.0)) return NULL;
+  if (!lat_in && (nrings & 1)) return NULL;
   for (int j = 0; j < nrings; ++j)
     if (nx_in[j] < 4) return NULL;
   if ((nx_in[0] & 1) || (nx_in[nrings - 1] & 1)) return NULL;
+  if (lat_in) {
+    for (int j = 0; j < nrings; ++j) {
+      if (!isfinite(lat_in[j]) || !(fabs(lat_in[j]) < 0.5 * ORC_PI)) return NULL;
+      if (j > 0 && !(lat_in[j] < lat_in[j - 1])) return NULL;
+    }
+  }
+  if (shift)
+    for (int j = 1; j < nrings; ++j)
+      if (nx_in[j] != nx_in[0]) return NULL;
   orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
   if (!m) return NULL;
   const int N = nrings / 2;
   m->N = N;
+  m->shift = shift ? 1 : 0;
   m->R = R;
   m->nrings = nrings;
   const int nr = m->nrings;
@@ -204,16 +234,18 @@ orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
   m->V = V;
 
   double *mu = (double *)malloc(sizeof(double) * nr);
-  orc_gauss_mu(N, mu);
+  if (!lat_in) orc_gauss_mu(N, mu);
   m->lon = (double *)malloc(sizeof(double) * V);
   m->lat = (double *)malloc(sizeof(double) * V);
   m->coslat = (double *)malloc(sizeof(double) * V);
   for (int j = 0; j < nr; ++j) {
-    double th = asin(mu[j]);
+    double th = lat_in ? lat_in[j] : asin(mu[j]);
     for (int i = 0; i < m->nx[j]; ++i) {
       int64_t id = m->ring_off[j] + i;
-      /* equispaced along the parallel, first point at lon = 0 (Sec 4.2.3.5) */
-      m->lon[id] = 2.0 * ORC_PI * (double)i / (double)m->nx[j];
+      /* equispaced along the parallel, first point at lon = 0 (Sec 4.2.3.5),
+       * or half a spacing east of it on a shifted grid (Sec 4.2.3.8) */
+      m->lon[id] = shift ? 2.0 * ORC_PI * ((double)i + 0.5) / (double)m->nx[j]
+                         : 2.0 * ORC_PI * (double)i / (double)m->nx[j];
       m->lat[id] = th;
       m->coslat[id] = cos(th);
     }
@@ -226,14 +258,29 @@ orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
    * next lower point at 2pi(b+1)/nl; the one further west is consumed first
    * (compared exactly in integers).  On a tie the ring with more points
    * advances; with equal counts the lower ring advances.                   */
-  int64_t F = 0;
-  for (int j = 0; j + 1 < nr; ++j) F += m->nx[j] + m->nx[j + 1];
+  int64_t F = 0, Q = 0;
+  for (int j = 0; j + 1 < nr; ++j) {
+    if (quads && m->nx[j] == m->nx[j + 1]) Q += m->nx[j];
+    else F += m->nx[j] + m->nx[j + 1];
+  }
   m->F = F;
-  m->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * F);
-  int64_t t = 0;
+  m->Q = Q;
+  m->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * (F > 0 ? F : 1));
+  m->quad = (int32_t *)malloc(sizeof(int32_t) * 4 * (Q > 0 ? Q : 1));
+  int64_t t = 0, qd = 0;
   for (int j = 0; j + 1 < nr; ++j) {
     const int64_t nu = m->nx[j], nl = m->nx[j + 1];
     const int64_t ou = m->ring_off[j], ol = m->ring_off[j + 1];
+    if (quads && nu == nl) {
+      for (int64_t a = 0; a < nu; ++a) {
+        m->quad[4 * qd + 0] = (int32_t)(ou + a);
+        m->quad[4 * qd + 1] = (int32_t)(ol + a);
+        m->quad[4 * qd + 2] = (int32_t)(ol + (a + 1) % nl);
+        m->quad[4 * qd + 3] = (int32_t)(ou + (a + 1) % nu);
+        ++qd;
+      }
+      continue;
+    }
     int64_t a = 0, b = 0;
     while (a < nu || b < nl) {
       int64_t up = (a + 1) * nl, lo = (b + 1) * nu;
@@ -260,7 +307,8 @@ orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
   }
 
   /* --- unique edges (a < b), sorted lexicographically; id = rank -------- */
-  int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * 3 * F);
+  const int64_t nkeys = 3 * F + 4 * Q;
+  int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * nkeys);
   for (int64_t f = 0; f < F; ++f) {
     for (int k = 0; k < 3; ++k) {
       int64_t p = m->tri[3 * f + k], q = m->tri[3 * f + (k + 1) % 3];
@@ -268,9 +316,16 @@ orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
       keys[3 * f + k] = a * V + b;
     }
   }
-  qsort(keys, (size_t)(3 * F), sizeof(int64_t), cmp_i64);
+  for (int64_t f = 0; f < Q; ++f) {
+    for (int k = 0; k < 4; ++k) {
+      int64_t p = m->quad[4 * f + k], q = m->quad[4 * f + (k + 1) % 4];
+      int64_t a = p < q ? p : q, b = p < q ? q : p;
+      keys[3 * F + 4 * f + k] = a * V + b;
+    }
+  }
+  qsort(keys, (size_t)nkeys, sizeof(int64_t), cmp_i64);
   int64_t E = 0;
-  for (int64_t k = 0; k < 3 * F; ++k)
+  for (int64_t k = 0; k < nkeys; ++k)
     if (k == 0 || keys[k] != keys[k - 1]) keys[E++] = keys[k];
   m->E = E;
   m->edge = (int32_t *)malloc(sizeof(int32_t) * 2 * E);
@@ -319,6 +374,39 @@ orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
       double nxv = dy, nyv = -dx;
       /* direction a -> b, a the smaller node id */
       const int ia = (id[u] < id[v]) ? u : v, ib = (ia == u) ? v : u;
+      const double ex = x[ib] - x[ia], ey = y[ib] - y[ia];
+      if (nxv * ex + nyv * ey < 0.0) { nxv = -nxv; nyv = -nyv; }
+      m->S[2 * e + 0] += nxv;
+      m->S[2 * e + 1] += nyv;
+    }
+  }
+  /* Quadrilaterals: the same median dual about the element centre c (the
+   * mean of its four vertices).  Node k of the element receives the area of
+   * the polygon (x_k, m_k,k+1, c, m_k-1,k) (shoelace), and every edge the
+   * normal of its segment m_e -> c, oriented from a towards b. */
+  for (int64_t f = 0; f < Q; ++f) {
+    int32_t id[4];
+    double x[4], y[4];
+    for (int k = 0; k < 4; ++k) {
+      id[k] = m->quad[4 * f + k];
+      x[k] = m->lon[id[k]];
+      y[k] = m->lat[id[k]];
+    }
+    for (int k = 1; k < 4; ++k) x[k] = unwrap(x[k], x[0]);
+    const double cx = 0.25 * (x[0] + x[1] + x[2] + x[3]);
+    const double cy = 0.25 * (y[0] + y[1] + y[2] + y[3]);
+    for (int k = 0; k < 4; ++k) {
+      const int kn = (k + 1) % 4, kp = (k + 3) % 4;
+      const double mnx = 0.5 * (x[k] + x[kn]), mny = 0.5 * (y[k] + y[kn]);
+      const double mpx = 0.5 * (x[k] + x[kp]), mpy = 0.5 * (y[k] + y[kp]);
+      const double px[4] = {x[k], mnx, cx, mpx}, py[4] = {y[k], mny, cy, mpy};
+      double a2 = 0.0;
+      for (int s2 = 0; s2 < 4; ++s2) a2 += px[s2] * py[(s2 + 1) % 4] - px[(s2 + 1) % 4] * py[s2];
+      m->A[id[k]] += 0.5 * a2;
+      /* edge (k, k+1): segment from its midpoint to the centre */
+      const int64_t e = find_edge(m, first, id[k], id[kn]);
+      double nxv = cy - mny, nyv = -(cx - mnx);
+      const int ia = (id[k] < id[kn]) ? k : kn, ib = (ia == k) ? kn : k;
       const double ex = x[ib] - x[ia], ey = y[ib] - y[ia];
       if (nxv * ex + nyv * ey < 0.0) { nxv = -nxv; nyv = -nyv; }
       m->S[2 * e + 0] += nxv;
@@ -395,6 +483,17 @@ orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
   return m;
 }
 
+orc_mesh *orc_mesh_build_pl(int nrings, const int32_t *nx_in, double R) {
+  return build_general(nrings, nx_in, NULL, 0, 0, R);
+}
+
+/* Any grid of parallels: explicit latitudes (or NULL: Gaussian), shift,
+ * quadrilaterals where two consecutive parallels have equal counts. */
+orc_mesh *orc_mesh_build_ex(int nrings, const int32_t *nx_in, const double *lat_in, int shift,
+                            int quads, double R) {
+  return build_general(nrings, nx_in, lat_in, shift, quads, R);
+}
+
 /* Grid O<N>: Section 4.2.3.7, Listing 6 (nx = 20 + 4j up to the equator,
  * mirrored about it). */
 orc_mesh *orc_mesh_build(int N, double R) {
@@ -415,8 +514,12 @@ orc_mesh *orc_mesh_build(int N, double R) {
 /* ------------------------------------------------------------------------ */
 void orc_mesh_sizes(const orc_mesh *m, int64_t *out) {
   out[0] = m->V; out[1] = m->E; out[2] = m->F; out[3] = m->npole;
-  out[4] = m->nrings; out[5] = m->N;
+  out[4] = m->nrings; out[5] = m->N; out[6] = m->Q;
 }
+void orc_mesh_copy_quads(const orc_mesh *m, int32_t *quad) {
+  if (quad && m->Q > 0) memcpy(quad, m->quad, sizeof(int32_t) * 4 * m->Q);
+}
+
 void orc_mesh_copy(const orc_mesh *m, int32_t *nx, int64_t *ring_off,
                    double *lon, double *lat, int32_t *tri, int32_t *edge,
                    double *S, double *A, double *vol, int32_t *pole_edge,
@@ -469,7 +572,23 @@ int orc_set_threads(int n) {
 /*   grad_lon = G_lon / (R cos(lat_i) A_i),   grad_lat = G_lat / (R A_i).    */
 /* f: [V][nlev];  out: [V][nlev][2].                                         */
 /* ------------------------------------------------------------------------ */
+/* The same sums as derivatives in the computational (lon, lat) plane: both
+ * components divided by the dual area A_i,
+ *   (d phi/d lon, d phi/d lat)_i = (G_lon, G_lat) / A_i
+ * (= (R cos(lat_i) grad_lon, R grad_lat) of the physical gradient). */
+static int gradient_sums(const orc_mesh *m, int nlev, const double *f, double *out,
+                         int computational);
+
+int orc_gradient_lonlat(const orc_mesh *m, int nlev, const double *f, double *out) {
+  return gradient_sums(m, nlev, f, out, 1);
+}
+
 int orc_gradient(const orc_mesh *m, int nlev, const double *f, double *out) {
+  return gradient_sums(m, nlev, f, out, 0);
+}
+
+static int gradient_sums(const orc_mesh *m, int nlev, const double *f, double *out,
+                         int computational) {
   if (!m || nlev < 1 || !f || !out) return -1;
   const int64_t V = m->V, E = m->E;
   const int nc = n_chunks(nlev);
@@ -500,8 +619,8 @@ int orc_gradient(const orc_mesh *m, int nlev, const double *f, double *out) {
       }
     }
     for (int64_t i = 0; i < V; ++i) {
-      const double sx = m->R * m->coslat[i] * m->A[i];
-      const double sy = m->R * m->A[i];
+      const double sx = computational ? m->A[i] : m->R * m->coslat[i] * m->A[i];
+      const double sy = computational ? m->A[i] : m->R * m->A[i];
       for (int k = k0; k < k1; ++k) {
         out[(i * nlev + k) * 2 + 0] /= sx;
         out[(i * nlev + k) * 2 + 1] /= sy;
@@ -818,6 +937,7 @@ static int remap_one(const orc_mesh *m, const int64_t *toff, double lon, double 
 
 int orc_remap_weights(const orc_mesh *m, int64_t nt, const double *lon, const double *lat,
                       int32_t *idx, double *w) {
+  if (m->Q > 0 || m->shift) return -3; /* triangles from lon 0 only */
   const int nr = m->nrings;
   int64_t *toff = (int64_t *)malloc(sizeof(int64_t) * nr);
   if (!toff) return -2;

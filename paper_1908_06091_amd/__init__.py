@@ -131,6 +131,40 @@ def mesh_desc_reduced_gaussian(nx, radius: float = 1.0) -> dict:
         L.atlas_mesh_desc_free(p)
 
 
+ATLAS_MESH_SHIFTED, ATLAS_MESH_QUADS = 1, 2
+
+
+def mesh_desc_grid(nx, lat=None, *, shifted=False, quads=False, radius: float = 1.0) -> dict:
+    """The library's host description of any grid of parallels
+    (``atlas_mesh_desc_grid``): nx[j] points on parallel j at latitude lat[j]
+    (radians; None: Gaussian latitudes), optionally shifted half a spacing
+    east, optionally with quadrilaterals between parallels of equal counts.
+    ``lonlat_grid(nlon, nlat)`` gives the regular longitude-latitude grids."""
+    import numpy as _np
+    L = lib()
+    arr = _np.ascontiguousarray(nx, dtype=_np.int32)
+    la = None if lat is None else _np.ascontiguousarray(lat, dtype=_np.float64)
+    flags = (ATLAS_MESH_SHIFTED if shifted else 0) | (ATLAS_MESH_QUADS if quads else 0)
+    p = ctypes.POINTER(MeshDesc)()
+    _check(L.atlas_mesh_desc_grid(len(arr), arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  None if la is None else la.ctypes.data_as(
+                                      ctypes.POINTER(ctypes.c_double)),
+                                  flags, float(radius), ctypes.byref(p)))
+    try:
+        return _abi.desc_to_numpy(p.contents)
+    finally:
+        L.atlas_mesh_desc_free(p)
+
+
+def lonlat_grid(nlon: int, nlat: int):
+    """(nx, lat) of the regular longitude-latitude grid with nlat parallels
+    at lat = pi/2 - (j + 1/2) pi / nlat (none on a pole) and nlon points on
+    each: SLAT<nlon>x<nlat>, or S<nlon>x<nlat> with shifted=True."""
+    import numpy as _np
+    lat = 0.5 * _np.pi - (_np.arange(nlat) + 0.5) * _np.pi / nlat
+    return _np.full(nlat, int(nlon), _np.int32), lat
+
+
 def regular_gaussian_nx(N: int):
     """Points per parallel of F<N> (nx = 4N on each of the 2N parallels)."""
     import numpy as _np
@@ -151,12 +185,19 @@ class Mesh:
     """A mesh resident on the current device (``atlas_mesh_upload``)."""
 
     def __init__(self, N: int | None = None, radius: float = 1.0, *, desc: dict | None = None,
-                 layout: tuple[int, int] | None = None, nx=None):
+                 layout: tuple[int, int] | None = None, nx=None, lat=None, shifted=False,
+                 quads=False):
         """O<N> by default; ``nx`` (points per parallel) gives any reduced
-        Gaussian grid, ``desc`` any mesh description."""
+        Gaussian grid, with ``lat`` any grid of parallels (``shifted``,
+        ``quads`` as in mesh_desc_grid); ``desc`` any mesh description."""
         L = lib()
         self._lib = L
         self._h = ctypes.c_void_p()
+        if desc is None and (lat is not None or shifted or quads):
+            if nx is None:
+                nx = [20 + 4 * j for j in range(N)] + [20 + 4 * j for j in range(N - 1, -1, -1)]
+            desc = mesh_desc_grid(nx, lat, shifted=shifted, quads=quads, radius=radius)
+            N = len(nx) // 2
         if nx is not None and desc is None:
             desc = mesh_desc_reduced_gaussian(nx, radius)
             N = len(nx) // 2
@@ -259,6 +300,17 @@ class Mesh:
         op_ = _out_ptr(out, f, self.nnodes * nlev * 2, "out")
         _check(self._lib.atlas_nabla_gradient(self._h, _dev_ptr(f, "f"), nlev, _dtype_code(f),
                                               op_, _stream(stream)))
+        return out
+
+    def gradient_lonlat(self, f, out=None, stream=None):
+        """(d f/d lon, d f/d lat) in the computational plane, [V][nlev][2]
+        (``atlas_nabla_gradient_lonlat``)."""
+        nlev = self._nlev_scalar(f)
+        if out is None:
+            out = _torch().empty((self.nnodes, nlev, 2), dtype=f.dtype, device=f.device)
+        op_ = _out_ptr(out, f, self.nnodes * nlev * 2, "out")
+        _check(self._lib.atlas_nabla_gradient_lonlat(self._h, _dev_ptr(f, "f"), nlev,
+                                                     _dtype_code(f), op_, _stream(stream)))
         return out
 
     def divergence(self, uv, out=None, stream=None):

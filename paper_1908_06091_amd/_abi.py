@@ -36,6 +36,8 @@ class MeshDesc(ctypes.Structure):
         ("dual_volumes", _dp), ("dual_normals", _dp),
         ("npole_edges", ctypes.c_int64), ("pole_edges", _i32p), ("pole_normals", _dp),
         ("radius", ctypes.c_double),
+        ("ntriangles", ctypes.c_int64), ("triangles", _i32p),
+        ("nquads", ctypes.c_int64), ("quads", _i32p),
     ]
 
 
@@ -121,6 +123,9 @@ SIGNATURES = {
     "atlas_mesh_desc_reduced_gaussian": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                                         ctypes.c_double,
                                                         ctypes.POINTER(ctypes.POINTER(MeshDesc))]),
+    "atlas_mesh_desc_grid": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _dp,
+                                            ctypes.c_int32, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.POINTER(MeshDesc))]),
     "atlas_mesh_desc_free": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
     "atlas_mesh_upload": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
     "atlas_mesh_upload_ex": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Layout),
@@ -131,6 +136,9 @@ SIGNATURES = {
     "atlas_mesh_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MeshInfo)]),
     "atlas_nabla_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "atlas_nabla_gradient_lonlat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
+                                                   ctypes.c_void_p]),
     "atlas_nabla_divergence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                               ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "atlas_nabla_curl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
@@ -234,6 +242,11 @@ def desc_to_numpy(d: MeshDesc) -> dict:
     }
     if d.nrings > 0 and d.ring_off:
         out["ring_off"] = arr(d.ring_off, int(d.nrings) + 1, np.int64)
+    nt, nq = int(d.ntriangles), int(d.nquads)
+    out["triangles"] = (arr(d.triangles, 3 * nt, np.int32).reshape(nt, 3) if nt and d.triangles
+                        else np.zeros((0, 3), np.int32))
+    out["quads"] = (arr(d.quads, 4 * nq, np.int32).reshape(nq, 4) if nq and d.quads
+                    else np.zeros((0, 4), np.int32))
     return out
 
 
@@ -266,4 +279,9 @@ def numpy_to_desc(a: dict):
     d.pole_edges = ptr("pole_edges", np.int32, _i32p)
     d.pole_normals = ptr("pole_normals", np.float64, _dp)
     d.radius = float(a["radius"])
+    for name, n_name, width in (("triangles", "ntriangles", 3), ("quads", "nquads", 4)):
+        el = a.get(name)
+        if el is not None and len(el):
+            setattr(d, name, ptr(name, np.int32, _i32p))
+            setattr(d, n_name, len(np.asarray(el).reshape(-1, width)))
     return d, keep

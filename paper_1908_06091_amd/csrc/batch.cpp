@@ -167,8 +167,10 @@ static std::vector<atlas_launch> candidates(const MeshStore &m, atlas_op op, atl
     add(ATLAS_VARIANT_COLUMN, 256, 4, 0, 0, 0);
     add(ATLAS_VARIANT_COLUMN, 256, 0, 0, 4, 0);
     if (m.d.sweep_ok) {
-      for (int b : {512, 768, 1024}) add(ATLAS_VARIANT_SWEEP, b, 0, 0, 0, 0);
-      add(ATLAS_VARIANT_SWEEP, 768, 0, 0, 0, 2);
+      // wave-specialised (blocks_per_cu 0) and register-staged (1) sweeps
+      for (int b : {768, 1024}) add(ATLAS_VARIANT_SWEEP, b, 0, 0, 0, 0);
+      for (int b : {512, 768, 1024}) add(ATLAS_VARIANT_SWEEP, b, 0, 0, 1, 0);
+      add(ATLAS_VARIANT_SWEEP, 768, 0, 0, 1, 2);
     }
   }
   const int fl = std::max(16, std::min(1024, 4096 / std::max(1, nlev)));

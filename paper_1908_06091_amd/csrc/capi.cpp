@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <cmath>
 #include <mutex>
 #include <new>
 #include <string>
@@ -191,6 +192,52 @@ atlas_status atlas_mesh_desc_reduced_gaussian(int32_t nrings, const int32_t *nx,
   return ATLAS_OK;
 }
 
+atlas_status atlas_mesh_desc_grid(int32_t nrings, const int32_t *nx, const double *lat,
+                                  int32_t flags, double radius, atlas_mesh_desc **out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!nx) return fail(ATLAS_EINVAL, "nx is NULL");
+  if (flags & ~(ATLAS_MESH_SHIFTED | ATLAS_MESH_QUADS)) return fail(ATLAS_EINVAL, "unknown flags");
+  if (nrings < 2 || nrings > 16384) return fail(ATLAS_EINVAL, "nrings must be in [2, 16384]");
+  if (!lat && (nrings & 1)) return fail(ATLAS_EINVAL, "Gaussian latitudes need an even nrings");
+  int64_t total = 0;
+  for (int j = 0; j < nrings; ++j) {
+    if (nx[j] < 4 || nx[j] > (1 << 20)) return fail(ATLAS_EINVAL, "every nx must be in [4, 2^20]");
+    if ((flags & ATLAS_MESH_SHIFTED) && nx[j] != nx[0])
+      return fail(ATLAS_EINVAL, "a shifted grid needs equal counts on all parallels");
+    total += nx[j];
+  }
+  if ((nx[0] & 1) || (nx[nrings - 1] & 1))
+    return fail(ATLAS_EINVAL, "the polar parallels need an even number of points");
+  if (total * 3 >= ((int64_t)1 << 31)) return fail(ATLAS_EINVAL, "grid too large");
+  if (!(radius > 0.0)) return fail(ATLAS_EINVAL, "radius must be positive");
+  std::vector<double> lv;
+  if (lat) {
+    lv.assign(lat, lat + nrings);
+    for (int j = 0; j < nrings; ++j) {
+      if (!std::isfinite(lv[j]) || !(std::fabs(lv[j]) < 0.5 * 3.14159265358979323846))
+        return fail(ATLAS_EINVAL, "latitudes must lie inside (-pi/2, pi/2)");
+      if (j > 0 && !(lv[j] < lv[j - 1]))
+        return fail(ATLAS_EINVAL, "latitudes must decrease strictly");
+    }
+  }
+  HostMesh *h = new (std::nothrow) HostMesh();
+  if (!h) return fail(ATLAS_ENOMEM, "out of host memory");
+  try {
+    build_grid(std::vector<int32_t>(nx, nx + nrings), lat ? &lv : nullptr,
+               (flags & ATLAS_MESH_SHIFTED) != 0, (flags & ATLAS_MESH_QUADS) != 0, radius, *h);
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(ATLAS_ENOMEM, "out of host memory building the mesh");
+  }
+  {
+    std::lock_guard<std::mutex> g(g_desc_mu);
+    g_descs[&h->desc] = h;
+  }
+  *out = &h->desc;
+  return ATLAS_OK;
+}
+
 atlas_status atlas_mesh_desc_free(atlas_mesh_desc *desc) {
   if (!desc) return ATLAS_OK;
   HostMesh *h = nullptr;
@@ -303,6 +350,13 @@ atlas_status atlas_nabla_div_curl(atlas_mesh_t mesh, const void *uv, int32_t nle
   const size_t ob = out_bytes(m, ATLAS_OP_DIVERGENCE, nlev, dtype);
   if (overlap(out_div, ob, out_curl, ob)) return fail(ATLAS_EINVAL, "the two outputs overlap");
   return launch_div_curl(m, dtype, uv, nlev, out_div, out_curl, stream);
+}
+
+atlas_status atlas_nabla_gradient_lonlat(atlas_mesh_t mesh, const void *f, int32_t nlev,
+                                         atlas_dtype dtype, void *out, hipStream_t stream) {
+  const atlas_status st = check_call(mesh, ATLAS_OP_GRADIENT, f, nlev, dtype, out);
+  if (st != ATLAS_OK) return st;
+  return gradient_lonlat(*mesh->store, dtype, f, nlev, out, stream);
 }
 
 atlas_status atlas_nabla_laplacian(atlas_mesh_t mesh, const void *f, int32_t nlev,

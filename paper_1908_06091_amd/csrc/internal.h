@@ -37,12 +37,15 @@ struct HostMesh {
   std::vector<double> dual_volumes, dual_normals;
   std::vector<int32_t> pole_edges;
   std::vector<double> pole_normals;
+  std::vector<int32_t> tri, quad;  // element blocks
   atlas_mesh_desc desc{};
   void fill_desc();
 };
 
 int build_octahedral(int N, double R, HostMesh &h);
 int build_reduced_gaussian(const std::vector<int32_t> &nx, double R, HostMesh &h);
+int build_grid(const std::vector<int32_t> &nx, const std::vector<double> *lat, bool shifted,
+               bool quads, double R, HostMesh &h);
 
 // ------------------------------------------------------ device mesh store
 // All "position" arrays follow the processing order: the nodes re-ordered
@@ -107,6 +110,7 @@ struct DevMesh {
   int32_t l2_pmax = 0;               // most own positions of a tile on one parallel
   const int4 *l2_ggeo = nullptr;     // packed gradient-node records (device-built)
   const int4 *l2_lgeo = nullptr;     // packed own-position records (device-built)
+  const int4 *sgeo = nullptr;        // packed per-position sweep geometry (device-built)
 };
 
 // ------------------------------------------------------------- kernels
@@ -196,6 +200,12 @@ struct MeshStore {
   size_t ws_bytes = 0;
   int serve_refs = 0;
   double geometry_bytes = 0.0;
+  // scales of the derivatives in the computational plane (built on the
+  // first call that needs them)
+  double radius = 1.0;
+  std::mutex comp_mu;
+  bool comp_ready = false;
+  DevMesh dcomp;
   // autotuned launch shapes, keyed by (op, dtype, nlev)
   std::mutex tune_mu;
   std::map<TuneKey, LaunchShape> tuned;
@@ -215,12 +225,18 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
 // True if a Laplacian launched with `sh` runs the fused one-pass form
 // (which needs no workspace) rather than falling back to the two passes.
 bool lapl_fused_runs(const MeshStore &ms, int nlev, atlas_dtype dt, const LaunchShape &sh);
+// (d phi / d lon, d phi / d lat) of a scalar field, [V][nlev][2].
+atlas_status gradient_lonlat(MeshStore &ms, atlas_dtype dt, const void *in, int nlev, void *out,
+                             hipStream_t st);
 // Divergence and curl of one vector field (one read of the field).
 atlas_status launch_div_curl(const MeshStore &ms, atlas_dtype dt, const void *in, int nlev,
                              void *out_div, void *out_curl, hipStream_t st);
 // Packs the fused Laplacian's geometry records of a mesh with a two-ring
 // plan of `ngrec` gradient records (after derive_scales).
 atlas_status pack_lapl_geometry(MeshStore &m, int64_t ngrec);
+// Packs the wave-specialised sweep's per-position geometry (after
+// derive_scales; a mesh with a sweep plan).
+atlas_status pack_sweep_geometry(MeshStore &m);
 // The shape a call with launch `l` (NULL: tuned, else built-in) runs with.
 LaunchShape shape_from(const atlas_launch *l, const MeshStore &m, atlas_op op, int nlev,
                        atlas_dtype dt);

@@ -67,6 +67,18 @@ int build_octahedral(int N, double R, HostMesh &h) {
 // with nx[j] points on parallel j (nx.size() = 2N parallels; every nx >= 4,
 // the two polar parallels even).
 int build_reduced_gaussian(const std::vector<int32_t> &nx_in, double R, HostMesh &h) {
+  return build_grid(nx_in, nullptr, false, false, R, h);
+}
+
+// Any grid of parallels: nx[j] points on parallel j at latitude lat[j]
+// (strictly decreasing inside (-pi/2, pi/2); NULL: the Gaussian latitudes of
+// degree nx.size()).  shifted: every point half a spacing east of the
+// unshifted position (equal counts on all parallels).  quads: a strip
+// between parallels of equal counts becomes a row of quadrilaterals
+// (U_a, L_a, L_a+1, U_a+1) -- the blocked quadrilaterals of Section 4.3 --
+// and the other strips stay triangulated.
+int build_grid(const std::vector<int32_t> &nx_in, const std::vector<double> *lat_in,
+               bool shifted, bool quads, double R, HostMesh &h) {
   const int nr = (int)nx_in.size();
   const int N = nr / 2;
   h.N = N;
@@ -78,16 +90,17 @@ int build_reduced_gaussian(const std::vector<int32_t> &nx_in, double R, HostMesh
   const int64_t V = h.ring_off[nr];
 
   std::vector<double> mu;
-  gaussian_mu(N, mu);
+  if (!lat_in) gaussian_mu(N, mu);
   h.lon.resize(V);
   h.lat.resize(V);
   h.cos_lat.resize(V);
   for (int j = 0; j < nr; ++j) {
-    const double th = std::asin(mu[j]);
+    const double th = lat_in ? (*lat_in)[j] : std::asin(mu[j]);
     const double c = std::cos(th);
     const int64_t o = h.ring_off[j];
     for (int i = 0; i < h.nx[j]; ++i) {
-      h.lon[o + i] = 2.0 * kPi * (double)i / (double)h.nx[j];
+      h.lon[o + i] = shifted ? 2.0 * kPi * ((double)i + 0.5) / (double)h.nx[j]
+                             : 2.0 * kPi * (double)i / (double)h.nx[j];
       h.lat[o + i] = th;
       h.cos_lat[o + i] = c;
     }
@@ -96,11 +109,22 @@ int build_reduced_gaussian(const std::vector<int32_t> &nx_in, double R, HostMesh
   // --- triangles: walk each strip, consuming whichever of the two next
   // points lies further west (exact integer comparison of i/n); ties
   // advance the ring with more points, the lower ring if counts are equal.
-  std::vector<int32_t> tri;
+  std::vector<int32_t> &tri = h.tri;
+  std::vector<int32_t> &quad = h.quad;
+  tri.clear();
+  quad.clear();
   tri.reserve((size_t)3 * (2 * V));
   for (int j = 0; j + 1 < nr; ++j) {
     const int64_t nu = h.nx[j], nl = h.nx[j + 1];
     const int64_t ou = h.ring_off[j], ol = h.ring_off[j + 1];
+    if (quads && nu == nl) {
+      for (int64_t a = 0; a < nu; ++a) {
+        const int32_t q4[4] = {(int32_t)(ou + a), (int32_t)(ol + a),
+                               (int32_t)(ol + (a + 1) % nl), (int32_t)(ou + (a + 1) % nu)};
+        quad.insert(quad.end(), q4, q4 + 4);
+      }
+      continue;
+    }
     int64_t iu = 0, il = 0;
     for (int64_t step = 0; step < nu + nl; ++step) {
       bool take_upper;
@@ -118,24 +142,24 @@ int build_reduced_gaussian(const std::vector<int32_t> &nx_in, double R, HostMesh
     }
   }
   const int64_t F = (int64_t)tri.size() / 3;
+  const int64_t Q = (int64_t)quad.size() / 4;
 
   // --- edges: per node, its higher-numbered neighbours, sorted; reading
   // the nodes in order enumerates the pairs (a < b) lexicographically.
+  // (element sides: every triangle side, then every quadrilateral side)
+  auto for_each_side = [&](auto &&fn) {
+    for (int64_t t = 0; t < F; ++t)
+      for (int k = 0; k < 3; ++k) fn(tri[3 * t + k], tri[3 * t + (k + 1) % 3]);
+    for (int64_t t = 0; t < Q; ++t)
+      for (int k = 0; k < 4; ++k) fn(quad[4 * t + k], quad[4 * t + (k + 1) % 4]);
+  };
   std::vector<int64_t> up_ptr(V + 1, 0);
-  for (int64_t t = 0; t < F; ++t)
-    for (int k = 0; k < 3; ++k) {
-      int32_t p = tri[3 * t + k], q = tri[3 * t + (k + 1) % 3];
-      up_ptr[std::min(p, q) + 1]++;
-    }
+  for_each_side([&](int32_t p, int32_t q) { up_ptr[std::min(p, q) + 1]++; });
   for (int64_t i = 0; i < V; ++i) up_ptr[i + 1] += up_ptr[i];
   std::vector<int32_t> up(up_ptr[V]);
   {
     std::vector<int64_t> fill(up_ptr.begin(), up_ptr.end() - 1);
-    for (int64_t t = 0; t < F; ++t)
-      for (int k = 0; k < 3; ++k) {
-        int32_t p = tri[3 * t + k], q = tri[3 * t + (k + 1) % 3];
-        up[fill[std::min(p, q)]++] = std::max(p, q);
-      }
+    for_each_side([&](int32_t p, int32_t q) { up[fill[std::min(p, q)]++] = std::max(p, q); });
   }
   h.edge2node.clear();
   h.edge2node.reserve((size_t)2 * 3 * V);
@@ -188,6 +212,41 @@ int build_reduced_gaussian(const std::vector<int32_t> &nx_in, double R, HostMesh
       const double sx = gy - 0.5 * (y[p] + y[q]);   // normal of (g - m)
       const double sy = -(gx - 0.5 * (x[p] + x[q]));
       const int from = v[p] < v[q] ? p : q, to = from == p ? q : p;
+      const double dot = sx * (x[to] - x[from]) + sy * (y[to] - y[from]);
+      const double sgn = dot < 0.0 ? -1.0 : 1.0;
+      h.dual_normals[2 * e] += sgn * sx;
+      h.dual_normals[2 * e + 1] += sgn * sy;
+    }
+  }
+  // Quadrilaterals: the same construction about the element centre g (mean
+  // of the four corners): corner k owns the polygon (corner, midpoint
+  // towards k+1, g, midpoint towards k-1), its area by the shoelace
+  // formula; the face on side (k, k+1) is the segment midpoint -> g.
+  for (int64_t t = 0; t < Q; ++t) {
+    const int32_t v[4] = {quad[4 * t], quad[4 * t + 1], quad[4 * t + 2], quad[4 * t + 3]};
+    double x[4], y[4];
+    for (int k = 0; k < 4; ++k) {
+      x[k] = h.lon[v[k]];
+      y[k] = h.lat[v[k]];
+      if (k) {
+        if (x[k] - x[0] > kPi) x[k] -= 2.0 * kPi;
+        else if (x[k] - x[0] < -kPi) x[k] += 2.0 * kPi;
+      }
+    }
+    const double gx = 0.25 * (x[0] + x[1] + x[2] + x[3]);
+    const double gy = 0.25 * (y[0] + y[1] + y[2] + y[3]);
+    for (int k = 0; k < 4; ++k) {
+      const int q = (k + 1) % 4, r = (k + 3) % 4;
+      const double ax = 0.5 * (x[k] + x[q]), ay = 0.5 * (y[k] + y[q]);  // towards k+1
+      const double bx = 0.5 * (x[k] + x[r]), by = 0.5 * (y[k] + y[r]);  // towards k-1
+      const double cxs[4] = {x[k], ax, gx, bx}, cys[4] = {y[k], ay, gy, by};
+      double twice = 0.0;
+      for (int c = 0; c < 4; ++c)
+        twice += cxs[c] * cys[(c + 1) % 4] - cxs[(c + 1) % 4] * cys[c];
+      area[v[k]] += 0.5 * twice;
+      const int64_t e = edge_id(v[k], v[q]);
+      const double sx = gy - ay, sy = -(gx - ax);
+      const int from = v[k] < v[q] ? k : q, to = from == k ? q : k;
       const double dot = sx * (x[to] - x[from]) + sy * (y[to] - y[from]);
       const double sgn = dot < 0.0 ? -1.0 : 1.0;
       h.dual_normals[2 * e] += sgn * sx;
@@ -265,6 +324,10 @@ void HostMesh::fill_desc() {
   desc.pole_edges = pole_edges.data();
   desc.pole_normals = pole_normals.data();
   desc.radius = radius;
+  desc.ntriangles = (int64_t)tri.size() / 3;
+  desc.triangles = tri.empty() ? nullptr : tri.data();
+  desc.nquads = (int64_t)quad.size() / 4;
+  desc.quads = quad.empty() ? nullptr : quad.data();
 }
 
 }  // namespace atlasx

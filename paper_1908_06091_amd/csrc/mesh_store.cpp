@@ -556,6 +556,7 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->d.npole = (int32_t)NP;
   m->d.ntiles = (int32_t)tile_ptr.size() - 1;
   m->nincid = (int64_t)nbr.size() - kIncPad;
+  m->radius = d->radius;
   m->nrings = nrings;
   m->max_degree = maxdeg;
   m->d.maxdeg = maxdeg;
@@ -616,6 +617,10 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
     return st;
   }
   if (l2_ok && (st = pack_lapl_geometry(*m, (int64_t)lp.gnode.size())) != ATLAS_OK) {
+    delete m;
+    return st;
+  }
+  if (sweep_ok && (st = pack_sweep_geometry(*m)) != ATLAS_OK) {
     delete m;
     return st;
   }

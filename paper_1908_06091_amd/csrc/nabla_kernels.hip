@@ -1320,6 +1320,301 @@ __global__ void __launch_bounds__(1024) k_sweepv(DevMesh m, const T *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Wave-specialised sweep.  The same walk down a tile's band as k_sweepv, but
+// the waves of a workgroup split the work: producer waves only move data
+// into LDS, with buffer loads that write LDS directly (no registers, no
+// deposit pass), and consumer waves only compute from LDS and store
+// results.  One vector-memory counter per wave counts loads and stores
+// alike and retires them in order; so a wave that both stored results and
+// later waited for its next loads would wait for those stores too.  Here the
+// consumers never wait on memory (their stores drain while the next
+// parallels are computed) and the producers wait only for their own loads.
+// The producers form two groups that take alternate runs: at step q the
+// group of run q+3 loads its columns and packed geometry into ring slot
+// (q+3) mod 5, and at the end of step q the other group waits for run q+2,
+// which it issued one step earlier -- so every load has two steps to land.
+// The consumers compute the own positions of run q from slots q-1, q, q+1.
+// The roles run separate loops that meet at one workgroup barrier per step.
+// Lane vectors are 16 bytes (FP64: 2 levels of a scalar, 1 of a vector;
+// FP32: 4 of a scalar, 2 of a vector).  Items of a slot are numbered (node
+// of the run) x (lane vector of the chunk), so each load instruction fills
+// 64 consecutive 16-byte LDS words.  The packed normals are halved (exact):
+// the FP64 edge term sS (x_i + x_n)/2 is formed as (sS/2)(x_i + x_n) with the
+// same bits and one multiplication less.
+// ---------------------------------------------------------------------------
+constexpr int kSgeoWords = 14;  // packed sweep geometry per position (16-byte
+                                // words): {node, n, selfslot, 0}, (alpha,
+                                // beta), S[6] / 2, lref[8], ncos[6],
+                                // (cos lat, 0)
+constexpr int kSweepwGroups = 2;     // producer groups (alternate runs)
+constexpr int kSweepwSlots = 5;      // ring slots: runs q-1 .. q+3
+// Waves per producer group: two for the gradient (its loads dominate), one
+// for divergence and curl (their arithmetic wants every consumer wave;
+// measured at O1280, 137 levels).
+template <int OP> constexpr int sweepw_group_waves() { return OP == OP_GRAD ? 2 : 1; }
+
+__device__ __forceinline__ void lds_dma16(const i32x4 &rsrc, void *lds_wave_base, int voff) {
+  __amdgpu_buffer_rsrc_t r;
+  __builtin_memcpy(&r, &rsrc, 16);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(
+      r, (__attribute__((address_space(3))) void *)lds_wave_base, 16, voff, 0, 0, 0);
+}
+
+// The FP64 edge terms with halved normals (bits of Pol<double, *>::add).
+__device__ __forceinline__ void sweep_add_half(Pol<double, OP_GRAD>::St &s, double xn,
+                                               const double2 &Sh, bool pole, double) {
+  const double xe = s.xi + xn;
+  if (!pole) s.gl = s.gl + Sh.x * xe;
+  s.gt = s.gt + Sh.y * xe;
+}
+template <int OP>
+__device__ __forceinline__ void sweep_add_half(typename PolDC64<OP>::St &s, v2d un,
+                                               const double2 &Sh, bool, double cn) {
+  const double an = (OP == OP_DIV) ? un.x : un.y;
+  const double bn = ((OP == OP_DIV) ? un.y : un.x) * cn;
+  const double ae = s.ai + an, be = s.bi + bn;
+  const double f = (OP == OP_DIV) ? Sh.x * ae + Sh.y * be : Sh.x * ae - Sh.y * be;
+  s.acc = s.acc + f;
+}
+
+template <class T, int OP>
+__device__ __forceinline__ void sweep_term(typename Pol<T, OP>::St &s,
+                                           typename Pol<T, OP>::V xn, const double2 &Sh,
+                                           bool pole, double cn) {
+  if constexpr (sizeof(T) == 8) {
+    if constexpr (OP == OP_GRAD) sweep_add_half(s, xn, Sh, pole, cn);
+    else sweep_add_half<OP>(s, xn, Sh, pole, cn);
+  } else {
+    Pol<T, OP>::add(s, xn, make_double2(Sh.x + Sh.x, Sh.y + Sh.y), pole, cn);
+  }
+}
+
+template <class T, int OP, int NV>
+__global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict__ in,
+                                                 T *__restrict__ out, int nlev, int vpc,
+                                                 int ntiles, int per_xcd, int fcap, int gcap) {
+  using P = Pol<T, OP>;
+  using V = typename P::V;
+  using LV = LaneVec<V, NV>;
+  using R = typename LV::raw;
+  using Out = typename P::Out;
+  static_assert(sizeof(R) == 16, "wave-specialised sweep: 16-byte lane vectors");
+  constexpr int GW = P::kVecIn ? kSgeoWords : 10;  // geometry words read per position
+  constexpr int kSweepwGroupWaves = sweepw_group_waves<OP>();
+  constexpr int NPW = kSweepwGroups * kSweepwGroupWaves;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R *fbuf = reinterpret_cast<R *>(smem_raw);                           // [5][fcap]
+  i32x4 *gbuf = reinterpret_cast<i32x4 *>(fbuf + kSweepwSlots * fcap);  // [5][gcap]
+  const int u = xcd_tile(blockIdx.x, per_xcd);
+  const int nvec = (nlev + NV - 1) / NV;
+  const int nchunk = (nvec + vpc - 1) / vpc;
+  const int tile = u / nchunk;
+  const int c = u - tile * nchunk;
+  if (tile >= ntiles) return;
+  const int v0 = c * vpc;
+  if (v0 >= nvec) return;
+  const int nvc = min(vpc, nvec - v0);  // lane vectors in this chunk
+  const int s0 = cst(m.tile_seg)[tile];
+  const int nseg = cst(m.tile_seg)[tile + 1] - s0;
+  const size_t L = (size_t)nlev;
+  const uint32_t col_bytes = (uint32_t)(L * sizeof(V));
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int *segi = reinterpret_cast<const int *>(m.seg);
+  const int *segp = reinterpret_cast<const int *>(m.seg_pos);
+  auto run_lo = [&](int q) { return cst(segp)[2 * (s0 + q)]; };
+  auto run_hi = [&](int q) { return cst(segp)[2 * (s0 + q) + 1]; };
+  // first and last parallel with positions of this tile
+  int qa = nseg, qb = -1;
+  for (int q = 0; q < nseg; ++q) {
+    if (run_hi(q) > run_lo(q)) {
+      qa = min(qa, q);
+      qb = q;
+    }
+  }
+  if (qb < 0) return;
+
+  if (wave < NPW) {
+    // ---- producers: group grp loads the runs of its parity --------------
+    const int grp = wave / kSweepwGroupWaves, gwave = wave - grp * kSweepwGroupWaves;
+    const V *vin = reinterpret_cast<const V *>(in);
+    // columns and geometry of run q into ring slot q mod 5, the waves of
+    // the calling group (or, with gw_n = NPW, all producers) sharing the
+    // load instructions
+    auto load = [&](int q, int w, int nwv) {
+      const int sl = q % kSweepwSlots;
+      {
+        const int rb = cst(segi)[4 * (s0 + q)], nx = cst(segi)[4 * (s0 + q) + 1];
+        const int lo = cst(segi)[4 * (s0 + q) + 2], len = cst(segi)[4 * (s0 + q) + 3];
+        const i32x4 rs = make_rsrc(vin + (size_t)rb * L, (uint32_t)nx * col_bytes);
+        const int nitems = len * nvc;
+        R *slot = fbuf + sl * fcap;
+        for (int b = w; b * 64 < nitems; b += nwv) {
+          const int i = b * 64 + lane;
+          int off = kBufOff;
+          if (i < nitems) {
+            const int t = i / nvc, k = i - t * nvc;
+            int ii = lo + t;
+            if (ii >= nx) ii -= nx;
+            off = ii * (int)col_bytes + min(NV * (v0 + k), nlev - NV) * (int)sizeof(V);
+          }
+          lds_dma16(rs, slot + b * 64, off);
+        }
+      }
+      {
+        const int plo = run_lo(q), n = run_hi(q) - plo;
+        const i32x4 rs = make_rsrc(m.sgeo + (size_t)plo * kSgeoWords,
+                                   (uint32_t)n * kSgeoWords * 16u);
+        const int nitems = n * GW;
+        i32x4 *slot = gbuf + sl * gcap;
+        for (int b = w; b * 64 < nitems; b += nwv) {
+          const int i = b * 64 + lane;
+          int off = kBufOff;
+          if (i < nitems) {
+            const int t = i / GW, wd = i - t * GW;
+            off = (t * kSgeoWords + wd) * 16;
+          }
+          lds_dma16(rs, slot + b * 64, off);
+        }
+      }
+    };
+    // prologue: runs qa-1 .. qa+1 by every producer (waited), run qa+2 by
+    // its group (waited at the end of step qa)
+    for (int q = max(0, qa - 1); q <= min(nseg - 1, qa + 1); ++q) load(q, wave, NPW);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (qa + 2 < nseg && ((qa + 2) & 1) == grp) load(qa + 2, gwave, kSweepwGroupWaves);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    for (int q = qa; q <= qb; ++q) {
+      if (q + 3 < nseg && ((q + 3) & 1) == grp) load(q + 3, gwave, kSweepwGroupWaves);
+      // run q+2 (issued one step ago by the group of its parity) is in LDS
+      // before step q+1 reads it
+      if (((q + 2) & 1) == grp) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    }
+    // loads of runs past qb + 2 are never read; let them land before exit
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    return;
+  }
+
+  // ---- consumers ----------------------------------------------------------
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  const int cw = wave - NPW, ncw = nw - NPW;
+  const int kc = min(lane, nvc - 1);  // lanes past the chunk read a valid entry
+  const int s_l = min(NV * (v0 + kc), nlev - NV);
+  const bool lane_on = lane < nvc;
+  int sq = qa % kSweepwSlots;           // slot of run q
+  for (int q = qa; q <= qb; ++q) {
+    const int plo = run_lo(q), phi = run_hi(q);
+    const int sm = sq == 0 ? kSweepwSlots - 1 : sq - 1;  // slot of run q-1
+    const int sp = sq == kSweepwSlots - 1 ? 0 : sq + 1;  // slot of run q+1
+    const R *fq = fbuf + sq * fcap;
+    const i32x4 *gq = gbuf + sq * gcap;
+    for (int p = plo + cw; p < phi; p += ncw) {
+      const i32x4 *g = gq + (p - plo) * GW;
+      const i32x4 w0 = g[0], w1 = g[1];
+      const int node = w0.x, n = w0.y, selfslot = w0.z;
+      double al, be;
+      {
+        const int a2[2] = {w1.x, w1.y}, b2[2] = {w1.z, w1.w};
+        __builtin_memcpy(&al, a2, 8);
+        __builtin_memcpy(&be, b2, 8);
+      }
+      if (!P::kVecOut) be = 0.0;
+      constexpr int G = 6;
+      double2 Sh[G];
+      int lr[8];
+      double cn[G];
+      double ci = 0.0;
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const i32x4 v = g[2 + j];
+        __builtin_memcpy(&Sh[j], &v, 16);
+      }
+      {
+        const i32x4 a = g[8], b = g[9];
+        lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
+        lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
+      }
+      if constexpr (P::kVecIn) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const i32x4 v = g[10 + k];
+          __builtin_memcpy(&cn[2 * k], &v, 16);
+        }
+        const i32x4 v = g[13];
+        const int cc[2] = {v.x, v.y};
+        __builtin_memcpy(&ci, cc, 8);
+      } else {
+#pragma unroll
+        for (int j = 0; j < G; ++j) cn[j] = 0.0;
+      }
+      typename P::St st[NV];
+      {
+        const R xi = fq[selfslot * nvc + kc];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P::init(st[v], LV::get(xi, v), ci);
+      }
+      R xn[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int l = lr[j] & ~kLrefPole;
+        const int dq = (l >> 16) & 3;  // 0: run q-1, 1: run q, 2: run q+1
+        const int sl = dq == 0 ? sm : (dq == 1 ? sq : sp);
+        xn[j] = fbuf[sl * fcap + (l & 0xffff) * nvc + kc];
+      }
+      double cx = 0.0, cy = 0.0;  // closure sums (FP32 forms): full normals
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const bool pole = (lr[j] & kLrefPole) != 0;
+        const double2 S2 = make_double2(Sh[j].x + Sh[j].x, Sh[j].y + Sh[j].y);
+        if (j < kMinRow) {  // present in every row, never the pole edge
+          if constexpr (sizeof(T) == 4) closure_add<P::kOp>(cx, cy, S2, false);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sweep_term<T, OP>(st[v], LV::get(xn[j], v), Sh[j], false, cn[j]);
+          continue;
+        }
+        const bool use = j < n && !(P::kVecIn && pole);
+        if constexpr (sizeof(T) == 4) {
+          double tx = cx, ty = cy;
+          closure_add<P::kOp>(tx, ty, S2, pole);
+          cx = use ? tx : cx;
+          cy = use ? ty : cy;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          typename P::St tt = st[v];
+          sweep_term<T, OP>(tt, LV::get(xn[j], v), Sh[j], pole, cn[j]);
+          P::keep(st[v], tt, use);
+        }
+      }
+      const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
+                                 (uint32_t)(L * sizeof(Out)));
+      constexpr int W = NV * (int)sizeof(Out) / 4;
+      int wd[W];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const Out r = P::result(st[v], al, be, cx, cy, ci);
+        __builtin_memcpy(&wd[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
+      }
+      const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
+      buf_store_words<W>(wd, ro, ob);
+    }
+    // this step's LDS reads are done before the producers refill a slot
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    sq = sp;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused Laplacian: one pass over the two-ring plan.  A workgroup owns one
 // tile and one chunk of lane vectors and walks the tile's window of
 // parallels.  At step q it forms the gradient at every node of the g-run of
@@ -1791,6 +2086,34 @@ __global__ void k_pack_lgeo(DevMesh m, i32x4 *__restrict__ dst) {
   __builtin_memcpy(&o[10], m.ncos + pr.r0, 48);
 }
 
+// Packs the wave-specialised sweep's per-position geometry (after the
+// scales are derived): kSgeoWords 16-byte words per position, in position
+// order, normals halved.  Entries past a row are neutral: zero normals, the
+// position's own LDS slot as reference, cos(lat) 1.
+__global__ void k_pack_sgeo(DevMesh m, i32x4 *__restrict__ dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m.V) return;
+  const PosRec pr = m.pos[p];
+  const int n = pr.r1 - pr.r0;
+  i32x4 *o = dst + (size_t)p * kSgeoWords;
+  o[0] = i32x4{pr.node, n, pr.selfslot, 0};
+  const double ab[2] = {pr.alpha, pr.beta};
+  __builtin_memcpy(&o[1], ab, 16);
+  for (int j = 0; j < 6; ++j) {  // halved normals (exact)
+    const double2 v = j < n ? make_double2(0.5 * m.S[pr.r0 + j].x, 0.5 * m.S[pr.r0 + j].y)
+                            : make_double2(0.0, 0.0);
+    __builtin_memcpy(&o[2 + j], &v, 16);
+  }
+  int lr[8];
+  for (int j = 0; j < 8; ++j) lr[j] = j < n ? m.lref[pr.r0 + j] : ((1 << 16) | pr.selfslot);
+  __builtin_memcpy(&o[8], lr, 32);
+  double cn[6];
+  for (int j = 0; j < 6; ++j) cn[j] = j < n ? m.ncos[pr.r0 + j] : 1.0;
+  __builtin_memcpy(&o[10], cn, 48);
+  const double c2[2] = {m.coslat[pr.node], 0.0};
+  __builtin_memcpy(&o[13], c2, 16);
+}
+
 template <class T, int OP>
 __global__ void __launch_bounds__(1024) k_flat(DevMesh m, const T *__restrict__ in,
                                                T *__restrict__ out, int nlev, int npb,
@@ -2166,6 +2489,20 @@ atlas_status pack_lapl_geometry(MeshStore &m, int64_t ngrec) {
   return ATLAS_OK;
 }
 
+atlas_status pack_sweep_geometry(MeshStore &m) {
+  void *g = nullptr;
+  const size_t gb = std::max<size_t>(16, (size_t)m.d.V * kSgeoWords * 16);
+  if (hipMalloc(&g, gb) != hipSuccess) return fail(ATLAS_ENOMEM, "hipMalloc of mesh store failed");
+  m.allocations.push_back(g);
+  m.bytes += gb;
+  if (m.d.V > 0)
+    hipLaunchKernelGGL(k_pack_sgeo, dim3((m.d.V + 255) / 256), dim3(256), 0, 0, m.d,
+                       static_cast<i32x4 *>(g));
+  ATLASX_HIP(hipGetLastError());
+  m.d.sgeo = static_cast<const int4 *>(g);
+  return ATLAS_OK;
+}
+
 atlas_status derive_scales(MeshStore &m, const double *vol_by_pos, const double *cos_by_pos,
                            double radius) {
   const int V = m.d.V;
@@ -2190,16 +2527,17 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
 // measurements at O1280, 137 levels.  Long columns: the column form over
 // blocks of 16 consecutive positions (a run of one parallel, so the
 // neighbour columns of consecutive blocks overlap in L2) with the automatic
-// lane-vector width, except: the FP64 gradient runs the level-vector sweep
-// (768 threads), the FP32 gradient one level per lane (its compensated sums
-// keep every lane busy that way).  The Laplacian takes each pass's own
-// shape.  Short columns (measured at O320 and O1280, 1 to 47 levels, within
-// 1.3x of the best candidate everywhere, 2-4x faster than the flat form over
-// the mesh's tiles): below 24 levels the flat form over blocks of 64
-// positions (512 threads); from 24 levels the column form over blocks of 16
-// positions, one level per lane (FP64 divergence and curl: the automatic
-// lane-vector width), and on meshes of many tiles the level-vector sweep for
-// the FP32 gradient (up to 79 levels).
+// lane-vector width, except: the FP64 gradient runs the wave-specialised
+// sweep (1024 threads), the FP32 gradient one level per lane (its
+// compensated sums keep every lane busy that way).  The Laplacian takes each
+// pass's own shape.  Short columns (measured at O320 and O1280, 1 to 47
+// levels, within 1.3x of the best candidate everywhere, 2-4x faster than the
+// flat form over the mesh's tiles): below 24 levels the flat form over
+// blocks of 64 positions (512 threads); from 24 levels the column form over
+// blocks of 16 positions, one level per lane (FP64 divergence and curl: the
+// automatic lane-vector width), and on meshes of many tiles the
+// register-staged sweep for the FP32 gradient (up to 79 levels) and the
+// wave-specialised sweep for the FP64 divergence and curl (below 48).
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   LaunchShape s;
   s.variant = nlev >= 24 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
@@ -2208,6 +2546,8 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   s.level_vec = 0;
   const bool sweep_fits = m.d.sweep_ok && m.d.ntiles >= kSweepMinTiles &&
                           max(1, m.d.segmax) * kGeoWords <= 768;
+  // the wave-specialised sweep needs the packed geometry and rows of 4..6
+  const bool sweepw_fits = sweep_fits && m.d.sgeo && m.d.maxdeg <= 6 && m.d.mindeg >= kMinRow;
   if (op == ATLAS_OP_LAPLACIAN) {
     // FP64 on large meshes: the fused one-pass form (it moves a third of the
     // two passes' field bytes; in FP32 the two passes are still faster)
@@ -2226,8 +2566,17 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   // band's parallels in turn: only a mesh of many tiles fills the chip
   if (nlev < 48) {
     if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT && sweep_fits) {
+      // register-staged sweep: it keeps one level per lane at these lengths
+      // (37 levels at O1280: 1.9 ms against 3.6 ms for 16-byte lanes)
       s.variant = ATLAS_VARIANT_SWEEP;
       s.block = 768;
+      s.nodes_per_block = 0;
+      s.blocks_per_cu = 1;
+    } else if (dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL) &&
+               sweepw_fits) {
+      // wave-specialised sweep (37 levels at O1280: 2.37 ms against 2.91 ms)
+      s.variant = ATLAS_VARIANT_SWEEP;
+      s.block = 1024;
       s.nodes_per_block = 0;
     } else if (!(dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL))) {
       s.level_vec = 1;
@@ -2236,20 +2585,26 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   }
   if (dt == ATLAS_F32 && op == ATLAS_OP_GRADIENT) {
     s.level_vec = 1;
-    // up to ~80 levels the sweep's single read of each column wins over the
-    // compensated sums' lane work (64 levels: 2.08 ms against 2.52 ms at
-    // O1280); beyond, one level per lane (91 levels: 3.02 against 3.30 ms)
+    // up to ~80 levels the register-staged sweep's single read of each
+    // column wins over the compensated sums' lane work (64 levels: 2.1 ms
+    // against 2.5 ms at O1280); beyond, one level per lane (91 levels: 3.02
+    // against 3.30 ms)
     if (nlev < 80 && sweep_fits) {
       s.variant = ATLAS_VARIANT_SWEEP;
       s.block = 768;
       s.nodes_per_block = 0;
       s.level_vec = 0;
+      s.blocks_per_cu = 1;
     }
   }
   if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && sweep_fits) {
+    // wave-specialised sweep, 1024 threads (137 levels at O1280: 5.8 ms
+    // against 6.2 ms for the register-staged sweep); without the packed
+    // geometry the register-staged sweep on 768 threads
     s.variant = ATLAS_VARIANT_SWEEP;
-    s.block = 768;
+    s.block = sweepw_fits ? 1024 : 768;
     s.nodes_per_block = 0;
+    s.blocks_per_cu = sweepw_fits ? 0 : 1;
   }
   return s;
 }
@@ -2279,8 +2634,9 @@ static int sweep_chunk(int nlev, int want) {
 
 template <class T, int OP>
 static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *out, void *ws,
-                                 const LaunchShape &sh, hipStream_t st) {
-  const DevMesh &m = ms.d;
+                                 const LaunchShape &sh, hipStream_t st,
+                                 const DevMesh *dm = nullptr) {
+  const DevMesh &m = dm ? *dm : ms.d;
   const int ntiles = sh.nodes_per_block > 0 ? (m.V + sh.nodes_per_block - 1) / sh.nodes_per_block
                                             : m.ntiles;
   const int per_xcd = (ntiles + 7) / 8;
@@ -2376,6 +2732,43 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       // the level-vector sweep stages each position's geometry with one
       // thread per 16-byte word: it needs a block of segmax * kGeoWords
       // threads, else the one-level-per-lane sweep runs (same results)
+      // wave-specialised sweep (blocks_per_cu == 0): 16-byte lane vectors
+      constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP>::V);
+      if (sh.blocks_per_cu == 0 && m.sgeo && (sh.level_vec == 0 || sh.level_vec == nv16) &&
+          nlev >= nv16 && m.maxdeg <= 6 && m.mindeg >= kMinRow && sh.block >= 512 &&
+          sh.block % 64 == 0) {
+        const int nvec = (nlev + nv16 - 1) / nv16;
+        int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + nv16 - 1) / nv16) : 64;
+        vpc = min(vpc, nvec);
+        {
+          const int nchunk = (nvec + vpc - 1) / vpc;
+          vpc = (nvec + nchunk - 1) / nchunk;
+        }
+        const int seg = max(1, m.segmax);
+        constexpr int gw = Pol<T, OP>::kVecIn ? kSgeoWords : 10;
+        const int gcap = (seg * gw + 63) / 64 * 64;
+        auto fcap_of = [&](int v) { return (seg * v + 63) / 64 * 64; };
+        // more chunks (each an even share of the lane vectors) until the
+        // five slots fit in LDS
+        for (int nch = (nvec + vpc - 1) / vpc;
+             vpc > 1 && (size_t)kSweepwSlots * 16 * (fcap_of(vpc) + gcap) > kMaxLds;) {
+          ++nch;
+          vpc = (nvec + nch - 1) / nch;
+        }
+        const size_t lds = (size_t)kSweepwSlots * 16 * (fcap_of(vpc) + gcap);
+        if (lds > kMaxLds) return fail(ATLAS_EINVAL, "sweep tile too large for LDS");
+        const int nchunk = (nvec + vpc - 1) / vpc;
+        const int units = m.ntiles * nchunk;
+        const int per = (units + 7) / 8;
+        void (*kern)(DevMesh, const T *, T *, int, int, int, int, int, int) = nullptr;
+        if constexpr (lane_vec_ok<T, OP, nv16>()) kern = k_sweepw<T, OP, nv16>;
+        if (!kern) return fail(ATLAS_EINVAL, "wave-specialised sweep not available");
+        ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(per * 8), block, lds, st, m, in, out, nlev, vpc, m.ntiles,
+                           per, fcap_of(vpc), gcap);
+        break;
+      }
       int nv = sh.level_vec == 1 ? 0
                                  : auto_level_vec<T, OP>(nlev, m.maxdeg, m.mindeg, sh.level_vec);
       if (sh.block < max(1, m.segmax) * kGeoWords) nv = 0;
@@ -2621,6 +3014,70 @@ atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *ou
   ATLASX_HIP(hipGetLastError());
   *ran = true;
   return ATLAS_OK;
+}
+
+// Scales of the derivatives in the computational plane: d/dlon = R cos(lat)
+// times the zonal component, d/dlat = R times the meridional one, i.e. both
+// sums over the node's edges divided by its (lon, lat) dual area
+// A_i = V_i / (R^2 cos lat_i): alpha = beta = R beta_i.
+__global__ void k_comp_scales(int V, double R, const PosRec *__restrict__ pos,
+                              double *__restrict__ alpha, double *__restrict__ beta,
+                              PosRec *__restrict__ pos_c) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < V) {
+    PosRec r = pos[p];
+    const double s = R * r.beta;
+    r.alpha = s;
+    r.beta = s;
+    alpha[p] = s;
+    beta[p] = s;
+    pos_c[p] = r;
+  }
+}
+
+atlas_status gradient_lonlat(MeshStore &ms, atlas_dtype dt, const void *in, int nlev, void *out,
+                             hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> g(ms.comp_mu);
+    if (!ms.comp_ready) {
+      const int V = ms.d.V;
+      void *p = nullptr, *a = nullptr, *b = nullptr;
+      if (hipMalloc(&p, sizeof(PosRec) * (size_t)V) != hipSuccess)
+        return fail(ATLAS_ENOMEM, "derivative scales");
+      ms.allocations.push_back(p);
+      if (hipMalloc(&a, sizeof(double) * (size_t)V) != hipSuccess)
+        return fail(ATLAS_ENOMEM, "derivative scales");
+      ms.allocations.push_back(a);
+      if (hipMalloc(&b, sizeof(double) * (size_t)V) != hipSuccess)
+        return fail(ATLAS_ENOMEM, "derivative scales");
+      ms.allocations.push_back(b);
+      ms.bytes += (sizeof(PosRec) + 16) * (size_t)V;
+      hipLaunchKernelGGL(k_comp_scales, dim3((V + 255) / 256), dim3(256), 0, 0, V, ms.radius,
+                         ms.d.pos, static_cast<double *>(a), static_cast<double *>(b),
+                         static_cast<PosRec *>(p));
+      ATLASX_HIP(hipGetLastError());
+      ATLASX_HIP(hipDeviceSynchronize());
+      ms.dcomp = ms.d;
+      ms.dcomp.pos = static_cast<const PosRec *>(p);
+      ms.dcomp.alpha = static_cast<const double *>(a);
+      ms.dcomp.beta = static_cast<const double *>(b);
+      ms.dcomp.sgeo = nullptr;  // packed geometry holds the physical scales
+      ms.dcomp.l2_ok = 0;
+      ms.comp_ready = true;
+    }
+  }
+  // the built-in gradient shape, except the wave-specialised sweep (its
+  // packed geometry carries the physical scales): the register-staged one
+  LaunchShape sh = default_shape(ms, ATLAS_OP_GRADIENT, nlev, dt);
+  if (sh.variant == ATLAS_VARIANT_SWEEP) {
+    sh.blocks_per_cu = 1;
+    sh.block = 768;
+  }
+  if (dt == ATLAS_F64)
+    return launch_typed<double, OP_GRAD>(ms, static_cast<const double *>(in), nlev,
+                                         static_cast<double *>(out), nullptr, sh, st, &ms.dcomp);
+  return launch_typed<float, OP_GRAD>(ms, static_cast<const float *>(in), nlev,
+                                      static_cast<float *>(out), nullptr, sh, st, &ms.dcomp);
 }
 
 atlas_status launch_op(const MeshStore &ms, atlas_op op, atlas_dtype dt, const void *in,

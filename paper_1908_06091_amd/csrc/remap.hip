@@ -11,10 +11,10 @@
 //    one whose smallest barycentric coordinate is largest (the first such
 //    in strip order), giving one 48-byte record per target;
 //  * apply (the hot path): an HBM-bound gather, three source rows per
-//    target row; one thread per (target, column) element so every lane is
-//    busy for any column count, and workgroups mapped to XCDs in contiguous
-//    runs of targets so neighbouring targets, which share source rows, share
-//    an L2.
+//    target row; short rows (under 64 columns) take one thread per (target,
+//    column) element so every lane is busy, long rows one wavefront per row;
+//    workgroups are mapped to XCDs in contiguous runs of targets so
+//    neighbouring targets, which share source rows, share an L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -212,6 +212,44 @@ __global__ void __launch_bounds__(kApplyBlock)
   out[e] = (T)s;
 }
 
+// Long rows (ncol >= 64): one wavefront per target row, lanes over its
+// columns, four column blocks of 64 in flight per lane; the record is read
+// once per row with scalar loads.  Same arithmetic per element as the flat
+// form, so the same bits.
+#define ATLASX_RCST __attribute__((address_space(4)))
+template <class T>
+__global__ void __launch_bounds__(kApplyBlock)
+    k_remap_rows(const RemapRec *__restrict__ rec, const T *__restrict__ in, int32_t ncol,
+                 int64_t nt, int64_t per_xcd, T *__restrict__ out) {
+  constexpr int kWaves = kApplyBlock / 64, kU = 4;
+  const int64_t g = blockIdx.x;
+  const int64_t lb = (g % kXcds) * per_xcd + g / kXcds;
+  const int64_t t = lb * kWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (t >= nt) return;
+  const int lane = threadIdx.x & 63;
+  const ATLASX_RCST RemapRec *r = (const ATLASX_RCST RemapRec *)(rec + t);
+  const int32_t i0 = r->i[0], i1 = r->i[1], i2 = r->i[2];
+  const double w0 = r->w[0], w1 = r->w[1], w2 = r->w[2];
+  const T *a = in + (int64_t)i0 * ncol, *b = in + (int64_t)i1 * ncol, *c = in + (int64_t)i2 * ncol;
+  T *o = out + t * ncol;
+  for (int c0 = 0; c0 < ncol; c0 += 64 * kU) {
+    double va[kU], vb[kU], vc[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = c0 + 64 * u + lane;
+      const bool on = k < ncol;
+      va[u] = on ? (double)a[k] : 0.0;
+      vb[u] = on ? (double)b[k] : 0.0;
+      vc[u] = on ? (double)c[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = c0 + 64 * u + lane;
+      if (k < ncol) o[k] = (T)(w0 * va[u] + w1 * vb[u] + w2 * vc[u]);
+    }
+  }
+}
+
 atlas_status check_targets(int64_t nt, const double *lon, const double *lat) {
   for (int64_t t = 0; t < nt; ++t) {
     if (!std::isfinite(lon[t]) || !std::isfinite(lat[t]))
@@ -275,6 +313,22 @@ atlas_status build_plan(const MeshStore &src, const double *tlon, const double *
 
 atlas_status remap_launch(const RemapPlan &p, const void *in, int32_t ncol, atlas_dtype dt,
                           void *out, hipStream_t st) {
+  if (ncol >= 64) {
+    const int64_t nblk = (p.nt + kApplyBlock / 64 - 1) / (kApplyBlock / 64);
+    const int64_t per_xcd = (nblk + kXcds - 1) / kXcds;
+    const int64_t grid = per_xcd * kXcds;
+    if (grid >= ((int64_t)1 << 31)) return fail(ATLAS_EINVAL, "field too large");
+    if (dt == ATLAS_F64)
+      hipLaunchKernelGGL(k_remap_rows<double>, dim3((unsigned)grid), dim3(kApplyBlock), 0, st,
+                         p.rec, static_cast<const double *>(in), ncol, p.nt, per_xcd,
+                         static_cast<double *>(out));
+    else
+      hipLaunchKernelGGL(k_remap_rows<float>, dim3((unsigned)grid), dim3(kApplyBlock), 0, st,
+                         p.rec, static_cast<const float *>(in), ncol, p.nt, per_xcd,
+                         static_cast<float *>(out));
+    ATLASX_HIP(hipGetLastError());
+    return ATLAS_OK;
+  }
   const int64_t nelem = p.nt * (int64_t)ncol;
   const int64_t nblk = (nelem + kApplyBlock - 1) / kApplyBlock;
   const int64_t per_xcd = (nblk + kXcds - 1) / kXcds;

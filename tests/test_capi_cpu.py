@@ -121,3 +121,42 @@ def test_host_reduced_gaussian_rejects_bad_grids(P):
     r = P.mesh_desc_reduced_gaussian(np.array([20, 24, 28, 28, 24, 20], np.int32))
     for k in ("edge2node", "lon", "lat", "dual_normals", "dual_volumes", "pole_edges"):
         np.testing.assert_array_equal(o[k], r[k])
+
+
+@pytest.mark.parametrize("case", ["SLAT16x8", "S12x6", "O6q", "F4q", "R3q"])
+def test_host_grids_with_quadrilaterals_match_oracle(P, case):
+    """Regular longitude-latitude grids (latitude-shifted and shifted) and
+    Gaussian grids meshed with quadrilaterals where two parallels have equal
+    counts: the library's host description (element blocks included)
+    against the oracle's, topology bit for bit."""
+    if case.startswith(("SLAT", "S")):
+        shifted = not case.startswith("SLAT")
+        nlon, nlat = (16, 8) if case == "SLAT16x8" else (12, 6)
+        nx, lat = P.lonlat_grid(nlon, nlat)
+        d = P.mesh_desc_grid(nx, lat, shifted=shifted, quads=True)
+        m = oracle.Mesh(nx=nx, lat=lat, shift=shifted, quads=True)
+    else:
+        nx = {"O6q": np.array([20 + 4 * j for j in range(6)] + [20 + 4 * j for j in range(5, -1, -1)]),
+              "F4q": np.full(8, 16), "R3q": np.array([6, 9, 9, 13, 10, 8])}[case].astype(np.int32)
+        d = P.mesh_desc_grid(nx, quads=True)
+        m = oracle.Mesh(nx=nx, quads=True)
+    np.testing.assert_array_equal(d["edge2node"], m.edge)
+    np.testing.assert_array_equal(d["triangles"], m.tri)
+    np.testing.assert_array_equal(d["quads"], m.quad)
+    np.testing.assert_array_equal(d["pole_edges"], m.pole_edge)
+    np.testing.assert_array_equal(d["lon"], m.lon)
+    np.testing.assert_allclose(d["lat"], m.lat, rtol=0, atol=4e-16)
+    np.testing.assert_allclose(d["dual_normals"], m.S, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(d["dual_volumes"], m.vol, rtol=1e-13)
+    np.testing.assert_array_equal(d["pole_normals"], m.pole_normal)
+    assert len(m.quad) > 0
+
+
+def test_host_grid_arguments_refused(P):
+    nx = np.full(4, 8, np.int32)
+    for lat in (np.array([1.0, 0.5, 0.5, -1.0]), np.array([1.6, 0.5, 0.0, -1.0]),
+                np.array([np.nan, 0.5, 0.0, -1.0])):
+        with pytest.raises(P.AtlasError):
+            P.mesh_desc_grid(nx, lat)
+    with pytest.raises(P.AtlasError):  # shifted needs equal counts
+        P.mesh_desc_grid(np.array([8, 12, 12, 8], np.int32), shifted=True)

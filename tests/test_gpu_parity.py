@@ -98,6 +98,11 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))      # lane vectors
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 2))
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 3))
+            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 4))
+            # register-staged sweep (blocks_per_cu = 1) beside the
+            # wave-specialised one (blocks_per_cu = 0)
+            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 1))
+            shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 1, 2))
             if block <= 512:
                 shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 1))  # one level per lane
     for kc in (1, 7, 64):
@@ -281,3 +286,21 @@ def test_parity_long_columns(P, nlev, op, dtype):
         torch.cuda.synchronize()
         assert torch.equal(d, got)
         assert torch.equal(c, _run(P, gm, "curl", x))
+
+
+@pytest.mark.parametrize("N", [16, 48])
+@pytest.mark.parametrize("nlev", [1, 7, 137])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gradient_lonlat_matches_oracle(P, N, nlev, dtype):
+    """d/dlon and d/dlat (atlas_nabla_gradient_lonlat) against the oracle's
+    computational-plane derivatives."""
+    import oracle
+    om = oracle.Mesh(N)
+    gm = _gpu_mesh(P, N)
+    f, _ = _inputs(N, nlev)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    x = torch.from_numpy(np.ascontiguousarray(f)).to(device="cuda", dtype=tdt)
+    got = gm.gradient_lonlat(x).double().cpu().numpy()
+    ref = om.gradient_lonlat(x.double().cpu().numpy(), nlev)
+    emax, _ = normwise_error(got, ref)
+    assert emax <= TOL[dtype], emax

@@ -217,3 +217,29 @@ def test_second_order_convergence_away_from_seams():
     assert np.all(order[:, 4:] >= 1.7), order
     assert np.all(order[-1] >= 1.85), order
     # on the seams themselves the scheme is only first order (reported)
+
+
+@pytest.mark.parametrize("N", [8, 24])
+def test_computational_derivatives(N):
+    """d/dlon and d/dlat (the computational-plane derivatives the first
+    configuration compares): exact on lat and lon at interior nodes (off
+    the seam for lon), and equal to (R cos(lat) grad_lon, R grad_lat) of the
+    physical gradient for any field."""
+    R = 3.0
+    m = oracle.Mesh(N, R=R)
+    ins = np.ones(m.V, bool)
+    ins[:m.nx[0]] = False
+    ins[m.V - m.nx[-1]:] = False
+    d = m.gradient_lonlat(m.lat.copy(), 1)[:, 0, :]
+    assert np.abs(d[ins, 0]).max() <= 1e-12 and np.abs(d[ins, 1] - 1.0).max() <= 1e-12
+    seam = np.zeros(m.V, bool)
+    jump = np.abs(m.lon[m.edge[:, 0]] - m.lon[m.edge[:, 1]]) > np.pi
+    seam[m.edge[jump, 0]] = seam[m.edge[jump, 1]] = True
+    ok = ins & ~seam
+    d = m.gradient_lonlat(m.lon.copy(), 1)[:, 0, :]
+    assert np.abs(d[ok, 0] - 1.0).max() <= 1e-12 and np.abs(d[ok, 1]).max() <= 1e-12
+    f = np.random.default_rng(N).standard_normal((m.V, 3))
+    g = m.gradient(f, 3)
+    c = m.gradient_lonlat(f, 3)
+    want = np.stack([R * np.cos(m.lat)[:, None] * g[..., 0], R * g[..., 1]], axis=-1)
+    assert np.abs(c - want).max() <= 1e-12 * np.abs(want).max()
