@@ -61,11 +61,17 @@ def parse_args():
 
 
 def kernel_source_sha():
-    """Identity of what sets the dominant kernel's memory traffic: the kernel
-    source and the default tile layout of the processing order."""
+    """Identity of what sets the dominant kernel's memory traffic: the source
+    of the wave-specialised sweep (the FP64 gradient's kernel) and of its
+    geometry packing, and the default tile layout of the processing order."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1908_06091_amd", "csrc", "nabla_kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1908_06091_amd", "csrc", "nabla_kernels.hip")) as fh:
+        src = fh.read()
+    for start, end in (("// Wave-specialised sweep.", "// Fused Laplacian: one pass"),
+                       ("__global__ void k_pack_sgeo(", "\n}\n")):
+        i = src.find(start)
+        j = src.find(end, i + 1)
+        h.update(src[i:j].encode() if i >= 0 and j > i else src.encode())
     with open(os.path.join(ROOT, "paper_1908_06091_amd", "csrc", "internal.h")) as fh:
         layout = "\n".join(l for l in fh.read().splitlines() if re.search(r"kDefault(Band|Width)", l))
     h.update(layout.encode())
