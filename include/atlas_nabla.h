@@ -125,6 +125,9 @@ typedef struct {
   int32_t nrings, max_degree;
   size_t device_bytes;      /* device memory held by the mesh store        */
   double geometry_bytes_per_call; /* mesh bytes one operator pass reads   */
+  int64_t max_levels;       /* most levels a field on this mesh may have:  */
+                            /* byte offsets inside one parallel of columns */
+                            /* and element counters of one tile are 32-bit */
 } atlas_mesh_info;
 
 /* ---------------------------------------------------------------------- */
@@ -222,8 +225,8 @@ atlas_status atlas_mesh_get_info(atlas_mesh_t mesh, atlas_mesh_info *info);
 /* fields, FP64 geometry, FP32 edge terms with a compensated (Kahan) node   */
 /* sum, final scaling in FP64.                                              */
 /* Errors (nothing enqueued): ATLAS_EINVAL for a NULL or misaligned pointer,*/
-/* nlev < 1, overlapping input/output, unknown dtype; ATLAS_EDEVICE if the  */
-/* launch fails.                                                            */
+/* nlev < 1 or above the mesh's max_levels (atlas_mesh_info), overlapping   */
+/* input/output, unknown dtype; ATLAS_EDEVICE if the launch fails.          */
 /* ---------------------------------------------------------------------- */
 atlas_status atlas_nabla_gradient(atlas_mesh_t mesh, const void *f, int32_t nlev,
                                   atlas_dtype dtype, void *out, hipStream_t stream);

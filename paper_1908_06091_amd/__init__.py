@@ -215,6 +215,7 @@ class Mesh:
         self.info = info
         self.nnodes = int(info.nnodes)
         self.nedges = int(info.nedges)
+        self.max_levels = int(info.max_levels)
         self.N = N
 
     @property

@@ -47,7 +47,7 @@ class MeshInfo(ctypes.Structure):
         ("nincidences", ctypes.c_int64), ("npole_edges", ctypes.c_int64),
         ("ntiles", ctypes.c_int64), ("nrings", ctypes.c_int32),
         ("max_degree", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
-        ("geometry_bytes_per_call", ctypes.c_double),
+        ("geometry_bytes_per_call", ctypes.c_double), ("max_levels", ctypes.c_int64),
     ]
 
 

@@ -56,6 +56,32 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// Whether fields of `nlev` levels fit the library's offsets: all values of
+// a field below 2^40; the byte offsets inside one buffer resource (a
+// parallel of columns, 16 bytes per level at most) and the element
+// counters of one tile below 2^31.
+bool levels_fit(const MeshStore &m, int64_t nlev, std::string *why) {
+  const int64_t lim = (int64_t)1 << 31;
+  if ((int64_t)m.d.V * nlev * 2 >= ((int64_t)1 << 40)) {
+    if (why) *why = "nnodes * nlev too large";
+    return false;
+  }
+  if (m.max_run * nlev * 16 >= lim || m.max_tile * nlev * 2 >= lim) {
+    if (why)
+      *why = "nlev too large for this mesh: at most " +
+             std::to_string(max_levels(m)) + " levels (longest parallel " +
+             std::to_string(m.max_run) + " nodes, largest tile " + std::to_string(m.max_tile) + ")";
+    return false;
+  }
+  return true;
+}
+
+int64_t max_levels(const MeshStore &m) {
+  const int64_t lim = ((int64_t)1 << 31) - 1;
+  int64_t n = std::min(lim / (16 * m.max_run), lim / (2 * m.max_tile));
+  return std::min<int64_t>(n, (((int64_t)1 << 40) - 1) / (2 * (int64_t)m.d.V));
+}
+
 // Validates every argument of an operator call before anything is enqueued.
 atlas_status check_call(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev,
                         atlas_dtype dt, void *out) {
@@ -63,8 +89,7 @@ atlas_status check_call(atlas_mesh_t mesh, atlas_op op, const void *in, int nlev
   if (op < ATLAS_OP_GRADIENT || op > ATLAS_OP_LAPLACIAN) return fail(ATLAS_EINVAL, "unknown operator");
   if (dt != ATLAS_F32 && dt != ATLAS_F64) return fail(ATLAS_EINVAL, "unknown dtype");
   if (nlev < 1) return fail(ATLAS_EINVAL, "nlev must be >= 1");
-  if ((int64_t)mesh->store->d.V * nlev * 2 >= ((int64_t)1 << 31))
-    return fail(ATLAS_EINVAL, "nnodes * nlev too large");
+  if (std::string why; !levels_fit(*mesh->store, nlev, &why)) return fail(ATLAS_EINVAL, why);
   if (!in || !out) return fail(ATLAS_EINVAL, "field pointer is NULL");
   const size_t w = dt == ATLAS_F64 ? 8 : 4;
   const size_t vw = (op == ATLAS_OP_GRADIENT) ? 2 * w : w;
@@ -315,6 +340,7 @@ atlas_status atlas_mesh_get_info(atlas_mesh_t mesh, atlas_mesh_info *info) {
   info->max_degree = m.max_degree;
   info->device_bytes = m.bytes;
   info->geometry_bytes_per_call = m.geometry_bytes;
+  info->max_levels = max_levels(m);
   return ATLAS_OK;
 }
 

@@ -192,6 +192,14 @@ struct MeshStore {
   const double *node_lat = nullptr;  // device [V], by node id
   int64_t nincid = 0;
   int32_t nrings = 0, max_degree = 0;
+  // most nodes a sweep kernel addresses through one buffer resource (the
+  // longest parallel of a mesh with a sweep plan, else one column): the
+  // byte offsets inside it are 32-bit
+  int64_t max_run = 1;
+  // most nodes one workgroup's unit of work holds (the largest tile, and
+  // at least the 1024 nodes of a batch unit): its element counters are
+  // 32-bit
+  int64_t max_tile = 1024;
   size_t bytes = 0;
   std::vector<void *> allocations;
   // internal Laplacian / flux workspace, grown on demand
@@ -213,6 +221,11 @@ struct MeshStore {
 };
 
 int device_cu_count();
+
+// Whether fields of `nlev` levels fit the mesh's 32-bit offsets (else the
+// reason in *why), and the most levels that do.
+bool levels_fit(const MeshStore &m, int64_t nlev, std::string *why);
+int64_t max_levels(const MeshStore &m);
 
 atlas_status launch_op(const MeshStore &m, atlas_op op, atlas_dtype dt,
                        const void *in, int nlev, void *out, void *ws,

@@ -559,6 +559,12 @@ atlas_status upload_mesh(const atlas_mesh_desc *d, int band, int width, MeshStor
   m->radius = d->radius;
   m->nrings = nrings;
   m->max_degree = maxdeg;
+  for (size_t t = 0; t + 1 < tile_ptr.size(); ++t)
+    m->max_tile = std::max<int64_t>(m->max_tile, tile_ptr[t + 1] - tile_ptr[t]);
+  if (sweep_ok) {
+    const std::vector<int64_t> off = rings_of(d);
+    for (size_t j = 0; j + 1 < off.size(); ++j) m->max_run = std::max(m->max_run, off[j + 1] - off[j]);
+  }
   m->d.maxdeg = maxdeg;
   m->d.mindeg = V > 0 ? mindeg : 0;
   m->d.sweep_ok = sweep_ok ? 1 : 0;

@@ -2641,12 +2641,16 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
                                             : m.ntiles;
   const int per_xcd = (ntiles + 7) / 8;
   const dim3 grid(per_xcd * 8), block(sh.block);
+  if (sh.nodes_per_block > 0 && (int64_t)sh.nodes_per_block * nlev * 2 >= ((int64_t)1 << 31))
+    return fail(ATLAS_EINVAL, "nodes_per_block * nlev too large");
   switch (sh.variant) {
     case ATLAS_VARIANT_COLUMN: {
       if (sh.block > 512 && sh.level_chunk == 0)
         return fail(ATLAS_EINVAL, "the column form takes at most 512 threads per block");
       if (sh.level_chunk > 0) {
         const int nchunk = (nlev + sh.level_chunk - 1) / sh.level_chunk;
+        if ((int64_t)ntiles * nchunk * sh.block >= ((int64_t)1 << 32))
+          return fail(ATLAS_EINVAL, "too many work units: raise nodes_per_block or level_chunk");
         const int units = ntiles * nchunk;
         const int per = (units + 7) / 8;
         hipLaunchKernelGGL((k_column_chunked<T, OP>), dim3(per * 8), block, 0, st, m, in, out,

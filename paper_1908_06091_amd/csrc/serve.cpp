@@ -642,8 +642,9 @@ atlas_status atlas_serve_submit(atlas_server_t srv, const atlas_request *req, ui
     q.out_b = (size_t)re.nt * req->nlev * w;
   } else {
     const MeshEntry &me = sv.meshes[req->mesh_id];
-    if (me.V * req->nlev * 2 >= ((int64_t)1 << 31))
-      return reject(ATLAS_EINVAL, "nnodes * nlev too large");
+    if (std::string why; me.mesh ? !levels_fit(*me.mesh->store, req->nlev, &why)
+                                  : me.V * req->nlev * 2 >= ((int64_t)1 << 40))
+      return reject(ATLAS_EINVAL, why.empty() ? "nnodes * nlev too large" : why.c_str());
     const size_t base = (size_t)me.V * req->nlev * w;
     q.m = me.mesh ? me.mesh->store : nullptr;
     q.V = me.V;
