@@ -1678,10 +1678,10 @@ __device__ __forceinline__ int2 cst_int2(const int2 *p, size_t i) {
   return make_int2(d[2 * i], d[2 * i + 1]);
 }
 
-template <class T, int NV, int EPT, int NPW>
+template <class T, int NV, int EPT, int NL>
 __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict__ in,
                                                  T *__restrict__ out, int nlev, int vpc,
-                                                 int ntiles, int per_xcd) {
+                                                 int ntiles, int per_xcd, int lpn) {
   using PG = Pol<T, OP_GRAD>;
   using PD = Pol<T, OP_DIV>;
   using LF = LaneVec<T, NV>;
@@ -1854,14 +1854,15 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
   deposit_geo(0);
   __syncthreads();
 
-  // NPW nodes per wavefront: its lanes split into NPW groups of 64 / NPW,
-  // one node each (the chunk has at most 64 / NPW lane vectors)
-  constexpr int LPN = 64 / NPW;
-  const int sub = lane / LPN;
-  const int hl = lane - sub * LPN;
-  const int kc = min(hl, nvc - 1);  // lanes past the chunk read a valid entry
-  const int s_l = first(kc);
-  const bool lane_on = hl < nvc;
+  // lpn lanes per node, 64 / lpn nodes per wavefront (lanes past the last
+  // whole group idle); lane hl of a group walks the chunk's lane vectors
+  // hl, hl + lpn, ... (NL of them, lpn * NL >= nvc) with the node's
+  // geometry in registers, so one broadcast read of a record serves
+  // 64 / lpn nodes and NL lane vectors
+  const int npw = 64 / lpn;
+  const int sub = lane / lpn;
+  const int hl = lane - sub * lpn;
+  const bool sub_on = sub < npw;
   for (int q = 0; q < W + 2; ++q) {
     const bool pf = q + 2 < W;
     if (pf) fetch(q + 2);
@@ -1870,8 +1871,8 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
     const i32x4 *gq = geo + (q & 1) * geo_stride;
     // ---- gradients at the g-run of parallel q
     if (q < W) {
-      const int glen = cst_int4(m.l2_gseg, k0 + q).y;
-      for (int s = NPW * wave + sub; s < glen; s += NPW * nw) {
+      const int glen = sub_on ? cst_int4(m.l2_gseg, k0 + q).y : 0;
+      for (int s = npw * wave + sub; s < glen; s += npw * nw) {
         const i32x4 *r = gq + s * kGGeoWords;
         double2 S[G];  // halved normals (FP64), the normals (FP32)
         int lr[8];
@@ -1894,6 +1895,473 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
         }
         const i32x4 w9 = r[9];
         const int fself = w9.x, n = w9.y;  // fself: LDS offset
+        double cosg;
+        {
+          const int c2[2] = {w9.z, w9.w};
+          __builtin_memcpy(&cosg, c2, 8);
+        }
+        // closure of the node's normals (level independent)
+        double cx = 0.0, cy = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          const bool pole = (lr[j] & kLrefPole) != 0;
+          if (j < kMinRow) {
+            closure_add<OP_GRAD>(cx, cy, S[j], false);
+            continue;
+          }
+          double tx = cx, ty = cy;
+          closure_add<OP_GRAD>(tx, ty, S[j], pole);
+          cx = j < n ? tx : cx;
+          cy = j < n ? ty : cy;
+        }
+#pragma unroll 1
+        for (int i = 0; i < NL; ++i) {
+          const int k = hl + lpn * i;
+          const int kc = min(k, nvc - 1);  // lanes past the chunk read a valid entry
+          typename PG::St st[NV];
+          {
+            const RF xi = fbuf[fself + kc];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) PG::init(st[v], LF::get(xi, v), 0.0);
+          }
+          RF xn[G];
+#pragma unroll
+          for (int j = 0; j < G; ++j) xn[j] = fbuf[(lr[j] & ~kLrefPole) + kc];
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            const bool pole = (lr[j] & kLrefPole) != 0;
+            if (j < kMinRow) {  // present in every row, never the pole edge
+#pragma unroll
+              for (int v = 0; v < NV; ++v) {
+                if constexpr (F64) grad_add_half(st[v], LF::get(xn[j], v), S[j], false);
+                else PG::add(st[v], LF::get(xn[j], v), S[j], false, 0.0);
+              }
+              continue;
+            }
+            const bool use = j < n;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              typename PG::St tt = st[v];
+              if constexpr (F64) grad_add_half(tt, LF::get(xn[j], v), S[j], pole);
+              else PG::add(tt, LF::get(xn[j], v), S[j], pole, 0.0);
+              PG::keep(st[v], tt, use);
+            }
+          }
+          RG g;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const typename PG::Out o = PG::result(st[v], al, be, cx, cy, 0.0);
+            g.e[2 * v] = o.x;
+            if constexpr (F64) g.e[2 * v + 1] = o.y * cosg;  // v cos(lat), as the divergence forms it
+            else g.e[2 * v + 1] = o.y;
+          }
+          if (k < nvc) {
+            RF *d = gbuf + (q & 3) * gstride + s * 2 * vpc + kc;
+            __builtin_memcpy(d, &g, sizeof(RF));
+            __builtin_memcpy(d + vpc, reinterpret_cast<const char *>(&g) + sizeof(RF), sizeof(RF));
+          }
+        }
+      }
+    }
+    // The staged loads go to LDS here, between the two phases: the slots
+    // they fill (field ring (q + 2) mod 4, geometry slot (q + 1) mod 2) are
+    // read by neither phase of this step, the gradient phase has hidden
+    // their latency, and the wait for them comes before this step's output
+    // stores (vector memory operations retire in issue order).
+    if (pf) deposit(q + 2);
+    if (gf) deposit_geo(q + 1);
+    // ---- Laplacian at the own positions of parallel q - 2
+    if (q >= 2) {
+      const int q2 = q - 2;
+      const int2 sp = cst_int2(m.l2_seg_pos, k0 + q2);
+      const int nown = sub_on ? sp.y - sp.x : 0;
+      for (int t = npw * wave + sub; t < nown; t += npw * nw) {
+        const i32x4 *r = gq + gw + t * LGW;
+        double2 S[G];  // halved normals (FP64), the normals (FP32)
+        int lr[8];
+        double cn[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          __builtin_memcpy(&S[j], &r[j], 16);
+          if constexpr (!F64) S[j] = make_double2(S[j].x + S[j].x, S[j].y + S[j].y);
+        }
+        {
+          const i32x4 a = r[6], b = r[7];
+          lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
+          lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
+        }
+        if constexpr (!F64) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) __builtin_memcpy(&cn[2 * k], &r[10 + k], 16);
+        } else {
+#pragma unroll
+          for (int j = 0; j < G; ++j) cn[j] = 0.0;
+        }
+        double al, ci;
+        {
+          const i32x4 w8 = r[8];
+          const int a2[2] = {w8.x, w8.y}, c2[2] = {w8.z, w8.w};
+          __builtin_memcpy(&al, a2, 8);
+          __builtin_memcpy(&ci, c2, 8);
+        }
+        const i32x4 w9 = r[9];
+        const int node = w9.x, n = w9.y, self = w9.z;  // self: LDS offset
+        double cx = 0.0, cy = 0.0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          const bool pole = (lr[j] & kLrefPole) != 0;
+          if (j < kMinRow) {
+            closure_add<OP_DIV>(cx, cy, S[j], false);
+            continue;
+          }
+          double tx = cx, ty = cy;
+          closure_add<OP_DIV>(tx, ty, S[j], pole);
+          const bool use = j < n && !pole;
+          cx = use ? tx : cx;
+          cy = use ? ty : cy;
+        }
+#pragma unroll 1
+        for (int i = 0; i < NL; ++i) {
+          const int k = hl + lpn * i;
+          const int kc = min(k, nvc - 1);
+          typename PD::St st[NV];
+          {
+            const RG gi = gload(self + kc);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              if constexpr (F64) div_init_w(st[v], LG::get(gi, v));
+              else PD::init(st[v], LG::get(gi, v), ci);
+            }
+          }
+          RG gn[G];
+#pragma unroll
+          for (int j = 0; j < G; ++j) gn[j] = gload((lr[j] & ~kLrefPole) + kc);
+#pragma unroll
+          for (int j = 0; j < G; ++j) {
+            const bool pole = (lr[j] & kLrefPole) != 0;
+            if (j < kMinRow) {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) {
+                if constexpr (F64) div_add_half_w(st[v], LG::get(gn[j], v), S[j]);
+                else PD::add(st[v], LG::get(gn[j], v), S[j], false, cn[j]);
+              }
+              continue;
+            }
+            const bool use = j < n && !pole;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              typename PD::St tt = st[v];
+              if constexpr (F64) div_add_half_w(tt, LG::get(gn[j], v), S[j]);
+              else PD::add(tt, LG::get(gn[j], v), S[j], pole, cn[j]);
+              PD::keep(st[v], tt, use);
+            }
+          }
+          constexpr int WD = NV * (int)sizeof(T) / 4;
+          struct Words { int v[WD]; } o;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const T x = PD::result(st[v], al, 0.0, cx, cy, ci);
+            __builtin_memcpy(&o.v[v * (int)sizeof(T) / 4], &x, sizeof(T));
+          }
+          if (k < nvc) *reinterpret_cast<Words *>(out + (size_t)node * L + first(kc)) = o;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused Laplacian, wave-specialised: the register-staged kernel above waits
+// at every parallel for the loads it issued one parallel earlier, one
+// memory round trip per step.  Here two producer groups of two wavefronts
+// load the field runs and packed geometry straight into LDS (16-byte DMA
+// loads, as in the wave-specialised sweep) two steps ahead, and never
+// store, so each waits for exactly its own loads; the consumer wavefronts
+// only compute and store.
+//
+// Step q forms the gradients of the g-run of parallel q (field runs q-1,
+// q, q+1) into gradient slot q mod 3, then -- after a workgroup barrier --
+// the Laplacian of the own positions of parallel q-1 from the gradients of
+// parallels q-2, q-1, q.  Load set k = {field run k+1, geometry of step k
+// (g records of parallel k, own records of parallel k-1)} is issued at step
+// k-2 by group k mod 2 and waited for by that group at the end of step
+// k-1: field ring 5 slots, geometry ring 3, gradient ring 3.  References
+// in the packed records are resolved at use (the deposit of the
+// register-staged kernel resolved them once).
+// ---------------------------------------------------------------------------
+constexpr int kLswFSlots = 5, kLswGSlots = 3, kLswGeoSlots = 3;
+constexpr int kLswProducers = 4;  // two groups of two wavefronts
+
+template <class T, int NV>
+__global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict__ in,
+                                                  T *__restrict__ out, int nlev, int vpc,
+                                                  int ntiles, int per_xcd, int lpn, int fcap,
+                                                  int gcap, int ocap) {
+  using PG = Pol<T, OP_GRAD>;
+  using PD = Pol<T, OP_DIV>;
+  using LF = LaneVec<T, NV>;
+  using RF = typename LF::raw;
+  using GV = typename PD::V;
+  using LG = LaneVec<GV, NV>;
+  using RG = typename LG::raw;
+  static_assert(sizeof(RF) == 16, "wave-specialised fused Laplacian: 16-byte lane vectors");
+  static_assert(sizeof(RG) == 2 * sizeof(RF), "gradient lane vector = two field lane vectors");
+  constexpr int G = 6;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int LGW = F64 ? kLGeoWords64 : kLGeoWords;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int gmax = m.l2_gmax;
+  const int gstride = 2 * gmax * vpc;   // gradient slot (field lane vectors)
+  const int geo_stride = gcap + ocap;   // geometry slot (16-byte words)
+  RF *fbuf = reinterpret_cast<RF *>(smem_raw);                         // [5][fcap]
+  RF *gbuf = fbuf + kLswFSlots * fcap;                                 // [3][gmax][2][vpc]
+  i32x4 *geo = reinterpret_cast<i32x4 *>(gbuf + kLswGSlots * gstride);  // [3][gcap + ocap]
+  const int u = xcd_tile(blockIdx.x, per_xcd);
+  const int nvec = (nlev + NV - 1) / NV;
+  const int nchunk = (nvec + vpc - 1) / vpc;
+  const int tile = u / nchunk;
+  const int c = u - tile * nchunk;
+  if (tile >= ntiles) return;
+  const int v0 = c * vpc;
+  if (v0 >= nvec) return;
+  const int nvc = min(vpc, nvec - v0);
+  const int k0 = cst(m.l2_tile_seg)[tile];
+  const int W = cst(m.l2_tile_seg)[tile + 1] - k0;
+  const size_t L = (size_t)nlev;
+  const uint32_t col_bytes = (uint32_t)(L * sizeof(T));
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  auto first = [&](int k) { return min(NV * (v0 + k), nlev - NV); };
+
+  if (wave < kLswProducers) {
+    // ---- producers: waves 0, 1 form group 0 and waves 2, 3 group 1; the
+    // even wave of a group loads and resolves geometry, the odd one loads
+    // field runs, so every wave waits only for the loads it issued ---------
+    const int grp = wave >> 1;
+    const bool geo_wave = (wave & 1) == 0;
+    // field run q into slot q mod 5: item i = (node t of the run) x (lane
+    // vector kk); t and kk advance by whole load instructions
+    auto load_f = [&](int q) {
+      if (q < 0 || q >= W) return;
+      const int4 f = cst_int4(m.l2_fseg, k0 + q);  // {ring offset, ring size, first, length}
+      const i32x4 rs = make_rsrc(in + (size_t)f.x * L, (uint32_t)f.y * col_bytes);
+      const int nitems = f.w * nvc;
+      RF *slot = fbuf + (q % kLswFSlots) * fcap;
+      int t = lane / nvc, kk = lane - t * nvc;
+      const int dt = 64 / nvc, dk = 64 - dt * nvc;
+      for (int b = 0; b * 64 < nitems; ++b) {
+        int off = kBufOff;
+        if (b * 64 + lane < nitems) {
+          int ii = f.z + t;
+          if (ii >= f.y) ii -= f.y;  // the run wraps round the parallel
+          off = ii * (int)col_bytes + first(kk) * (int)sizeof(T);
+        }
+        lds_dma16(rs, slot + b * 64, off);
+        t += dt;
+        kk += dk;
+        if (kk >= nvc) {
+          kk -= nvc;
+          ++t;
+        }
+      }
+    };
+    // geometry of step k: g records of parallel k, own records of k - 1
+    auto load_g = [&](int k) {
+      if (k < 0 || k > W) return;
+      i32x4 *gs = geo + (k % kLswGeoSlots) * geo_stride;
+      if (k < W) {
+        const int4 g = cst_int4(m.l2_gseg, k0 + k);  // {g first, g length, first g record, 0}
+        const i32x4 rs = make_rsrc(m.l2_ggeo + (size_t)g.z * kGGeoWords,
+                                   (uint32_t)g.y * kGGeoWords * 16u);
+        const int nitems = g.y * kGGeoWords;
+        for (int b = 0; b * 64 < nitems; ++b) {
+          const int i = b * 64 + lane;
+          lds_dma16(rs, gs + b * 64, i < nitems ? i * 16 : kBufOff);
+        }
+      }
+      if (k >= 1) {
+        const int2 sp = cst_int2(m.l2_seg_pos, k0 + k - 1);
+        const int np = sp.y - sp.x;
+        const i32x4 rs = make_rsrc(m.l2_lgeo + (size_t)sp.x * kLGeoWords,
+                                   (uint32_t)np * kLGeoWords * 16u);
+        const int nitems = np * LGW;
+        int t = lane / LGW, wd = lane - t * LGW;
+        constexpr int dt = 64 / LGW, dw = 64 - dt * LGW;
+        for (int b = 0; b * 64 < nitems; ++b) {
+          lds_dma16(rs, gs + gcap + b * 64,
+                    b * 64 + lane < nitems ? (t * kLGeoWords + wd) * 16 : kBufOff);
+          t += dt;
+          wd += dw;
+          if (wd >= LGW) {
+            wd -= LGW;
+            ++t;
+          }
+        }
+      }
+    };
+    // The reference words of geometry set k (words 6, 7, 9 of each record:
+    // one g record and one own record per lane) also go to registers with
+    // the set's loads; once the set has landed they become LDS element
+    // offsets for the step that reads them (field-run references of the g
+    // records of parallel k: runs k-1, k, k+1; gradient-run references of
+    // the own records of parallel k-1: runs k-2, k-1, k; pole flags kept)
+    // and overwrite the copied words.
+    i32x4 gr6 = {}, gr7 = {}, gr9 = {}, or6 = {}, or7 = {}, or9 = {};
+    auto load_refs = [&](int k) {
+      if (k < 0 || k > W) return;
+      if (k < W) {
+        const int4 g = cst_int4(m.l2_gseg, k0 + k);
+        const i32x4 rs = make_rsrc(m.l2_ggeo + (size_t)g.z * kGGeoWords,
+                                   (uint32_t)g.y * kGGeoWords * 16u);
+        const int o = lane < g.y ? lane * kGGeoWords * 16 : kBufOff;
+        gr6 = buf_load<i32x4>(rs, o + 6 * 16);
+        gr7 = buf_load<i32x4>(rs, o + 7 * 16);
+        gr9 = buf_load<i32x4>(rs, o + 9 * 16);
+      }
+      if (k >= 1) {
+        const int2 sp = cst_int2(m.l2_seg_pos, k0 + k - 1);
+        const i32x4 rs = make_rsrc(m.l2_lgeo + (size_t)sp.x * kLGeoWords,
+                                   (uint32_t)(sp.y - sp.x) * kLGeoWords * 16u);
+        const int o = lane < sp.y - sp.x ? lane * kLGeoWords * 16 : kBufOff;
+        or6 = buf_load<i32x4>(rs, o + 6 * 16);
+        or7 = buf_load<i32x4>(rs, o + 7 * 16);
+        or9 = buf_load<i32x4>(rs, o + 9 * 16);
+      }
+    };
+    auto resolve = [&](int k) {
+      // the loaded words are used from here on only: no computation on them
+      // may move up to the loads, where it would wait for the whole set
+      asm volatile("" : "+v"(gr6), "+v"(gr7), "+v"(gr9), "+v"(or6), "+v"(or7), "+v"(or9));
+      if (k < 0 || k > W) return;
+      i32x4 *gs = geo + (k % kLswGeoSlots) * geo_stride;
+      if (k < W) {
+        const int b0 = ((k + kLswFSlots - 1) % kLswFSlots) * fcap;
+        const int b1 = (k % kLswFSlots) * fcap, b2 = ((k + 1) % kLswFSlots) * fcap;
+        auto rf = [&](int v) {
+          const int l = v & ~kLrefPole, dq = (l >> 16) & 3;
+          return (v & kLrefPole) | ((dq == 0 ? b0 : dq == 1 ? b1 : b2) + (l & 0xffff) * nvc);
+        };
+        if (lane < cst_int4(m.l2_gseg, k0 + k).y) {
+          i32x4 *r = gs + lane * kGGeoWords;
+          i32x4 a = gr6, b = gr7, c = gr9;
+          a.x = rf(a.x); a.y = rf(a.y); a.z = rf(a.z); a.w = rf(a.w);
+          b.x = rf(b.x); b.y = rf(b.y); b.z = rf(b.z); b.w = rf(b.w);
+          c.x = b1 + c.x * nvc;
+          r[6] = a; r[7] = b; r[9] = c;
+        }
+      }
+      if (k >= 1) {
+        const int b0 = ((k + 1) % kLswGSlots) * gstride;
+        const int b1 = ((k + 2) % kLswGSlots) * gstride, b2 = (k % kLswGSlots) * gstride;
+        auto rg = [&](int v) {
+          const int l = v & ~kLrefPole, dq = (l >> 16) & 3;
+          return (v & kLrefPole) | ((dq == 0 ? b0 : dq == 1 ? b1 : b2) + (l & 0xffff) * 2 * vpc);
+        };
+        const int2 sp = cst_int2(m.l2_seg_pos, k0 + k - 1);
+        if (lane < sp.y - sp.x) {
+          i32x4 *r = gs + gcap + lane * LGW;
+          i32x4 a = or6, b = or7, c = or9;
+          a.x = rg(a.x); a.y = rg(a.y); a.z = rg(a.z); a.w = rg(a.w);
+          b.x = rg(b.x); b.y = rg(b.y); b.z = rg(b.z); b.w = rg(b.w);
+          c.z = b1 + c.z * 2 * vpc;
+          r[6] = a; r[7] = b; r[9] = c;
+        }
+      }
+    };
+    // prologue: group 0 takes geometry 0 and field runs 0, 1; group 1
+    // geometry 1 and field run 2; each geometry wave resolves its own set
+    if (geo_wave) {
+      load_refs(grp);  // first: no DMA of the set may wait on these registers
+      load_g(grp);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      resolve(grp);
+    } else {
+      if (grp == 0) {
+        load_f(0);
+        load_f(1);
+      } else {
+        load_f(2);
+      }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    for (int q = 0; q <= W; ++q) {
+      // set q + 2 (field run q + 3, geometry q + 2) by group q mod 2
+      if ((q & 1) == grp) {
+        if (geo_wave) {
+          load_refs(q + 2);
+          load_g(q + 2);
+        } else {
+          load_f(q + 3);
+        }
+      }
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();  // between the consumers' two phases
+      asm volatile("" ::: "memory");
+      // set q + 1 (issued at step q - 1 by this group; sets 0 and 1 came
+      // with the prologue) lands, and is resolved, before step q + 1
+      if (((q + 1) & 1) == grp && q >= 1) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (geo_wave) resolve(q + 1);
+      }
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    return;
+  }
+
+  // ---- consumers ------------------------------------------------------------
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  const int cw = wave - kLswProducers, ncw = nw - kLswProducers;
+  const int npw = 64 / lpn;  // nodes per wavefront, lpn lanes each
+  const int sub = lane / lpn;
+  const int hl = lane - sub * lpn;
+  const bool sub_on = sub < npw;
+  const int kc = min(hl, nvc - 1);  // lanes past the chunk read a valid entry
+  const bool lane_on = sub_on && hl < nvc;
+  auto gload = [&](int at) {
+    RG r;
+    __builtin_memcpy(&r, &gbuf[at], sizeof(RF));
+    __builtin_memcpy(reinterpret_cast<char *>(&r) + sizeof(RF), &gbuf[at + vpc], sizeof(RF));
+    return r;
+  };
+  for (int q = 0; q <= W; ++q) {
+    const i32x4 *gq = geo + (q % kLswGeoSlots) * geo_stride;
+    // ---- gradients at the g-run of parallel q
+    if (q < W) {
+      RF *gout = gbuf + (q % kLswGSlots) * gstride;
+      const int glen = sub_on ? cst_int4(m.l2_gseg, k0 + q).y : 0;
+      for (int s = npw * cw + sub; s < glen; s += npw * ncw) {
+        const i32x4 *r = gq + s * kGGeoWords;
+        double2 S[G];  // halved normals (FP64), the normals (FP32)
+        int lr[8];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          __builtin_memcpy(&S[j], &r[j], 16);
+          if constexpr (!F64) S[j] = make_double2(S[j].x + S[j].x, S[j].y + S[j].y);
+        }
+        {
+          const i32x4 a = r[6], b = r[7];
+          lr[0] = a.x; lr[1] = a.y; lr[2] = a.z; lr[3] = a.w;
+          lr[4] = b.x; lr[5] = b.y; lr[6] = b.z; lr[7] = b.w;
+        }
+        double al, be;
+        {
+          const i32x4 w8 = r[8];
+          const int a2[2] = {w8.x, w8.y}, b2[2] = {w8.z, w8.w};
+          __builtin_memcpy(&al, a2, 8);
+          __builtin_memcpy(&be, b2, 8);
+        }
+        const i32x4 w9 = r[9];
+        const int fself = w9.x, n = w9.y;
         double cosg;
         {
           const int c2[2] = {w9.z, w9.w};
@@ -1943,19 +2411,23 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
           else g.e[2 * v + 1] = o.y;
         }
         if (lane_on) {
-          RF *d = gbuf + (q & 3) * gstride + s * 2 * vpc + kc;
+          RF *d = gout + s * 2 * vpc + kc;
           __builtin_memcpy(d, &g, sizeof(RF));
           __builtin_memcpy(d + vpc, reinterpret_cast<const char *>(&g) + sizeof(RF), sizeof(RF));
         }
       }
     }
-    // ---- Laplacian at the own positions of parallel q - 2
-    if (q >= 2) {
-      const int q2 = q - 2;
-      const int2 sp = cst_int2(m.l2_seg_pos, k0 + q2);
-      for (int t = NPW * wave + sub; t < sp.y - sp.x; t += NPW * nw) {
-        const i32x4 *r = gq + gw + t * LGW;
-        double2 S[G];  // halved normals (FP64), the normals (FP32)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();  // the gradients of parallel q are in LDS
+    asm volatile("" ::: "memory");
+    // ---- Laplacian at the own positions of parallel q - 1
+    if (q >= 1) {
+      const int q1 = q - 1;
+      const int2 sp = cst_int2(m.l2_seg_pos, k0 + q1);
+      const int nown = sub_on ? sp.y - sp.x : 0;
+      for (int t = npw * cw + sub; t < nown; t += npw * ncw) {
+        const i32x4 *r = gq + gcap + t * LGW;
+        double2 S[G];
         int lr[8];
         double cn[G];
 #pragma unroll
@@ -1983,7 +2455,7 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
           __builtin_memcpy(&ci, c2, 8);
         }
         const i32x4 w9 = r[9];
-        const int node = w9.x, n = w9.y, self = w9.z;  // self: LDS offset
+        const int node = w9.x, n = w9.y, self = w9.z;
         typename PD::St st[NV];
         {
           const RG gi = gload(self + kc);
@@ -2023,29 +2495,18 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
           }
         }
         constexpr int WD = NV * (int)sizeof(T) / 4;
-        int w[WD];
+        struct Words { int v[WD]; } o;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const T o = PD::result(st[v], al, 0.0, cx, cy, ci);
-          __builtin_memcpy(&w[v * (int)sizeof(T) / 4], &o, sizeof(T));
+          const T x = PD::result(st[v], al, 0.0, cx, cy, ci);
+          __builtin_memcpy(&o.v[v * (int)sizeof(T) / 4], &x, sizeof(T));
         }
-        if constexpr (NPW == 1) {
-          // one node per wavefront: a buffer store over the node's row (the
-          // resource is wavefront-uniform)
-          const i32x4 ro = make_rsrc(out + (size_t)node * L, (uint32_t)(L * sizeof(T)));
-          buf_store_words<WD>(w, ro, lane_on ? s_l * (int)sizeof(T) : kBufOff);
-        } else if (lane_on) {
-          // several nodes per wavefront: a plain store through each lane's
-          // own address
-          struct Words { int v[WD]; } o;
-          __builtin_memcpy(o.v, w, sizeof(o));
-          *reinterpret_cast<Words *>(out + (size_t)node * L + s_l) = o;
-        }
+        if (lane_on) *reinterpret_cast<Words *>(out + (size_t)node * L + first(kc)) = o;
       }
     }
-    if (pf) deposit(q + 2);
-    if (gf) deposit_geo(q + 1);
-    __syncthreads();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
   }
 }
 
@@ -2549,10 +3010,11 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   // the wave-specialised sweep needs the packed geometry and rows of 4..6
   const bool sweepw_fits = sweep_fits && m.d.sgeo && m.d.maxdeg <= 6 && m.d.mindeg >= kMinRow;
   if (op == ATLAS_OP_LAPLACIAN) {
-    // FP64 on large meshes: the fused one-pass form (it moves a third of the
-    // two passes' field bytes; in FP32 the two passes are still faster)
-    if (dt == ATLAS_F64 && nlev >= 48 && m.d.l2_ok && m.d.ntiles >= kSweepMinTiles &&
-        m.d.maxdeg <= 6 && m.d.mindeg >= kMinRow) {
+    // large meshes: the fused one-pass form, wave-specialised (it moves a
+    // third of the two passes' field bytes; measured faster than the two
+    // passes at 16 to 137 levels at O640 and O1280 in both precisions)
+    if (nlev >= 16 && m.d.l2_ok && m.d.ntiles >= kSweepMinTiles && m.d.maxdeg <= 6 &&
+        m.d.mindeg >= kMinRow) {
       s.variant = ATLAS_VARIANT_FUSED;
       s.block = 1024;
       s.nodes_per_block = 0;
@@ -2981,11 +3443,55 @@ static bool fused_plan(const MeshStore &ms, int nlev, const LaunchShape &sh, Fus
   return true;
 }
 
+// The wave-specialised fused Laplacian's plan (blocks_per_cu 0, 16-byte
+// lanes, at least one consumer wavefront): the level chunk shrinks until
+// the three rings fit in LDS; false where it cannot run.
+struct FusedwPlan {
+  int vpc, nchunk, fcap, gcap, ocap;
+  size_t lds;
+};
+template <class T>
+static bool fusedw_plan(const MeshStore &ms, int nlev, const LaunchShape &sh, FusedwPlan *fp) {
+  const DevMesh &m = ms.d;
+  constexpr int NVW = (int)(16 / sizeof(T));
+  if (!m.l2_ok || m.maxdeg > 6 || m.mindeg < kMinRow || !m.l2_ggeo || !m.l2_lgeo) return false;
+  if (sh.blocks_per_cu != 0 || sh.level_vec == 1 || nlev < NVW) return false;
+  if (sh.block < 64 * (kLswProducers + 1)) return false;
+  if (m.l2_gmax > 64 || m.l2_pmax > 64) return false;  // one record of each kind per lane
+  const int nvec = (nlev + NVW - 1) / NVW;
+  int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + NVW - 1) / NVW) : 64;
+  vpc = min(vpc, nvec);
+  int nch = (nvec + vpc - 1) / vpc;
+  vpc = (nvec + nch - 1) / nch;
+  auto r64 = [](int64_t x) { return (int)((x + 63) / 64 * 64); };
+  const int LGW = sizeof(T) == 8 ? kLGeoWords64 : kLGeoWords;
+  const int gcap = r64((int64_t)m.l2_gmax * kGGeoWords), ocap = r64((int64_t)m.l2_pmax * LGW);
+  auto bytes = [&](int v) {
+    return (size_t)16 * ((size_t)kLswFSlots * r64((int64_t)m.l2_fmax * v) +
+                         (size_t)kLswGSlots * 2 * m.l2_gmax * v +
+                         (size_t)kLswGeoSlots * (gcap + ocap));
+  };
+  while (vpc > 1 && bytes(vpc) > kMaxLds) {
+    ++nch;
+    vpc = (nvec + nch - 1) / nch;
+  }
+  if (bytes(vpc) > kMaxLds) return false;
+  fp->vpc = vpc;
+  fp->nchunk = (nvec + vpc - 1) / vpc;
+  fp->fcap = r64((int64_t)m.l2_fmax * vpc);
+  fp->gcap = gcap;
+  fp->ocap = ocap;
+  fp->lds = bytes(vpc);
+  return true;
+}
+
 bool lapl_fused_runs(const MeshStore &ms, int nlev, atlas_dtype dt, const LaunchShape &sh) {
   if (sh.variant != ATLAS_VARIANT_FUSED) return false;
   FusedPlan fp;
-  return dt == ATLAS_F64 ? fused_plan<double>(ms, nlev, sh, &fp)
-                         : fused_plan<float>(ms, nlev, sh, &fp);
+  FusedwPlan fw;
+  return dt == ATLAS_F64
+             ? fusedw_plan<double>(ms, nlev, sh, &fw) || fused_plan<double>(ms, nlev, sh, &fp)
+             : fusedw_plan<float>(ms, nlev, sh, &fw) || fused_plan<float>(ms, nlev, sh, &fp);
 }
 
 // The fused Laplacian on the two-ring plan; *ran = false (nothing
@@ -2995,26 +3501,44 @@ atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *ou
                                const LaunchShape &sh, hipStream_t st, bool *ran) {
   const DevMesh &m = ms.d;
   *ran = false;
+  constexpr int NVW = (int)(16 / sizeof(T));
+  FusedwPlan fw;
+  if (fusedw_plan<T>(ms, nlev, sh, &fw)) {
+    // wave-specialised: consumers take one lane vector per lane, vpc lanes
+    // per node
+    const int units = m.ntiles * fw.nchunk;
+    const int per = (units + 7) / 8;
+    auto kern = k_lsweepw<T, NVW>;
+    ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)fw.lds));
+    hipLaunchKernelGGL(kern, dim3(per * 8), dim3(sh.block), fw.lds, st, m, in, out, nlev, fw.vpc,
+                       m.ntiles, per, fw.vpc, fw.fcap, fw.gcap, fw.ocap);
+    ATLASX_HIP(hipGetLastError());
+    *ran = true;
+    return ATLAS_OK;
+  }
   FusedPlan fp;
   if (!fused_plan<T>(ms, nlev, sh, &fp)) return ATLAS_OK;
-  constexpr int NVW = (int)(16 / sizeof(T));
   const int nv = fp.nv, vpc = fp.vpc, nchunk = fp.nchunk;
   const size_t lds = fp.lds;
   const int units = m.ntiles * nchunk;
   const int per = (units + 7) / 8;
-  // several nodes per wavefront when the chunk fills at most half or a
-  // quarter of it
-  void (*kern)(DevMesh, const T *, T *, int, int, int, int) = nullptr;
+  // each lane walks nl lane vectors of a node (blocks_per_cu 1..3 picks
+  // nl; 0: one), so a node takes lpn = vpc / nl lanes (rounded up) and a
+  // wavefront 64 / lpn nodes
+  const int nl = sh.blocks_per_cu >= 1 && sh.blocks_per_cu <= 3 ? sh.blocks_per_cu : 1;
+  const int lpn = (vpc + nl - 1) / nl;
+  void (*kern)(DevMesh, const T *, T *, int, int, int, int, int) = nullptr;
   if (nv == 1)
-    kern = vpc <= 16 ? k_lsweep<T, 1, kLsweepEpt, 4>
-           : vpc <= 32 ? k_lsweep<T, 1, kLsweepEpt, 2> : k_lsweep<T, 1, kLsweepEpt, 1>;
+    kern = nl == 1 ? k_lsweep<T, 1, kLsweepEpt, 1>
+           : nl == 2 ? k_lsweep<T, 1, kLsweepEpt, 2> : k_lsweep<T, 1, kLsweepEpt, 3>;
   else
-    kern = vpc <= 16 ? k_lsweep<T, NVW, kLsweepEpt, 4>
-           : vpc <= 32 ? k_lsweep<T, NVW, kLsweepEpt, 2> : k_lsweep<T, NVW, kLsweepEpt, 1>;
+    kern = nl == 1 ? k_lsweep<T, NVW, kLsweepEpt, 1>
+           : nl == 2 ? k_lsweep<T, NVW, kLsweepEpt, 2> : k_lsweep<T, NVW, kLsweepEpt, 3>;
   ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(kern, dim3(per * 8), dim3(sh.block), lds, st, m, in, out, nlev, vpc,
-                     m.ntiles, per);
+                     m.ntiles, per, lpn);
   ATLASX_HIP(hipGetLastError());
   *ran = true;
   return ATLAS_OK;
