@@ -2286,7 +2286,8 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-    asm volatile("" ::: "memory");
+    // the resolved words are in LDS before the consumers pass the barrier
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     for (int q = 0; q <= W; ++q) {
@@ -2308,7 +2309,7 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (geo_wave) resolve(q + 1);
       }
-      asm volatile("" ::: "memory");
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
       __builtin_amdgcn_s_barrier();
       asm volatile("" ::: "memory");
     }
@@ -2417,7 +2418,7 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
         }
       }
     }
-    asm volatile("" ::: "memory");
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();  // the gradients of parallel q are in LDS
     asm volatile("" ::: "memory");
     // ---- Laplacian at the own positions of parallel q - 1
@@ -2504,7 +2505,8 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
         if (lane_on) *reinterpret_cast<Words *>(out + (size_t)node * L + first(kc)) = o;
       }
     }
-    asm volatile("" ::: "memory");
+    // this step's LDS reads are done before the producers refill a slot
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   }
