@@ -310,7 +310,13 @@ typedef struct {
                                others compute and store; 16-byte lane
                                vectors, at least 256 threads, level_vec 0
                                or the 16-byte width); > 0 = every wave
-                               stages loads through registers            */
+                               stages loads through registers.  Fused
+                               form: 0 = wave-specialised (four wavefronts
+                               load the next parallels straight into LDS,
+                               the others compute and store; at least 320
+                               threads, 16-byte lanes); 1..3 = every wave
+                               stages loads through registers, each lane
+                               taking that many lane vectors of a node  */
   int32_t level_vec;        /* column, sweep and fused forms: levels per
                                lane.  0 = the level-vector kernels at the
                                automatic width: FP64 16-byte lanes (2
