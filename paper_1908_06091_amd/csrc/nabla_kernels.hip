@@ -1450,16 +1450,25 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         const i32x4 rs = make_rsrc(vin + (size_t)rb * L, (uint32_t)nx * col_bytes);
         const int nitems = len * nvc;
         R *slot = fbuf + sl * fcap;
+        // item i = (node t of the run) x (lane vector k); t and k advance
+        // by whole strides of the calling waves' load instructions
+        const int i0 = w * 64 + lane, di = nwv * 64;
+        int t = i0 / nvc, k = i0 - t * nvc;
+        const int dt = di / nvc, dk = di - dt * nvc;
         for (int b = w; b * 64 < nitems; b += nwv) {
-          const int i = b * 64 + lane;
           int off = kBufOff;
-          if (i < nitems) {
-            const int t = i / nvc, k = i - t * nvc;
+          if (b * 64 + lane < nitems) {
             int ii = lo + t;
             if (ii >= nx) ii -= nx;
             off = ii * (int)col_bytes + min(NV * (v0 + k), nlev - NV) * (int)sizeof(V);
           }
           lds_dma16(rs, slot + b * 64, off);
+          t += dt;
+          k += dk;
+          if (k >= nvc) {
+            k -= nvc;
+            ++t;
+          }
         }
       }
       {
