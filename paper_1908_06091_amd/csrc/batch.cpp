@@ -100,7 +100,19 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   hipEvent_t last = nullptr;
+  // solo items on parallel branches: side streams joined back by events
+  // (used when no item writes memory another item touches)
+  static constexpr int kSide = 3;
+  int nside = 0;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork = nullptr, join[kSide] = {};
+  std::vector<int> solo_lane;   // branch of each solo item (0: the stream)
   ~Batch() {
+    for (int i = 0; i < kSide; ++i) {
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+      if (join[i]) (void)hipEventDestroy(join[i]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -121,11 +133,51 @@ atlas_status enqueue(Batch &b, hipStream_t st) {
                                   b.two_pass, b.d_heads, b.grid, b.block, st);
     if (s != ATLAS_OK) return s;
   }
-  for (const SoloItem &x : b.solo) {
-    atlas_status s = launch_op(*x.m, x.op, b.dtype, x.in, x.nlev, x.out, x.ws, x.sh, st);
+  if (b.nside == 0) {
+    for (const SoloItem &x : b.solo) {
+      atlas_status s = launch_op(*x.m, x.op, b.dtype, x.in, x.nlev, x.out, x.ws, x.sh, st);
+      if (s != ATLAS_OK) return s;
+    }
+    return ATLAS_OK;
+  }
+  ATLASX_HIP(hipEventRecord(b.fork, st));
+  for (int i = 0; i < b.nside; ++i) ATLASX_HIP(hipStreamWaitEvent(b.side[i], b.fork, 0));
+  for (size_t k = 0; k < b.solo.size(); ++k) {
+    const SoloItem &x = b.solo[k];
+    const int lane = b.solo_lane[k];
+    atlas_status s = launch_op(*x.m, x.op, b.dtype, x.in, x.nlev, x.out, x.ws, x.sh,
+                               lane ? b.side[lane - 1] : st);
     if (s != ATLAS_OK) return s;
   }
+  for (int i = 0; i < b.nside; ++i) {
+    ATLASX_HIP(hipEventRecord(b.join[i], b.side[i]));
+    ATLASX_HIP(hipStreamWaitEvent(st, b.join[i], 0));
+  }
   return ATLAS_OK;
+}
+
+// Whether any item writes memory that another item reads or writes (then
+// the solo items keep their order on one stream).
+bool items_overlap(const atlas_work_item *items, int n, atlas_dtype dt) {
+  if (n > 4096) return true;
+  const size_t w = dt == ATLAS_F64 ? 8 : 4;
+  struct R { uintptr_t a, b; int item; bool write; };
+  std::vector<R> r;
+  for (int i = 0; i < n; ++i) {
+    const atlas_work_item &it = items[i];
+    const size_t V = (size_t)it.mesh->store->d.V, L = (size_t)it.nlev;
+    const bool vin = it.op == ATLAS_OP_DIVERGENCE || it.op == ATLAS_OP_CURL;
+    const size_t ib = V * L * w * (vin ? 2 : 1), ob = V * L * w * (it.op == ATLAS_OP_GRADIENT ? 2 : 1);
+    r.push_back({(uintptr_t)it.in, (uintptr_t)it.in + ib, i, false});
+    r.push_back({(uintptr_t)it.out, (uintptr_t)it.out + ob, i, true});
+    if (it.op == ATLAS_OP_LAPLACIAN && it.workspace)
+      r.push_back({(uintptr_t)it.workspace, (uintptr_t)it.workspace + V * L * w * 2, i, true});
+  }
+  for (size_t x = 0; x < r.size(); ++x)
+    for (size_t y = x + 1; y < r.size(); ++y)
+      if (r[x].item != r[y].item && (r[x].write || r[y].write) && r[x].a < r[y].b && r[y].a < r[x].b)
+        return true;
+  return false;
 }
 
 }  // namespace
@@ -465,6 +517,28 @@ atlas_status atlas_batch_build(const atlas_work_item *items, int32_t n,
                      std::max(8, (b->nunits + 7) / 8 * 8));
   if (hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess)
     return bail(fail(ATLAS_EDEVICE, "event"));
+  // solo items on parallel branches, largest first onto the least loaded
+  // (by nnodes * nlev), when the items are independent
+  if (b->solo.size() > 1 && !items_overlap(items, n, dt)) {
+    b->nside = (int)std::min<size_t>(Batch::kSide, b->solo.size() - 1);
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(ATLAS_EDEVICE, "event"));
+    for (int i = 0; i < b->nside; ++i)
+      if (hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) != hipSuccess)
+        return bail(fail(ATLAS_EDEVICE, "side stream"));
+    std::vector<size_t> order(b->solo.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    auto cost = [&](size_t k) { return (int64_t)b->solo[k].m->d.V * b->solo[k].nlev; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(x) > cost(y); });
+    std::vector<int64_t> load(b->nside + 1, 0);
+    b->solo_lane.assign(b->solo.size(), 0);
+    for (size_t k : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->solo_lane[k] = l;
+      load[l] += cost(k);
+    }
+  }
   if (c.use_graph) {
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
       return bail(fail(ATLAS_EDEVICE, "capture stream"));
