@@ -1347,7 +1347,9 @@ constexpr int kSgeoWords = 14;  // packed sweep geometry per position (16-byte
                                 // beta), S[6] / 2, lref[8], ncos[6],
                                 // (cos lat, 0)
 constexpr int kSweepwGroups = 2;     // producer groups (alternate runs)
-constexpr int kSweepwSlots = 5;      // ring slots: runs q-1 .. q+3
+constexpr int kSweepwSlots = 5;      // field ring slots: runs q-1 .. q+3
+constexpr int kSweepwGeoSlots = 4;   // geometry ring slots: runs q .. q+3 (the
+                                     // consumers read only run q's records)
 // Waves per producer group: two for every operator (with the item indices
 // advanced incrementally, a second producer wave made the FP64 divergence
 // sweep faster too: 7.84 -> 7.62 ms at O1280, 137 levels; 2.08 -> 1.97 ms
@@ -1405,7 +1407,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
   constexpr int NPW = kSweepwGroups * kSweepwGroupWaves;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R *fbuf = reinterpret_cast<R *>(smem_raw);                           // [5][fcap]
-  i32x4 *gbuf = reinterpret_cast<i32x4 *>(fbuf + kSweepwSlots * fcap);  // [5][gcap]
+  i32x4 *gbuf = reinterpret_cast<i32x4 *>(fbuf + kSweepwSlots * fcap);  // [4][gcap]
   const int u = xcd_tile(blockIdx.x, per_xcd);
   const int nvec = (nlev + NV - 1) / NV;
   const int nchunk = (nvec + vpc - 1) / vpc;
@@ -1477,7 +1479,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         const i32x4 rs = make_rsrc(m.sgeo + (size_t)plo * kSgeoWords,
                                    (uint32_t)n * kSgeoWords * 16u);
         const int nitems = n * GW;
-        i32x4 *slot = gbuf + sl * gcap;
+        i32x4 *slot = gbuf + (q & (kSweepwGeoSlots - 1)) * gcap;
         for (int b = w; b * 64 < nitems; b += nwv) {
           const int i = b * 64 + lane;
           int off = kBufOff;
@@ -1525,7 +1527,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
     const int sm = sq == 0 ? kSweepwSlots - 1 : sq - 1;  // slot of run q-1
     const int sp = sq == kSweepwSlots - 1 ? 0 : sq + 1;  // slot of run q+1
     const R *fq = fbuf + sq * fcap;
-    const i32x4 *gq = gbuf + sq * gcap;
+    const i32x4 *gq = gbuf + (q & (kSweepwGeoSlots - 1)) * gcap;
     for (int p = plo + cw; p < phi; p += ncw) {
       const i32x4 *g = gq + (p - plo) * GW;
       const i32x4 w0 = g[0], w1 = g[1];
@@ -3011,6 +3013,9 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
 // automatic lane-vector width), and on meshes of many tiles the
 // register-staged sweep for the FP32 gradient (up to 79 levels) and the
 // wave-specialised sweep for the FP64 divergence and curl (below 48).
+size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchunk, int *vpc_out,
+                     int *fcap_out, int *gcap_out);
+
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   LaunchShape s;
   s.variant = nlev >= 24 ? ATLAS_VARIANT_COLUMN : ATLAS_VARIANT_FLAT;
@@ -3071,6 +3076,21 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
       s.blocks_per_cu = 1;
     }
   }
+  if (dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL) && sweepw_fits) {
+    // wave-specialised sweep where its level chunks fill the lanes: two or
+    // three chunks of at least 36 lane vectors (O1280 divergence: 72-91
+    // levels 3.8-4.2 ms against 4.2-5.0; 137 levels 6.25 against 7.00);
+    // else the column form (64 levels: 3.30 against 3.76)
+    int nch = 0, vpc = 0;
+    (void)sweepw_chunks(m.d, kSgeoWords, nlev, 0, &nch, &vpc, nullptr, nullptr);
+    if ((nch == 2 || nch == 3) && vpc >= 36) {
+      s.variant = ATLAS_VARIANT_SWEEP;
+      s.block = 1024;
+      s.nodes_per_block = 0;
+      s.level_vec = 0;
+      return s;
+    }
+  }
   if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && sweep_fits) {
     // wave-specialised sweep, 1024 threads (137 levels at O1280: 5.8 ms
     // against 6.2 ms for the register-staged sweep); without the packed
@@ -3084,6 +3104,32 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
+
+// Level chunking of the wave-specialised sweep: nvec lane vectors per column
+// in nchunk even chunks of vpc (at most 64, or level_chunk's share), more
+// chunks until the field ring (5 slots) and the geometry ring (4 slots of gw
+// words per position) fit in LDS.  Returns the LDS bytes.
+size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchunk, int *vpc_out,
+                     int *fcap_out, int *gcap_out) {
+  int vpc = min(want_vpc > 0 ? want_vpc : 64, nvec);
+  int nch = (nvec + vpc - 1) / vpc;
+  vpc = (nvec + nch - 1) / nch;
+  const int seg = max(1, m.segmax);
+  const int gcap = (seg * gw + 63) / 64 * 64;
+  auto fcap_of = [&](int v) { return (seg * v + 63) / 64 * 64; };
+  auto bytes = [&](int v) {
+    return (size_t)16 * (kSweepwSlots * fcap_of(v) + kSweepwGeoSlots * gcap);
+  };
+  while (vpc > 1 && bytes(vpc) > kMaxLds) {
+    ++nch;
+    vpc = (nvec + nch - 1) / nch;
+  }
+  *nchunk = (nvec + vpc - 1) / vpc;
+  *vpc_out = vpc;
+  if (fcap_out) *fcap_out = fcap_of(vpc);
+  if (gcap_out) *gcap_out = gcap;
+  return bytes(vpc);
+}
 
 int device_cu_count() {
   static int cached[64] = {0};
@@ -3216,24 +3262,11 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
           nlev >= nv16 && m.maxdeg <= 6 && m.mindeg >= kMinRow && sh.block >= 512 &&
           sh.block % 64 == 0) {
         const int nvec = (nlev + nv16 - 1) / nv16;
-        int vpc = sh.level_chunk > 0 ? min(64, (sh.level_chunk + nv16 - 1) / nv16) : 64;
-        vpc = min(vpc, nvec);
-        {
-          const int nchunk = (nvec + vpc - 1) / vpc;
-          vpc = (nvec + nchunk - 1) / nchunk;
-        }
-        const int seg = max(1, m.segmax);
         constexpr int gw = Pol<T, OP>::kVecIn ? kSgeoWords : 10;
-        const int gcap = (seg * gw + 63) / 64 * 64;
-        auto fcap_of = [&](int v) { return (seg * v + 63) / 64 * 64; };
-        // more chunks (each an even share of the lane vectors) until the
-        // five slots fit in LDS
-        for (int nch = (nvec + vpc - 1) / vpc;
-             vpc > 1 && (size_t)kSweepwSlots * 16 * (fcap_of(vpc) + gcap) > kMaxLds;) {
-          ++nch;
-          vpc = (nvec + nch - 1) / nch;
-        }
-        const size_t lds = (size_t)kSweepwSlots * 16 * (fcap_of(vpc) + gcap);
+        int nchunk0 = 0, vpc = 0, fcap = 0, gcap = 0;
+        const size_t lds = sweepw_chunks(m, gw, nvec,
+                                         sh.level_chunk > 0 ? (sh.level_chunk + nv16 - 1) / nv16 : 0,
+                                         &nchunk0, &vpc, &fcap, &gcap);
         if (lds > kMaxLds) return fail(ATLAS_EINVAL, "sweep tile too large for LDS");
         const int nchunk = (nvec + vpc - 1) / vpc;
         const int units = m.ntiles * nchunk;
@@ -3244,7 +3277,7 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(kern, dim3(per * 8), block, lds, st, m, in, out, nlev, vpc, m.ntiles,
-                           per, fcap_of(vpc), gcap);
+                           per, fcap, gcap);
         break;
       }
       int nv = sh.level_vec == 1 ? 0
