@@ -1392,7 +1392,7 @@ __device__ __forceinline__ void sweep_term(typename Pol<T, OP>::St &s,
   }
 }
 
-template <class T, int OP, int NV>
+template <class T, int OP, int NV, int NPN>
 __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict__ in,
                                                  T *__restrict__ out, int nlev, int vpc,
                                                  int ntiles, int per_xcd, int fcap, int gcap) {
@@ -1518,9 +1518,14 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
   const int cw = wave - NPW, ncw = nw - NPW;
-  const int kc = min(lane, nvc - 1);  // lanes past the chunk read a valid entry
+  // NPN positions per wavefront, 64 / NPN lanes each (chunks of at most
+  // 64 / NPN lane vectors)
+  constexpr int LPN = 64 / NPN;
+  const int sub = NPN > 1 ? lane / LPN : 0;
+  const int hl = lane - sub * LPN;
+  const int kc = min(hl, nvc - 1);  // lanes past the chunk read a valid entry
   const int s_l = min(NV * (v0 + kc), nlev - NV);
-  const bool lane_on = lane < nvc;
+  const bool lane_on = hl < nvc;
   int sq = qa % kSweepwSlots;           // slot of run q
   for (int q = qa; q <= qb; ++q) {
     const int plo = run_lo(q), phi = run_hi(q);
@@ -1528,7 +1533,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
     const int sp = sq == kSweepwSlots - 1 ? 0 : sq + 1;  // slot of run q+1
     const R *fq = fbuf + sq * fcap;
     const i32x4 *gq = gbuf + (q & (kSweepwGeoSlots - 1)) * gcap;
-    for (int p = plo + cw; p < phi; p += ncw) {
+    for (int p = plo + NPN * cw + sub; p < phi; p += NPN * ncw) {
       const i32x4 *g = gq + (p - plo) * GW;
       const i32x4 w0 = g[0], w1 = g[1];
       const int node = w0.x, n = w0.y, selfslot = w0.z;
@@ -1606,8 +1611,6 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
           P::keep(st[v], tt, use);
         }
       }
-      const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
-                                 (uint32_t)(L * sizeof(Out)));
       constexpr int W = NV * (int)sizeof(Out) / 4;
       int wd[W];
 #pragma unroll
@@ -1615,8 +1618,20 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         const Out r = P::result(st[v], al, be, cx, cy, ci);
         __builtin_memcpy(&wd[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
       }
-      const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
-      buf_store_words<W>(wd, ro, ob);
+      if constexpr (NPN == 1) {
+        // one position per wavefront: a buffer store over its row (the
+        // resource is wavefront-uniform)
+        const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
+                                   (uint32_t)(L * sizeof(Out)));
+        const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
+        buf_store_words<W>(wd, ro, ob);
+      } else if (lane_on) {
+        // several positions per wavefront: a store through each lane's own
+        // address
+        struct Words { int v[W]; } o;
+        __builtin_memcpy(o.v, wd, sizeof(o));
+        *reinterpret_cast<Words *>(out + ((size_t)node * L + s_l) * (sizeof(Out) / sizeof(T))) = o;
+      }
     }
     // this step's LDS reads are done before the producers refill a slot
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -3077,13 +3092,15 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
     }
   }
   if (dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL) && sweepw_fits) {
-    // wave-specialised sweep where its level chunks fill the lanes: two or
-    // three chunks of at least 36 lane vectors (O1280 divergence: 72-91
-    // levels 3.8-4.2 ms against 4.2-5.0; 137 levels 6.25 against 7.00);
-    // else the column form (64 levels: 3.30 against 3.76)
+    // wave-specialised sweep where its level chunks fill the lanes: at most
+    // three chunks, each of at least 36 lane vectors or of 24-32 (two
+    // positions per wavefront).  O1280 divergence: 48 / 64 levels 2.74 /
+    // 2.95 ms against 2.96 / 3.32 for the column form, 72-91 levels 3.8-4.2
+    // against 4.2-5.0, 137 levels 6.25 against 7.00; the column form at
+    // 100 levels (three chunks of 34: 5.74 against 5.08) and from 150
     int nch = 0, vpc = 0;
     (void)sweepw_chunks(m.d, kSgeoWords, nlev, 0, &nch, &vpc, nullptr, nullptr);
-    if ((nch == 2 || nch == 3) && vpc >= 36) {
+    if (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))) {
       s.variant = ATLAS_VARIANT_SWEEP;
       s.block = 1024;
       s.nodes_per_block = 0;
@@ -3272,7 +3289,9 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
         const int units = m.ntiles * nchunk;
         const int per = (units + 7) / 8;
         void (*kern)(DevMesh, const T *, T *, int, int, int, int, int, int) = nullptr;
-        if constexpr (lane_vec_ok<T, OP, nv16>()) kern = k_sweepw<T, OP, nv16>;
+        // two positions per wavefront when a chunk fills at most half of it
+        if constexpr (lane_vec_ok<T, OP, nv16>())
+          kern = vpc <= 32 ? k_sweepw<T, OP, nv16, 2> : k_sweepw<T, OP, nv16, 1>;
         if (!kern) return fail(ATLAS_EINVAL, "wave-specialised sweep not available");
         ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
