@@ -203,3 +203,32 @@ def test_mixed_grid_batch_forms_match_oracle(P):
         worst = max(worst, emax)
         assert emax <= TOL["f32"], (N, op, nlev, emax)
     print(f"mixed-grid batch: worst max_rel vs oracle {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_dependent_solo_items_keep_their_order(P, meshes, use_graph):
+    """Items launched on their own run on parallel branches only when no
+    item writes memory another touches.  Here item 1 reads item 0's output
+    (a gradient, then its divergence) and items 2 and 3 write the same
+    buffer, so the batch keeps the items' order: the results are those of
+    the calls made one after another."""
+    print(f"dependent solo items graph={use_graph}", flush=True)
+    gm = meshes[24]
+    f = torch.randn(gm.nnodes, 10, dtype=torch.float64, device="cuda")
+    g = torch.full((gm.nnodes, 10, 2), float("nan"), dtype=torch.float64, device="cuda")
+    d = torch.full((gm.nnodes, 10), float("nan"), dtype=torch.float64, device="cuda")
+    uv = torch.randn(gm.nnodes, 10, 2, dtype=torch.float64, device="cuda")
+    shared = torch.full((gm.nnodes, 10), float("nan"), dtype=torch.float64, device="cuda")
+    items = [(gm, P.ATLAS_OP_GRADIENT, f, g), (gm, P.ATLAS_OP_DIVERGENCE, g, d),
+             (gm, P.ATLAS_OP_DIVERGENCE, uv, shared), (gm, P.ATLAS_OP_CURL, uv, shared)]
+    b = P.Batch(items, use_graph=use_graph, solo_min_elems=1)
+    assert b.info.solo_items == 4
+    for _ in range(2):
+        b.launch()
+        b.check()
+        assert torch.equal(g, gm.gradient(f))
+        assert torch.equal(d, gm.divergence(gm.gradient(f)))
+        assert torch.equal(shared, gm.curl(uv))
+        g.fill_(float("nan"))
+        d.fill_(float("nan"))
+        shared.fill_(float("nan"))
