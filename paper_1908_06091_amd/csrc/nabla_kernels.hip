@@ -1392,11 +1392,16 @@ __device__ __forceinline__ void sweep_term(typename Pol<T, OP>::St &s,
   }
 }
 
-template <class T, int OP, int NV, int NPN>
+// DC (OP = OP_DIV only): the curl of the same field as well, into out2,
+// from the same loads; each output bitwise that of its own operator.
+template <class T, int OP, int NV, int NPN, bool DC = false>
 __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict__ in,
-                                                 T *__restrict__ out, int nlev, int vpc,
-                                                 int ntiles, int per_xcd, int fcap, int gcap) {
+                                                 T *__restrict__ out, T *__restrict__ out2,
+                                                 int nlev, int vpc, int ntiles, int per_xcd,
+                                                 int fcap, int gcap) {
+  static_assert(!DC || OP == OP_DIV, "the one-pass curl rides on the divergence");
   using P = Pol<T, OP>;
+  using PC = Pol<T, OP_CURL>;
   using V = typename P::V;
   using LV = LaneVec<V, NV>;
   using R = typename LV::raw;
@@ -1573,10 +1578,15 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         for (int j = 0; j < G; ++j) cn[j] = 0.0;
       }
       typename P::St st[NV];
+      typename PC::St stc[DC ? NV : 1];
       {
         const R xi = fq[selfslot * nvc + kc];
 #pragma unroll
         for (int v = 0; v < NV; ++v) P::init(st[v], LV::get(xi, v), ci);
+        if constexpr (DC) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) PC::init(stc[v], LV::get(xi, v), ci);
+        }
       }
       R xn[G];
 #pragma unroll
@@ -1587,14 +1597,21 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         xn[j] = fbuf[sl * fcap + (l & 0xffff) * nvc + kc];
       }
       double cx = 0.0, cy = 0.0;  // closure sums (FP32 forms): full normals
+      double ccx = 0.0, ccy = 0.0;  // the curl's (DC)
 #pragma unroll
       for (int j = 0; j < G; ++j) {
         const bool pole = (lr[j] & kLrefPole) != 0;
         const double2 S2 = make_double2(Sh[j].x + Sh[j].x, Sh[j].y + Sh[j].y);
         if (j < kMinRow) {  // present in every row, never the pole edge
           if constexpr (sizeof(T) == 4) closure_add<P::kOp>(cx, cy, S2, false);
+          if constexpr (sizeof(T) == 4 && DC) closure_add<OP_CURL>(ccx, ccy, S2, false);
 #pragma unroll
           for (int v = 0; v < NV; ++v) sweep_term<T, OP>(st[v], LV::get(xn[j], v), Sh[j], false, cn[j]);
+          if constexpr (DC) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              sweep_term<T, OP_CURL>(stc[v], LV::get(xn[j], v), Sh[j], false, cn[j]);
+          }
           continue;
         }
         const bool use = j < n && !(P::kVecIn && pole);
@@ -1603,12 +1620,26 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
           closure_add<P::kOp>(tx, ty, S2, pole);
           cx = use ? tx : cx;
           cy = use ? ty : cy;
+          if constexpr (DC) {
+            double ux = ccx, uy = ccy;
+            closure_add<OP_CURL>(ux, uy, S2, pole);
+            ccx = use ? ux : ccx;
+            ccy = use ? uy : ccy;
+          }
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           typename P::St tt = st[v];
           sweep_term<T, OP>(tt, LV::get(xn[j], v), Sh[j], pole, cn[j]);
           P::keep(st[v], tt, use);
+        }
+        if constexpr (DC) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            typename PC::St tt = stc[v];
+            sweep_term<T, OP_CURL>(tt, LV::get(xn[j], v), Sh[j], pole, cn[j]);
+            PC::keep(stc[v], tt, use);
+          }
         }
       }
       constexpr int W = NV * (int)sizeof(Out) / 4;
@@ -1618,19 +1649,32 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         const Out r = P::result(st[v], al, be, cx, cy, ci);
         __builtin_memcpy(&wd[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
       }
-      if constexpr (NPN == 1) {
-        // one position per wavefront: a buffer store over its row (the
-        // resource is wavefront-uniform)
-        const i32x4 ro = make_rsrc(out + (size_t)node * L * (sizeof(Out) / sizeof(T)),
-                                   (uint32_t)(L * sizeof(Out)));
-        const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
-        buf_store_words<W>(wd, ro, ob);
-      } else if (lane_on) {
-        // several positions per wavefront: a store through each lane's own
-        // address
-        struct Words { int v[W]; } o;
-        __builtin_memcpy(o.v, wd, sizeof(o));
-        *reinterpret_cast<Words *>(out + ((size_t)node * L + s_l) * (sizeof(Out) / sizeof(T))) = o;
+      auto store_row = [&](T *dst, const int (&w)[W]) {
+        if constexpr (NPN == 1) {
+          // one position per wavefront: a buffer store over its row (the
+          // resource is wavefront-uniform)
+          const i32x4 ro = make_rsrc(dst + (size_t)node * L * (sizeof(Out) / sizeof(T)),
+                                     (uint32_t)(L * sizeof(Out)));
+          const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
+          buf_store_words<W>(w, ro, ob);
+        } else if (lane_on) {
+          // several positions per wavefront: a store through each lane's
+          // own address
+          struct Words { int v[W]; } o;
+          __builtin_memcpy(o.v, w, sizeof(o));
+          *reinterpret_cast<Words *>(dst + ((size_t)node * L + s_l) * (sizeof(Out) / sizeof(T))) = o;
+        }
+      };
+      store_row(out, wd);
+      if constexpr (DC) {
+        static_assert(sizeof(typename PC::Out) == sizeof(Out), "curl output type");
+        int wc[W];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const typename PC::Out r = PC::result(stc[v], al, be, ccx, ccy, ci);
+          __builtin_memcpy(&wc[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
+        }
+        store_row(out2, wc);
       }
     }
     // this step's LDS reads are done before the producers refill a slot
@@ -3169,6 +3213,45 @@ static int sweep_chunk(int nlev, int want) {
   return (nlev + n - 1) / n;
 }
 
+// Whether a sweep shape runs the wave-specialised kernel: blocks_per_cu 0,
+// the packed geometry, 16-byte lane vectors, rows of 4..6 incidences and a
+// block of at least 512 threads.
+template <class T, int OP>
+static bool sweepw_applies(const DevMesh &m, int nlev, const LaunchShape &sh) {
+  constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP>::V);
+  return sh.blocks_per_cu == 0 && m.sgeo && (sh.level_vec == 0 || sh.level_vec == nv16) &&
+         nlev >= nv16 && m.maxdeg <= 6 && m.mindeg >= kMinRow && sh.block >= 512 &&
+         sh.block % 64 == 0;
+}
+
+// The wave-specialised sweep of `sh` (sweepw_applies); DC: the divergence
+// and, into out2, the curl of the same field in one pass.
+template <class T, int OP, bool DC>
+static atlas_status launch_sweepw(const DevMesh &m, const T *in, T *out, T *out2, int nlev,
+                                  const LaunchShape &sh, hipStream_t st) {
+  constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP>::V);
+  const int nvec = (nlev + nv16 - 1) / nv16;
+  constexpr int gw = Pol<T, OP>::kVecIn ? kSgeoWords : 10;
+  int nchunk = 0, vpc = 0, fcap = 0, gcap = 0;
+  const size_t lds = sweepw_chunks(m, gw, nvec,
+                                   sh.level_chunk > 0 ? (sh.level_chunk + nv16 - 1) / nv16 : 0,
+                                   &nchunk, &vpc, &fcap, &gcap);
+  if (lds > kMaxLds) return fail(ATLAS_EINVAL, "sweep tile too large for LDS");
+  const int units = m.ntiles * nchunk;
+  const int per = (units + 7) / 8;
+  void (*kern)(DevMesh, const T *, T *, T *, int, int, int, int, int, int) = nullptr;
+  // two positions per wavefront when a chunk fills at most half of it
+  if constexpr (lane_vec_ok<T, OP, nv16>())
+    kern = vpc <= 32 ? k_sweepw<T, OP, nv16, 2, DC> : k_sweepw<T, OP, nv16, 1, DC>;
+  if (!kern) return fail(ATLAS_EINVAL, "wave-specialised sweep not available");
+  ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3(per * 8), dim3(sh.block), lds, st, m, in, out, out2, nlev, vpc,
+                     m.ntiles, per, fcap, gcap);
+  ATLASX_HIP(hipGetLastError());
+  return ATLAS_OK;
+}
+
 template <class T, int OP>
 static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *out, void *ws,
                                  const LaunchShape &sh, hipStream_t st,
@@ -3274,29 +3357,9 @@ static atlas_status launch_typed(const MeshStore &ms, const T *in, int nlev, T *
       // thread per 16-byte word: it needs a block of segmax * kGeoWords
       // threads, else the one-level-per-lane sweep runs (same results)
       // wave-specialised sweep (blocks_per_cu == 0): 16-byte lane vectors
-      constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP>::V);
-      if (sh.blocks_per_cu == 0 && m.sgeo && (sh.level_vec == 0 || sh.level_vec == nv16) &&
-          nlev >= nv16 && m.maxdeg <= 6 && m.mindeg >= kMinRow && sh.block >= 512 &&
-          sh.block % 64 == 0) {
-        const int nvec = (nlev + nv16 - 1) / nv16;
-        constexpr int gw = Pol<T, OP>::kVecIn ? kSgeoWords : 10;
-        int nchunk0 = 0, vpc = 0, fcap = 0, gcap = 0;
-        const size_t lds = sweepw_chunks(m, gw, nvec,
-                                         sh.level_chunk > 0 ? (sh.level_chunk + nv16 - 1) / nv16 : 0,
-                                         &nchunk0, &vpc, &fcap, &gcap);
-        if (lds > kMaxLds) return fail(ATLAS_EINVAL, "sweep tile too large for LDS");
-        const int nchunk = (nvec + vpc - 1) / vpc;
-        const int units = m.ntiles * nchunk;
-        const int per = (units + 7) / 8;
-        void (*kern)(DevMesh, const T *, T *, int, int, int, int, int, int) = nullptr;
-        // two positions per wavefront when a chunk fills at most half of it
-        if constexpr (lane_vec_ok<T, OP, nv16>())
-          kern = vpc <= 32 ? k_sweepw<T, OP, nv16, 2> : k_sweepw<T, OP, nv16, 1>;
-        if (!kern) return fail(ATLAS_EINVAL, "wave-specialised sweep not available");
-        ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kern, dim3(per * 8), block, lds, st, m, in, out, nlev, vpc, m.ntiles,
-                           per, fcap, gcap);
+      if (sweepw_applies<T, OP>(m, nlev, sh)) {
+        atlas_status s = launch_sweepw<T, OP, false>(m, in, out, nullptr, nlev, sh, st);
+        if (s != ATLAS_OK) return s;
         break;
       }
       int nv = sh.level_vec == 1 ? 0
@@ -3413,6 +3476,13 @@ template <class T>
 static atlas_status launch_div_curl_typed(const MeshStore &ms, atlas_dtype dt, const T *in,
                                           int nlev, T *od, T *oc, hipStream_t st) {
   const DevMesh &m = ms.d;
+  {
+    // where the divergence runs the wave-specialised sweep, the curl rides
+    // on the same loads
+    const LaunchShape sh = shape_from(nullptr, ms, ATLAS_OP_DIVERGENCE, nlev, dt);
+    if (sh.variant == ATLAS_VARIANT_SWEEP && sweepw_applies<T, OP_DIV>(m, nlev, sh))
+      return launch_sweepw<T, OP_DIV, true>(m, in, od, oc, nlev, sh, st);
+  }
   const int nv = nlev >= 48 ? auto_level_vec<T, OP_DIV>(nlev, m.maxdeg, m.mindeg) : 0;
   if (nv == 0) {
     for (atlas_op op : {ATLAS_OP_DIVERGENCE, ATLAS_OP_CURL}) {

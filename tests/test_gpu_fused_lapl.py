@@ -147,3 +147,18 @@ def test_div_curl_rejects_overlapping_outputs(P):
     o = torch.empty(gm.nnodes, 4, dtype=torch.float64, device="cuda")
     with pytest.raises(P.AtlasError, match="overlap"):
         gm.div_curl(uv, out_div=o, out_curl=o)
+
+
+@pytest.mark.parametrize("nlev", [24, 37, 48, 64, 91, 137])
+def test_div_curl_on_the_sweep_equals_separate_calls(P, nlev):
+    """O640 (over a thousand tiles): where the FP64 divergence runs the
+    wave-specialised sweep, the curl rides on its loads (one or two
+    positions per wavefront, one to three level chunks); both outputs are
+    bitwise the separate operators' results."""
+    print(f"div_curl sweep O640 nlev={nlev}", flush=True)
+    gm = _mesh(P, 640)
+    uv = torch.randn(gm.nnodes, nlev, 2, dtype=torch.float64, device="cuda")
+    d, c = gm.div_curl(uv)
+    torch.cuda.synchronize()
+    assert torch.equal(d, gm.divergence(uv))
+    assert torch.equal(c, gm.curl(uv))
