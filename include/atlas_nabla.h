@@ -290,7 +290,14 @@ typedef struct {
   int32_t variant;          /* atlas_variant                                */
   int32_t block_threads;    /* 64, 128, 256, 512 or 1024                    */
   int32_t nodes_per_block;  /* column/flat: processing positions per block;
-                               0 = the mesh's tiles                         */
+                               0 = the mesh's tiles.  Fused form,
+                               wave-specialised: 4 or 5 = slots of its ring
+                               of field runs (4: each run is loaded one step
+                               before use instead of one and a half, and a
+                               longer level chunk fits in LDS); 0 = five, or
+                               four where five would need one more level
+                               chunk; other values run the register-staged
+                               form                                         */
   int32_t level_chunk;      /* column: levels per unit of work (1..64); the
                                units run chunk by chunk over the whole mesh
                                so a parallel's columns are still cached when

@@ -2157,14 +2157,18 @@ __global__ void __launch_bounds__(1024) k_lsweep(DevMesh m, const T *__restrict_
 // parallels q-2, q-1, q.  Load set k = {field run k+1, geometry of step k
 // (g records of parallel k, own records of parallel k-1)} is issued at step
 // k-2 by group k mod 2 and waited for by that group at the end of step
-// k-1: field ring 5 slots, geometry ring 3, gradient ring 3.  References
-// in the packed records are resolved at use (the deposit of the
-// register-staged kernel resolved them once).
+// k-1: field ring 5 slots, geometry ring 3, gradient ring 3.  With FS = 4
+// field slots the field run of set k is issued after the mid-step barrier
+// of step k-2 instead (the gradients of that step have then finished
+// reading the slot it takes), one step before it is read rather than one
+// and a half: the ring holds one parallel of columns less, so a longer
+// level chunk fits in LDS.  References in the packed records are resolved
+// once the set has landed, into LDS offsets.
 // ---------------------------------------------------------------------------
 constexpr int kLswFSlots = 5, kLswGSlots = 3, kLswGeoSlots = 3;
 constexpr int kLswProducers = 4;  // two groups of two wavefronts
 
-template <class T, int NV>
+template <class T, int NV, int FS = kLswFSlots>
 __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict__ in,
                                                   T *__restrict__ out, int nlev, int vpc,
                                                   int ntiles, int per_xcd, int lpn, int fcap,
@@ -2178,6 +2182,7 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
   using RG = typename LG::raw;
   static_assert(sizeof(RF) == 16, "wave-specialised fused Laplacian: 16-byte lane vectors");
   static_assert(sizeof(RG) == 2 * sizeof(RF), "gradient lane vector = two field lane vectors");
+  static_assert(FS == 4 || FS == 5, "field ring of four or five slots");
   constexpr int G = 6;
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int LGW = F64 ? kLGeoWords64 : kLGeoWords;
@@ -2185,8 +2190,8 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
   const int gmax = m.l2_gmax;
   const int gstride = 2 * gmax * vpc;   // gradient slot (field lane vectors)
   const int geo_stride = gcap + ocap;   // geometry slot (16-byte words)
-  RF *fbuf = reinterpret_cast<RF *>(smem_raw);                         // [5][fcap]
-  RF *gbuf = fbuf + kLswFSlots * fcap;                                 // [3][gmax][2][vpc]
+  RF *fbuf = reinterpret_cast<RF *>(smem_raw);                         // [FS][fcap]
+  RF *gbuf = fbuf + FS * fcap;                                         // [3][gmax][2][vpc]
   i32x4 *geo = reinterpret_cast<i32x4 *>(gbuf + kLswGSlots * gstride);  // [3][gcap + ocap]
   const int u = xcd_tile(blockIdx.x, per_xcd);
   const int nvec = (nlev + NV - 1) / NV;
@@ -2212,14 +2217,14 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
     // field runs, so every wave waits only for the loads it issued ---------
     const int grp = wave >> 1;
     const bool geo_wave = (wave & 1) == 0;
-    // field run q into slot q mod 5: item i = (node t of the run) x (lane
+    // field run q into slot q mod FS: item i = (node t of the run) x (lane
     // vector kk); t and kk advance by whole load instructions
     auto load_f = [&](int q) {
       if (q < 0 || q >= W) return;
       const int4 f = cst_int4(m.l2_fseg, k0 + q);  // {ring offset, ring size, first, length}
       const i32x4 rs = make_rsrc(in + (size_t)f.x * L, (uint32_t)f.y * col_bytes);
       const int nitems = f.w * nvc;
-      RF *slot = fbuf + (q % kLswFSlots) * fcap;
+      RF *slot = fbuf + (q % FS) * fcap;
       int t = lane / nvc, kk = lane - t * nvc;
       const int dt = 64 / nvc, dk = 64 - dt * nvc;
       for (int b = 0; b * 64 < nitems; ++b) {
@@ -2308,8 +2313,8 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
       if (k < 0 || k > W) return;
       i32x4 *gs = geo + (k % kLswGeoSlots) * geo_stride;
       if (k < W) {
-        const int b0 = ((k + kLswFSlots - 1) % kLswFSlots) * fcap;
-        const int b1 = (k % kLswFSlots) * fcap, b2 = ((k + 1) % kLswFSlots) * fcap;
+        const int b0 = ((k + FS - 1) % FS) * fcap;
+        const int b1 = (k % FS) * fcap, b2 = ((k + 1) % FS) * fcap;
         auto rf = [&](int v) {
           const int l = v & ~kLrefPole, dq = (l >> 16) & 3;
           return (v & kLrefPole) | ((dq == 0 ? b0 : dq == 1 ? b1 : b2) + (l & 0xffff) * nvc);
@@ -2367,13 +2372,16 @@ __global__ void __launch_bounds__(1024) k_lsweepw(DevMesh m, const T *__restrict
         if (geo_wave) {
           load_refs(q + 2);
           load_g(q + 2);
-        } else {
+        } else if (FS == 5) {
           load_f(q + 3);
         }
       }
       asm volatile("" ::: "memory");
       __builtin_amdgcn_s_barrier();  // between the consumers' two phases
       asm volatile("" ::: "memory");
+      // four slots: field run q + 3 takes the slot of run q - 1, which the
+      // gradients of step q (runs q - 1 .. q + 1) have finished reading
+      if (FS == 4 && (q & 1) == grp && !geo_wave) load_f(q + 3);
       // set q + 1 (issued at step q - 1 by this group; sets 0 and 1 came
       // with the prologue) lands, and is resolved, before step q + 1
       if (((q + 1) & 1) == grp && q >= 1) {
@@ -3579,9 +3587,12 @@ static bool fused_plan(const MeshStore &ms, int nlev, const LaunchShape &sh, Fus
 
 // The wave-specialised fused Laplacian's plan (blocks_per_cu 0, 16-byte
 // lanes, at least one consumer wavefront): the level chunk shrinks until
-// the three rings fit in LDS; false where it cannot run.
+// the three rings fit in LDS; false where it cannot run.  The field ring
+// has five slots, or four where five would take one more level chunk
+// (FP64 at 137 levels on O1280's tiles: three chunks of 23 lane vectors
+// instead of four of 18); nodes_per_block 4 or 5 sets it.
 struct FusedwPlan {
-  int vpc, nchunk, fcap, gcap, ocap;
+  int vpc, nchunk, fcap, gcap, ocap, fslots;
   size_t lds;
 };
 template <class T>
@@ -3600,22 +3611,29 @@ static bool fusedw_plan(const MeshStore &ms, int nlev, const LaunchShape &sh, Fu
   auto r64 = [](int64_t x) { return (int)((x + 63) / 64 * 64); };
   const int LGW = sizeof(T) == 8 ? kLGeoWords64 : kLGeoWords;
   const int gcap = r64((int64_t)m.l2_gmax * kGGeoWords), ocap = r64((int64_t)m.l2_pmax * LGW);
-  auto bytes = [&](int v) {
-    return (size_t)16 * ((size_t)kLswFSlots * r64((int64_t)m.l2_fmax * v) +
+  auto bytes = [&](int v, int fs) {
+    return (size_t)16 * ((size_t)fs * r64((int64_t)m.l2_fmax * v) +
                          (size_t)kLswGSlots * 2 * m.l2_gmax * v +
                          (size_t)kLswGeoSlots * (gcap + ocap));
   };
-  while (vpc > 1 && bytes(vpc) > kMaxLds) {
+  if (sh.nodes_per_block != 0 && sh.nodes_per_block != 4 && sh.nodes_per_block != 5) return false;
+  int fs = sh.nodes_per_block ? sh.nodes_per_block : kLswFSlots;
+  while (vpc > 1 && bytes(vpc, fs) > kMaxLds) {
+    if (!sh.nodes_per_block && fs == kLswFSlots && bytes(vpc, 4) <= kMaxLds) {
+      fs = 4;  // four slots save this chunk
+      break;
+    }
     ++nch;
     vpc = (nvec + nch - 1) / nch;
   }
-  if (bytes(vpc) > kMaxLds) return false;
+  if (bytes(vpc, fs) > kMaxLds) return false;
   fp->vpc = vpc;
   fp->nchunk = (nvec + vpc - 1) / vpc;
   fp->fcap = r64((int64_t)m.l2_fmax * vpc);
   fp->gcap = gcap;
   fp->ocap = ocap;
-  fp->lds = bytes(vpc);
+  fp->fslots = fs;
+  fp->lds = bytes(vpc, fs);
   return true;
 }
 
@@ -3642,7 +3660,7 @@ atlas_status launch_lapl_fused(const MeshStore &ms, const T *in, int nlev, T *ou
     // per node
     const int units = m.ntiles * fw.nchunk;
     const int per = (units + 7) / 8;
-    auto kern = k_lsweepw<T, NVW>;
+    auto kern = fw.fslots == 4 ? k_lsweepw<T, NVW, 4> : k_lsweepw<T, NVW, 5>;
     ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fw.lds));
     hipLaunchKernelGGL(kern, dim3(per * 8), dim3(sh.block), fw.lds, st, m, in, out, nlev, fw.vpc,

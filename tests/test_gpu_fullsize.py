@@ -121,7 +121,15 @@ def test_o1280_l137_laplacian_forms_and_div_curl(big, dtype):
     two = gm.apply(P.ATLAS_OP_LAPLACIAN, f, launch=P.Launch(P.VARIANT_COLUMN, 256, 16, 0, 0, 0))
     torch.cuda.synchronize()
     assert torch.equal(one, two)
-    del one, two, f
+    del one
+    # the field ring forced to five slots (the automatic choice takes four
+    # where that saves a level chunk: FP64 here) and to four
+    for fslots in (4, 5):
+        one = gm.apply(P.ATLAS_OP_LAPLACIAN, f, launch=P.Launch(P.VARIANT_FUSED, 1024, fslots, 0, 0, 0))
+        torch.cuda.synchronize()
+        assert torch.equal(one, two), fslots
+        del one
+    del two, f
     uv = big["uv"].to(dt)
     d, c = gm.div_curl(uv)
     torch.cuda.synchronize()

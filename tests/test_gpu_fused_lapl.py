@@ -94,6 +94,41 @@ def test_fused_blocks_and_chunks(P, block, level_chunk):
     assert torch.equal(_lapl(P, gm, x, _fused(P, block, level_chunk)), two)
 
 
+@pytest.mark.parametrize("fslots", [4, 5])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nlev", [2, 37, 137, 300])
+@pytest.mark.parametrize("N", [8, 24, 48])
+def test_fused_field_ring_slots(P, N, nlev, dtype, fslots):
+    """The wave-specialised kernel with its field ring forced to four slots
+    (each field run loaded one step ahead) or five (one and a half): the
+    bits of the two passes, and the oracle's values."""
+    print(f"fused lapl ring={fslots} O{N} nlev={nlev} {dtype}", flush=True)
+    gm = _mesh(P, N)
+    om = _oracle_mesh(N)
+    f, _ = make_inputs(om, nlev)
+    if dtype == torch.float32:
+        f = f.astype(np.float32).astype(np.float64)
+    x = torch.from_numpy(f).to(dtype=dtype, device="cuda").contiguous()
+    two = _lapl(P, gm, x, P.Launch(P.VARIANT_COLUMN, 256, 16, 0, 0, 0))
+    one = _lapl(P, gm, x, P.Launch(P.VARIANT_FUSED, 1024, fslots, 0, 0, 0))
+    assert torch.equal(one, two)
+    ref = oracle_apply(om, "lapl", f, nlev)
+    err, _ = normwise_error(one.double().cpu().numpy().reshape(ref.shape), ref)
+    assert err <= TOL["f64" if dtype == torch.float64 else "f32"], err
+
+
+@pytest.mark.parametrize("layout", [(1, 1), (2, 3), (64, 64)])
+@pytest.mark.parametrize("level_chunk", [0, 8])
+def test_fused_four_slot_ring_layouts_and_chunks(P, layout, level_chunk):
+    """Four field slots on tiles of one node, thin bands and tiles wider
+    than the mesh, with one and several level chunks."""
+    print(f"fused lapl ring=4 layout={layout} level_chunk={level_chunk}", flush=True)
+    gm = _mesh(P, 16, layout)
+    x = torch.randn(gm.nnodes, 45, dtype=torch.float64, device="cuda")
+    two = _lapl(P, gm, x, P.Launch(P.VARIANT_COLUMN, 256, 16, 0, 0, 0))
+    assert torch.equal(_lapl(P, gm, x, P.Launch(P.VARIANT_FUSED, 1024, 4, level_chunk, 0, 0)), two)
+
+
 def test_fused_repeated_and_into_nan_output(P):
     gm = _mesh(P, 24)
     x = torch.randn(gm.nnodes, 91, dtype=torch.float64, device="cuda")
