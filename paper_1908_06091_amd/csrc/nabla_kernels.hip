@@ -1529,14 +1529,45 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
   const int sub = NPN > 1 ? lane / LPN : 0;
   const int hl = lane - sub * LPN;
   const int kc = min(hl, nvc - 1);  // lanes past the chunk read a valid entry
-  const int s_l = min(NV * (v0 + kc), nlev - NV);
   const bool lane_on = hl < nvc;
+  // Lanes whose results exceed 16 bytes (the gradient: two components at
+  // NV levels) would make every store instruction strided, each lane
+  // writing part of its own piece of the row.  Such a lane takes NG groups
+  // of GS adjacent levels (16 bytes of output each), one from each of the
+  // chunk's NG equal parts: group g holds level slots g GS nvc + GS kc + e,
+  // so the g-th store of the lanes covers one contiguous run of the row.
+  // Every level goes through the same arithmetic: the bits are unchanged.
+  constexpr bool kSplit = NV * sizeof(Out) > 16;
+  constexpr int GS = kSplit ? (int)(16 / sizeof(Out)) : NV;  // levels per group
+  constexpr int NG = NV / GS;
+  static_assert(!kSplit || (ElemOf<V>::C == 1 && NV % GS == 0), "split lanes: scalar inputs");
+  int s_g[NG];  // first output level of each group
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int p = kSplit ? g * GS * nvc + GS * kc : NV * kc;  // slot in the chunk
+    s_g[g] = min(NV * (v0 + p / NV), nlev - NV) + p % NV;
+  }
+  // the lane's NV levels of the chunk row starting at lane vector `base`
+  auto ldrow = [&](int base) {
+    if constexpr (kSplit) {
+      struct Grp { typename ElemOf<V>::E e[GS]; };
+      const Grp *fv = reinterpret_cast<const Grp *>(fbuf + base);
+      R r;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const Grp x = fv[g * nvc + kc];
+        __builtin_memcpy(&r.e[g * GS], x.e, sizeof(Grp));
+      }
+      return r;
+    } else {
+      return fbuf[base + kc];
+    }
+  };
   int sq = qa % kSweepwSlots;           // slot of run q
   for (int q = qa; q <= qb; ++q) {
     const int plo = run_lo(q), phi = run_hi(q);
     const int sm = sq == 0 ? kSweepwSlots - 1 : sq - 1;  // slot of run q-1
     const int sp = sq == kSweepwSlots - 1 ? 0 : sq + 1;  // slot of run q+1
-    const R *fq = fbuf + sq * fcap;
     const i32x4 *gq = gbuf + (q & (kSweepwGeoSlots - 1)) * gcap;
     for (int p = plo + NPN * cw + sub; p < phi; p += NPN * ncw) {
       const i32x4 *g = gq + (p - plo) * GW;
@@ -1580,7 +1611,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
       typename P::St st[NV];
       typename PC::St stc[DC ? NV : 1];
       {
-        const R xi = fq[selfslot * nvc + kc];
+        const R xi = ldrow(sq * fcap + selfslot * nvc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) P::init(st[v], LV::get(xi, v), ci);
         if constexpr (DC) {
@@ -1594,7 +1625,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         const int l = lr[j] & ~kLrefPole;
         const int dq = (l >> 16) & 3;  // 0: run q-1, 1: run q, 2: run q+1
         const int sl = dq == 0 ? sm : (dq == 1 ? sq : sp);
-        xn[j] = fbuf[sl * fcap + (l & 0xffff) * nvc + kc];
+        xn[j] = ldrow(sl * fcap + (l & 0xffff) * nvc);
       }
       double cx = 0.0, cy = 0.0;  // closure sums (FP32 forms): full normals
       double ccx = 0.0, ccy = 0.0;  // the curl's (DC)
@@ -1650,19 +1681,32 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         __builtin_memcpy(&wd[v * (int)sizeof(Out) / 4], &r, sizeof(Out));
       }
       auto store_row = [&](T *dst, const int (&w)[W]) {
-        if constexpr (NPN == 1) {
+        if constexpr (kSplit) {
+          // one contiguous run per group (16 bytes per lane)
+          const size_t ew = sizeof(Out) / sizeof(T);
+          const i32x4 ro = make_rsrc(dst + (size_t)node * L * ew, (uint32_t)(L * sizeof(Out)));
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            const i32x4 v4 = {w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]};
+            if constexpr (NPN == 1) {
+              buf_store16(v4, ro, lane_on ? s_g[g] * (int)sizeof(Out) : kBufOff, 0, kStoreAux);
+            } else if (lane_on) {
+              *reinterpret_cast<i32x4 *>(dst + ((size_t)node * L + s_g[g]) * ew) = v4;
+            }
+          }
+        } else if constexpr (NPN == 1) {
           // one position per wavefront: a buffer store over its row (the
           // resource is wavefront-uniform)
           const i32x4 ro = make_rsrc(dst + (size_t)node * L * (sizeof(Out) / sizeof(T)),
                                      (uint32_t)(L * sizeof(Out)));
-          const int ob = lane_on ? s_l * (int)sizeof(Out) : kBufOff;
+          const int ob = lane_on ? s_g[0] * (int)sizeof(Out) : kBufOff;
           buf_store_words<W>(w, ro, ob);
         } else if (lane_on) {
           // several positions per wavefront: a store through each lane's
           // own address
           struct Words { int v[W]; } o;
           __builtin_memcpy(o.v, w, sizeof(o));
-          *reinterpret_cast<Words *>(dst + ((size_t)node * L + s_l) * (sizeof(Out) / sizeof(T))) = o;
+          *reinterpret_cast<Words *>(dst + ((size_t)node * L + s_g[0]) * (sizeof(Out) / sizeof(T))) = o;
         }
       };
       store_row(out, wd);
