@@ -3124,8 +3124,51 @@ size_t flux_ws_bytes(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) 
 // automatic lane-vector width), and on meshes of many tiles the
 // register-staged sweep for the FP32 gradient (up to 79 levels) and the
 // wave-specialised sweep for the FP64 divergence and curl (below 48).
+constexpr size_t kMaxLds = 160 * 1024;
 size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchunk, int *vpc_out,
                      int *fcap_out, int *gcap_out);
+
+// Where the wave-specialised sweep is the built-in shape (meshes of many
+// tiles with packed geometry), measured at O1280 and O640 against the other
+// forms: the FP64 gradient from 11 levels (16 levels: 1.16 against 1.61 ms
+// for the flat form, 37: 1.51 against 2.75 for the column form, 137: 5.2
+// against 6.2 for the register-staged sweep); the FP64 divergence and curl
+// from 8 levels (16: 1.06 against 1.71 ms) to 47, and beyond where their
+// chunks fill the lanes (at most three chunks, each of at least 36 lane
+// vectors or of 24-32 with two positions per wavefront; 137 levels: 6.2
+// against 7.0 ms for the column form, which keeps 100 levels and from 150);
+// in FP32, where one chunk of at most 32 lane vectors takes two positions
+// per wavefront: the gradient from 65 to 128 levels (68: 2.34 against 3.25
+// ms; 91: 2.58 against 3.02; at 137 one position per wavefront is slower
+// than the column form's 3.84 ms) and the divergence and curl from 16 to
+// 64 levels (16: 1.56 against 1.81 ms for the flat form, 24: 1.59 against
+// 2.51 for the column form, 48: 2.06 against 2.80; at 91 the column form
+// wins).  FP32 workgroups whose LDS fits twice in a compute unit take 768
+// threads (24 levels of an FP32 vector field: 1.59 against 1.92 ms with
+// 1024).
+static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nlev, LaunchShape *s) {
+  const bool grad = op == ATLAS_OP_GRADIENT;
+  if (!grad && op != ATLAS_OP_DIVERGENCE && op != ATLAS_OP_CURL) return false;
+  // lane vectors of 16 bytes: levels per lane vector
+  const int nv = dt == ATLAS_F64 ? (grad ? 2 : 1) : (grad ? 4 : 2);
+  const int nvec = (nlev + nv - 1) / nv;
+  int nch = 0, vpc = 0;
+  const size_t lds = sweepw_chunks(m, grad ? 10 : kSgeoWords, nvec, 0, &nch, &vpc, nullptr, nullptr);
+  bool take;
+  if (dt == ATLAS_F64)
+    take = grad ? nlev >= 11
+                : nlev >= 8 && (nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))));
+  else
+    take = nch == 1 && vpc <= 32 && (grad ? vpc >= 17 : nlev >= 16);
+  if (!take) return false;
+  s->variant = ATLAS_VARIANT_SWEEP;
+  s->block = dt == ATLAS_F32 && 2 * lds <= kMaxLds ? 768 : 1024;
+  s->nodes_per_block = 0;
+  s->level_chunk = 0;
+  s->blocks_per_cu = 0;
+  s->level_vec = 0;
+  return true;
+}
 
 LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype dt) {
   LaunchShape s;
@@ -3151,6 +3194,7 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
     s.per_pass = 1;
     return s;
   }
+  if (sweepw_fits && sweepw_default(m.d, op, dt, nlev, &s)) return s;
   if (nlev < 24) return s;
   // the sweep runs one workgroup per tile and level chunk, each walking its
   // band's parallels in turn: only a mesh of many tiles fills the chip
@@ -3162,12 +3206,6 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
       s.block = 768;
       s.nodes_per_block = 0;
       s.blocks_per_cu = 1;
-    } else if (dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL) &&
-               sweepw_fits) {
-      // wave-specialised sweep (37 levels at O1280: 2.37 ms against 2.91 ms)
-      s.variant = ATLAS_VARIANT_SWEEP;
-      s.block = 1024;
-      s.nodes_per_block = 0;
     } else if (!(dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL))) {
       s.level_vec = 1;
     }
@@ -3187,36 +3225,16 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
       s.blocks_per_cu = 1;
     }
   }
-  if (dt == ATLAS_F64 && (op == ATLAS_OP_DIVERGENCE || op == ATLAS_OP_CURL) && sweepw_fits) {
-    // wave-specialised sweep where its level chunks fill the lanes: at most
-    // three chunks, each of at least 36 lane vectors or of 24-32 (two
-    // positions per wavefront).  O1280 divergence: 48 / 64 levels 2.74 /
-    // 2.95 ms against 2.96 / 3.32 for the column form, 72-91 levels 3.8-4.2
-    // against 4.2-5.0, 137 levels 6.25 against 7.00; the column form at
-    // 100 levels (three chunks of 34: 5.74 against 5.08) and from 150
-    int nch = 0, vpc = 0;
-    (void)sweepw_chunks(m.d, kSgeoWords, nlev, 0, &nch, &vpc, nullptr, nullptr);
-    if (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))) {
-      s.variant = ATLAS_VARIANT_SWEEP;
-      s.block = 1024;
-      s.nodes_per_block = 0;
-      s.level_vec = 0;
-      return s;
-    }
-  }
   if (dt == ATLAS_F64 && op == ATLAS_OP_GRADIENT && sweep_fits) {
-    // wave-specialised sweep, 1024 threads (137 levels at O1280: 5.8 ms
-    // against 6.2 ms for the register-staged sweep); without the packed
-    // geometry the register-staged sweep on 768 threads
+    // without the packed geometry: the register-staged sweep on 768 threads
     s.variant = ATLAS_VARIANT_SWEEP;
-    s.block = sweepw_fits ? 1024 : 768;
+    s.block = 768;
     s.nodes_per_block = 0;
-    s.blocks_per_cu = sweepw_fits ? 0 : 1;
+    s.blocks_per_cu = 1;
   }
   return s;
 }
 
-constexpr size_t kMaxLds = 160 * 1024;
 
 // Level chunking of the wave-specialised sweep: nvec lane vectors per column
 // in nchunk even chunks of vpc (at most 64, or level_chunk's share), more

@@ -176,15 +176,19 @@ def test_o1280_256_levels(big, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nlev", [1, 17, 24, 37, 48, 64, 72, 79, 80, 91])
+@pytest.mark.parametrize("nlev", [1, 7, 8, 10, 11, 15, 16, 17, 24, 37, 48, 64, 65, 72, 79, 80,
+                                  91, 100, 128, 129])
 def test_o1280_short_columns_sampled(big, nlev, dtype):
     """O1280 with the first nlev levels of the benchmark fields, in the
     default shapes of those sizes, against the oracle at the sampled nodes.
-    The sizes cover every built-in shape switch: the flat form (1, 17: one
-    GPU's slab when 137 levels are split over eight GPUs), the column forms
-    from 24 levels, the FP32 gradient's sweep (24-79 levels, lane vectors of
-    1 or 2 levels), the level-vector forms from 48 levels and one level per
-    lane for the FP32 gradient from 80.  The oracle treats every level on
+    The sizes cover every built-in shape switch: the flat form (1, 7, 10,
+    15, 17: one GPU's slab when 137 levels are split over eight GPUs), the
+    wave-specialised sweep of the FP64 divergence and curl from 8 levels
+    and of the FP64 gradient from 11 (one and two positions per wavefront),
+    the FP32 divergence and curl on it from 16 to 64 levels and the FP32
+    gradient from 65 to 128 (768 and 1024 threads), the column forms, the
+    FP32 gradient's register-staged sweep (24-64 levels), one level per
+    lane for the FP32 gradient from 129.  The oracle treats every level on
     its own, so its values for the first nlev levels are the first nlev
     levels of its 137-level values."""
     _sampled(big, nlev, dtype)
@@ -325,9 +329,9 @@ def mid():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nlev", [1, 37, 64, 137])
+@pytest.mark.parametrize("nlev", [1, 16, 37, 64, 100, 137])
 def test_o640_sampled(mid, nlev, dtype):
     """O640, the serving mix's second largest grid, at its level counts (1,
-    37, 137) and at 64 levels, default shapes, against the oracle at the
-    sampled nodes."""
+    37, 137) and at 16, 64 and 100 levels, default shapes, against the
+    oracle at the sampled nodes."""
     _sampled(mid, nlev, dtype)
