@@ -1346,10 +1346,16 @@ constexpr int kSgeoWords = 14;  // packed sweep geometry per position (16-byte
                                 // words): {node, n, selfslot, 0}, (alpha,
                                 // beta), S[6] / 2, lref[8], ncos[6],
                                 // (cos lat, 0)
-constexpr int kSweepwGroups = 2;     // producer groups (alternate runs)
-constexpr int kSweepwSlots = 5;      // field ring slots: runs q-1 .. q+3
-constexpr int kSweepwGeoSlots = 4;   // geometry ring slots: runs q .. q+3 (the
-                                     // consumers read only run q's records)
+// Positions per wavefront: as many as 64 lanes hold chunks of (at most 8)
+// 8 lane vectors: eight, 12: five, 16: four, 21: three, 32: two; wider
+// chunks one.
+constexpr int kSweepwNpn8 = 8;
+constexpr int kSweepwGroups = 2;     // producer groups (runs taken in turn)
+constexpr int kSweepwLead = kSweepwGroups + 1;  // run q + lead issued at step q
+constexpr int kSweepwSlots = kSweepwLead + 2;   // field ring: runs q-1 .. q+lead
+constexpr int kSweepwGeoSlots = kSweepwLead + 1;  // geometry ring: runs q ..
+                                                  // q+lead (the consumers read
+                                                  // only run q's records)
 // Waves per producer group: two for every operator (with the item indices
 // advanced incrementally, a second producer wave made the FP64 divergence
 // sweep faster too: 7.84 -> 7.62 ms at O1280, 137 levels; 2.08 -> 1.97 ms
@@ -1411,8 +1417,8 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
   constexpr int kSweepwGroupWaves = sweepw_group_waves<OP>();
   constexpr int NPW = kSweepwGroups * kSweepwGroupWaves;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R *fbuf = reinterpret_cast<R *>(smem_raw);                           // [5][fcap]
-  i32x4 *gbuf = reinterpret_cast<i32x4 *>(fbuf + kSweepwSlots * fcap);  // [4][gcap]
+  R *fbuf = reinterpret_cast<R *>(smem_raw);                           // [field slots][fcap]
+  i32x4 *gbuf = reinterpret_cast<i32x4 *>(fbuf + kSweepwSlots * fcap);  // [geometry slots][gcap]
   const int u = xcd_tile(blockIdx.x, per_xcd);
   const int nvec = (nlev + NV - 1) / NV;
   const int nchunk = (nvec + vpc - 1) / vpc;
@@ -1444,11 +1450,11 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
   if (qb < 0) return;
 
   if (wave < NPW) {
-    // ---- producers: group grp loads the runs of its parity --------------
+    // ---- producers: group grp loads the runs r with r mod groups = grp ----
     const int grp = wave / kSweepwGroupWaves, gwave = wave - grp * kSweepwGroupWaves;
     const V *vin = reinterpret_cast<const V *>(in);
-    // columns and geometry of run q into ring slot q mod 5, the waves of
-    // the calling group (or, with gw_n = NPW, all producers) sharing the
+    // columns and geometry of run q into the ring slots of q, the waves of
+    // the calling group (or, with nwv = NPW, all producers) sharing the
     // load instructions
     auto load = [&](int q, int w, int nwv) {
       const int sl = q % kSweepwSlots;
@@ -1484,7 +1490,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         const i32x4 rs = make_rsrc(m.sgeo + (size_t)plo * kSgeoWords,
                                    (uint32_t)n * kSgeoWords * 16u);
         const int nitems = n * GW;
-        i32x4 *slot = gbuf + (q & (kSweepwGeoSlots - 1)) * gcap;
+        i32x4 *slot = gbuf + (q % kSweepwGeoSlots) * gcap;
         for (int b = w; b * 64 < nitems; b += nwv) {
           const int i = b * 64 + lane;
           int off = kBufOff;
@@ -1496,19 +1502,21 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
         }
       }
     };
-    // prologue: runs qa-1 .. qa+1 by every producer (waited), run qa+2 by
-    // its group (waited at the end of step qa)
+    // prologue: runs qa-1 .. qa+1 by every producer (waited), runs qa+2 ..
+    // qa+lead-1 by their groups (run r waited at the end of step r-2)
     for (int q = max(0, qa - 1); q <= min(nseg - 1, qa + 1); ++q) load(q, wave, NPW);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (qa + 2 < nseg && ((qa + 2) & 1) == grp) load(qa + 2, gwave, kSweepwGroupWaves);
+    for (int r = qa + 2; r < min(nseg, qa + kSweepwLead); ++r)
+      if (r % kSweepwGroups == grp) load(r, gwave, kSweepwGroupWaves);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     for (int q = qa; q <= qb; ++q) {
-      if (q + 3 < nseg && ((q + 3) & 1) == grp) load(q + 3, gwave, kSweepwGroupWaves);
-      // run q+2 (issued one step ago by the group of its parity) is in LDS
-      // before step q+1 reads it
-      if (((q + 2) & 1) == grp) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (q + kSweepwLead < nseg && (q + kSweepwLead) % kSweepwGroups == grp)
+        load(q + kSweepwLead, gwave, kSweepwGroupWaves);
+      // run q+2 (issued lead-2 steps ago by its group, which has issued
+      // nothing since) is in LDS before step q+1 reads it
+      if ((q + 2) % kSweepwGroups == grp) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       asm volatile("" ::: "memory");
       __builtin_amdgcn_s_barrier();
       asm volatile("" ::: "memory");
@@ -1524,12 +1532,14 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
   asm volatile("" ::: "memory");
   const int cw = wave - NPW, ncw = nw - NPW;
   // NPN positions per wavefront, 64 / NPN lanes each (chunks of at most
-  // 64 / NPN lane vectors)
+  // 64 / NPN lane vectors); where NPN does not divide 64 the lanes left over
+  // repeat the last position's first lanes and store nothing
   constexpr int LPN = 64 / NPN;
-  const int sub = NPN > 1 ? lane / LPN : 0;
-  const int hl = lane - sub * LPN;
+  const int sub_raw = NPN > 1 ? lane / LPN : 0;
+  const int sub = min(sub_raw, NPN - 1);
+  const int hl = lane - sub_raw * LPN;
   const int kc = min(hl, nvc - 1);  // lanes past the chunk read a valid entry
-  const bool lane_on = hl < nvc;
+  const bool lane_on = sub_raw < NPN && hl < nvc;
   // Lanes whose results exceed 16 bytes (the gradient: two components at
   // NV levels) would make every store instruction strided, each lane
   // writing part of its own piece of the row.  Such a lane takes NG groups
@@ -1568,7 +1578,7 @@ __global__ void __launch_bounds__(1024) k_sweepw(DevMesh m, const T *__restrict_
     const int plo = run_lo(q), phi = run_hi(q);
     const int sm = sq == 0 ? kSweepwSlots - 1 : sq - 1;  // slot of run q-1
     const int sp = sq == kSweepwSlots - 1 ? 0 : sq + 1;  // slot of run q+1
-    const i32x4 *gq = gbuf + (q & (kSweepwGeoSlots - 1)) * gcap;
+    const i32x4 *gq = gbuf + (q % kSweepwGeoSlots) * gcap;
     for (int p = plo + NPN * cw + sub; p < phi; p += NPN * ncw) {
       const i32x4 *g = gq + (p - plo) * GW;
       const i32x4 w0 = g[0], w1 = g[1];
@@ -3129,23 +3139,25 @@ size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchu
                      int *fcap_out, int *gcap_out);
 
 // Where the wave-specialised sweep is the built-in shape (meshes of many
-// tiles with packed geometry), measured at O1280 and O640 against the other
-// forms: the FP64 gradient from 11 levels (16 levels: 1.16 against 1.61 ms
-// for the flat form, 37: 1.51 against 2.75 for the column form, 137: 5.2
-// against 6.2 for the register-staged sweep); the FP64 divergence and curl
-// from 8 levels (16: 1.06 against 1.71 ms) to 47, and beyond where their
-// chunks fill the lanes (at most three chunks, each of at least 36 lane
-// vectors or of 24-32 with two positions per wavefront; 137 levels: 6.2
-// against 7.0 ms for the column form, which keeps 100 levels and from 150);
-// in FP32, where one chunk of at most 32 lane vectors takes two positions
-// per wavefront: the gradient from 65 to 128 levels (68: 2.34 against 3.25
-// ms; 91: 2.58 against 3.02; at 137 one position per wavefront is slower
-// than the column form's 3.84 ms) and the divergence and curl from 16 to
-// 64 levels (16: 1.56 against 1.81 ms for the flat form, 24: 1.59 against
-// 2.51 for the column form, 48: 2.06 against 2.80; at 91 the column form
-// wins).  FP32 workgroups whose LDS fits twice in a compute unit take 768
-// threads (24 levels of an FP32 vector field: 1.59 against 1.92 ms with
-// 1024).
+// tiles with packed geometry), measured at O1280 against the other forms.
+// Narrow level chunks take 2, 4 or 8 positions per wavefront, so short
+// columns fill the lanes too.  FP64 gradient from 4 levels (8: 0.57 against
+// 0.87 ms for the flat form, 37: 1.51 against 2.75 for the column form,
+// 137: 5.2 against 6.2 for the register-staged sweep); FP64 divergence and
+// curl from 2 levels (4: 0.47 against 0.62 ms, 16: 0.82 against 1.71) to
+// 47, and beyond where their chunks fill the lanes (at most three chunks,
+// each of at least 36 lane vectors or of 24-32; 137 levels: 6.2 against
+// 7.0 ms for the column form, which keeps 100 levels and from 150).  In
+// FP32, where one chunk of at most 32 lane vectors holds the column: the
+// gradient from 12 to 128 levels (16: 0.82 against 1.37 ms for the flat
+// form, 64: 1.50 against 2.07 for the register-staged sweep, 91: 2.58
+// against 3.02 for the column form; at 137 one position per wavefront is
+// slower than the column form's 3.84 ms) and the divergence and curl from
+// 6 to 64 levels (8: 0.65 against 0.96 ms, 48: 2.06 against 2.80; at 91
+// the column form wins).  Workgroups of 768 threads where the LDS fits
+// twice in a compute unit, in FP32 (24 levels of a vector field: 1.59
+// against 1.92 ms with 1024) and for FP64 chunks of at most 8 lane vectors
+// (4 levels of the gradient: 0.50 against 0.57 ms).
 static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nlev, LaunchShape *s) {
   const bool grad = op == ATLAS_OP_GRADIENT;
   if (!grad && op != ATLAS_OP_DIVERGENCE && op != ATLAS_OP_CURL) return false;
@@ -3156,13 +3168,14 @@ static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nl
   const size_t lds = sweepw_chunks(m, grad ? 10 : kSgeoWords, nvec, 0, &nch, &vpc, nullptr, nullptr);
   bool take;
   if (dt == ATLAS_F64)
-    take = grad ? nlev >= 11
-                : nlev >= 8 && (nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))));
+    take = grad ? nlev >= 4
+                : nlev >= 2 && (nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))));
   else
-    take = nch == 1 && vpc <= 32 && (grad ? vpc >= 17 : nlev >= 16);
+    take = nch == 1 && vpc <= 32 && nlev >= (grad ? 12 : 6);
   if (!take) return false;
+  const bool two_per_cu = 2 * lds <= kMaxLds && (dt == ATLAS_F32 || vpc <= kSweepwNpn8);
   s->variant = ATLAS_VARIANT_SWEEP;
-  s->block = dt == ATLAS_F32 && 2 * lds <= kMaxLds ? 768 : 1024;
+  s->block = two_per_cu ? 768 : 1024;
   s->nodes_per_block = 0;
   s->level_chunk = 0;
   s->blocks_per_cu = 0;
@@ -3238,8 +3251,9 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
 
 // Level chunking of the wave-specialised sweep: nvec lane vectors per column
 // in nchunk even chunks of vpc (at most 64, or level_chunk's share), more
-// chunks until the field ring (5 slots) and the geometry ring (4 slots of gw
-// words per position) fit in LDS.  Returns the LDS bytes.
+// chunks until the field ring (kSweepwSlots slots) and the geometry ring
+// (kSweepwGeoSlots slots of gw words per position) fit in LDS.  Returns the
+// LDS bytes.
 size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchunk, int *vpc_out,
                      int *fcap_out, int *gcap_out) {
   int vpc = min(want_vpc > 0 ? want_vpc : 64, nvec);
@@ -3310,9 +3324,14 @@ static atlas_status launch_sweepw(const DevMesh &m, const T *in, T *out, T *out2
   const int units = m.ntiles * nchunk;
   const int per = (units + 7) / 8;
   void (*kern)(DevMesh, const T *, T *, T *, int, int, int, int, int, int) = nullptr;
-  // two positions per wavefront when a chunk fills at most half of it
+  // NPN positions per wavefront when NPN chunks fit in its lanes
   if constexpr (lane_vec_ok<T, OP, nv16>())
-    kern = vpc <= 32 ? k_sweepw<T, OP, nv16, 2, DC> : k_sweepw<T, OP, nv16, 1, DC>;
+    kern = vpc <= 8    ? k_sweepw<T, OP, nv16, 8, DC>
+           : vpc <= 12 ? k_sweepw<T, OP, nv16, 5, DC>
+           : vpc <= 16 ? k_sweepw<T, OP, nv16, 4, DC>
+           : vpc <= 21 ? k_sweepw<T, OP, nv16, 3, DC>
+           : vpc <= 32 ? k_sweepw<T, OP, nv16, 2, DC>
+                       : k_sweepw<T, OP, nv16, 1, DC>;
   if (!kern) return fail(ATLAS_EINVAL, "wave-specialised sweep not available");
   ATLASX_HIP(hipFuncSetAttribute((const void *)kern,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -176,18 +176,18 @@ def test_o1280_256_levels(big, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nlev", [1, 7, 8, 10, 11, 15, 16, 17, 24, 37, 48, 64, 65, 72, 79, 80,
-                                  91, 100, 128, 129])
+@pytest.mark.parametrize("nlev", [1, 2, 3, 4, 5, 6, 8, 11, 12, 16, 17, 24, 33, 37, 48, 64, 65,
+                                  72, 79, 80, 91, 100, 128, 129])
 def test_o1280_short_columns_sampled(big, nlev, dtype):
     """O1280 with the first nlev levels of the benchmark fields, in the
     default shapes of those sizes, against the oracle at the sampled nodes.
-    The sizes cover every built-in shape switch: the flat form (1, 7, 10,
-    15, 17: one GPU's slab when 137 levels are split over eight GPUs), the
-    wave-specialised sweep of the FP64 divergence and curl from 8 levels
-    and of the FP64 gradient from 11 (one and two positions per wavefront),
-    the FP32 divergence and curl on it from 16 to 64 levels and the FP32
-    gradient from 65 to 128 (768 and 1024 threads), the column forms, the
-    FP32 gradient's register-staged sweep (24-64 levels), one level per
+    The sizes cover every built-in shape switch: the flat form (1 to 11
+    levels depending on the operator; 17 is one GPU's slab when 137 levels
+    are split over eight GPUs), the wave-specialised sweep of the FP64
+    divergence and curl from 2 levels and of the FP64 gradient from 4, of
+    the FP32 divergence and curl from 6 to 64 and of the FP32 gradient from
+    12 to 128, with 8, 4, 2 and 1 positions per wavefront as the level
+    chunk narrows (768 and 1024 threads), the column forms, one level per
     lane for the FP32 gradient from 129.  The oracle treats every level on
     its own, so its values for the first nlev levels are the first nlev
     levels of its 137-level values."""

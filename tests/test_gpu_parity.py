@@ -93,8 +93,10 @@ def test_launch_shapes_bitwise_identical(P, nlev, op, dtype):
                 shapes.append(P.Launch(variant, block, npb))
     shapes.append(P.Launch(P.VARIANT_FLUX, 256, 0))
     shapes.append(P.Launch(P.VARIANT_FLUX, 64, 0))
+    # level chunks of 1..64 levels: 1 to 8 positions per wavefront in the
+    # wave-specialised sweep (blocks of at least 512 threads)
     for block in (64, 256, 512, 1024):
-        for kc in (0, 1, 5, 32):
+        for kc in (0, 1, 5, 20, 32, 40):
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc))      # lane vectors
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 2))
             shapes.append(P.Launch(P.VARIANT_SWEEP, block, 0, kc, 0, 3))
