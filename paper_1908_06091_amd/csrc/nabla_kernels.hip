@@ -3140,24 +3140,24 @@ size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchu
 
 // Where the wave-specialised sweep is the built-in shape (meshes of many
 // tiles with packed geometry), measured at O1280 against the other forms.
-// Narrow level chunks take 2, 4 or 8 positions per wavefront, so short
+// Narrow level chunks take up to eight positions per wavefront, so short
 // columns fill the lanes too.  FP64 gradient from 4 levels (8: 0.57 against
-// 0.87 ms for the flat form, 37: 1.51 against 2.75 for the column form,
-// 137: 5.2 against 6.2 for the register-staged sweep); FP64 divergence and
-// curl from 2 levels (4: 0.47 against 0.62 ms, 16: 0.82 against 1.71) to
-// 47, and beyond where their chunks fill the lanes (at most three chunks,
-// each of at least 36 lane vectors or of 24-32; 137 levels: 6.2 against
-// 7.0 ms for the column form, which keeps 100 levels and from 150).  In
-// FP32, where one chunk of at most 32 lane vectors holds the column: the
-// gradient from 12 to 128 levels (16: 0.82 against 1.37 ms for the flat
-// form, 64: 1.50 against 2.07 for the register-staged sweep, 91: 2.58
-// against 3.02 for the column form; at 137 one position per wavefront is
-// slower than the column form's 3.84 ms) and the divergence and curl from
-// 6 to 64 levels (8: 0.65 against 0.96 ms, 48: 2.06 against 2.80; at 91
-// the column form wins).  Workgroups of 768 threads where the LDS fits
-// twice in a compute unit, in FP32 (24 levels of a vector field: 1.59
-// against 1.92 ms with 1024) and for FP64 chunks of at most 8 lane vectors
-// (4 levels of the gradient: 0.50 against 0.57 ms).
+// 0.87 ms for the flat form, 37: 1.51 against 2.75 for the column form),
+// long columns in the chunk count that fills the most lanes; FP64
+// divergence and curl from 2 levels (4: 0.47 against 0.62 ms, 16: 0.82
+// against 1.71) to 47, from 90 in chunks of 16 lane vectors, and between
+// where at most three chunks of at least 36 lane vectors or of 24-32 fill
+// the lanes.  In FP32, where one chunk of at most 32 lane vectors holds
+// the column: the gradient from 12 to 128 levels (16: 0.82 against 1.37 ms
+// for the flat form, 64: 1.50 against 2.07 for the register-staged sweep,
+// 91: 2.58 against 3.02 for the column form; at 137 one position per
+// wavefront is slower than the column form's 3.84 ms) and the divergence
+// and curl from 6 to 64 levels (8: 0.65 against 0.96 ms, 48: 2.06 against
+// 2.80), on the largest meshes to 96 in chunks of 16.  Workgroups of 768
+// threads where the LDS fits twice in a compute unit, in FP32 (24 levels of
+// a vector field: 1.59 against 1.92 ms with 1024), for the FP64 divergence
+// in chunks of 16, and for FP64 chunks of at most 8 lane vectors (4 levels
+// of the gradient: 0.50 against 0.57 ms).
 static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nlev, LaunchShape *s) {
   const bool grad = op == ATLAS_OP_GRADIENT;
   if (!grad && op != ATLAS_OP_DIVERGENCE && op != ATLAS_OP_CURL) return false;
@@ -3167,6 +3167,45 @@ static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nl
   int nch = 0, vpc = 0;
   const size_t lds = sweepw_chunks(m, grad ? 10 : kSgeoWords, nvec, 0, &nch, &vpc, nullptr, nullptr);
   bool take;
+  int want = 0;  // lane vectors per chunk asked for (0: as many as fit)
+  if (dt == ATLAS_F64 && grad && nch > 1) {
+    // columns of several chunks: the count (up to two more than the fewest)
+    // that fills the most lanes with whole chunks (137 levels: four chunks
+    // of 18, three positions per wavefront, 5.19 against 5.45 ms for two
+    // chunks of 35)
+    double best = 0.0;
+    for (int c = nch; c <= nch + 2; ++c) {
+      const int v = (nvec + c - 1) / c;
+      const double fill = (double)(min(8, 64 / v) * v) / 64.0;
+      if (fill > best + 1e-9) {
+        best = fill;
+        want = v;
+      }
+    }
+  } else if (dt == ATLAS_F64 && !grad && nlev >= 90) {
+    want = 16;  // long vector columns: chunks of 16 (four positions per
+                // wavefront) at two workgroups per CU; O1280: 110 levels
+                // 4.78 against 5.82 ms for the column form, 137 levels 6.19
+                // against 6.57 for three chunks of 46
+  } else if (dt == ATLAS_F32 && !grad && nlev > 64 && nlev <= 96 && m.ntiles >= 4096) {
+    want = 16;  // (O1280, 91 levels: 3.15 against 3.30 ms for the column
+                // form; at O640 the column form stays ahead)
+  }
+  if (want && want * nv <= 64) {  // a level_chunk a caller may pass back
+    int nch2 = 0, vpc2 = 0;
+    const size_t l2 =
+        sweepw_chunks(m, grad ? 10 : kSgeoWords, nvec, want, &nch2, &vpc2, nullptr, nullptr);
+    if (l2 <= kMaxLds) {
+      s->level_chunk = want * nv;
+      const bool two_per_cu = 2 * l2 <= kMaxLds && !(dt == ATLAS_F64 && grad);
+      s->variant = ATLAS_VARIANT_SWEEP;
+      s->block = two_per_cu ? 768 : 1024;
+      s->nodes_per_block = 0;
+      s->blocks_per_cu = 0;
+      s->level_vec = 0;
+      return true;
+    }
+  }
   if (dt == ATLAS_F64)
     take = grad ? nlev >= 4
                 : nlev >= 2 && (nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))));
@@ -3568,7 +3607,23 @@ static atlas_status launch_div_curl_typed(const MeshStore &ms, atlas_dtype dt, c
   {
     // where the divergence runs the wave-specialised sweep, the curl rides
     // on the same loads
-    const LaunchShape sh = shape_from(nullptr, ms, ATLAS_OP_DIVERGENCE, nlev, dt);
+    LaunchShape sh = shape_from(nullptr, ms, ATLAS_OP_DIVERGENCE, nlev, dt);
+    if (sh.variant == ATLAS_VARIANT_SWEEP && sh.level_chunk > 0) {
+      // chunks of 16 lane vectors pay for the divergence alone; with the
+      // curl's states beside it the one pass runs slower in them (9.67
+      // against 8.42 ms at O1280, 137 levels), so it takes the widest
+      // chunks where at most three of at least 36 (or 24-32) lane vectors
+      // fill the lanes, else the column form
+      int nch = 0, vpc = 0;
+      constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP_DIV>::V);
+      (void)sweepw_chunks(m, kSgeoWords, (nlev + nv16 - 1) / nv16, 0, &nch, &vpc, nullptr, nullptr);
+      if (sizeof(T) == 8 && nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))) {
+        sh.level_chunk = 0;
+        sh.block = 1024;
+      } else {
+        sh.variant = ATLAS_VARIANT_COLUMN;
+      }
+    }
     if (sh.variant == ATLAS_VARIANT_SWEEP && sweepw_applies<T, OP_DIV>(m, nlev, sh))
       return launch_sweepw<T, OP_DIV, true>(m, in, od, oc, nlev, sh, st);
   }
