@@ -3145,9 +3145,7 @@ size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchu
 // 0.87 ms for the flat form, 37: 1.51 against 2.75 for the column form),
 // long columns in the chunk count that fills the most lanes; FP64
 // divergence and curl from 2 levels (4: 0.47 against 0.62 ms, 16: 0.82
-// against 1.71) to 47, from 90 in chunks of 16 lane vectors, and between
-// where at most three chunks of at least 36 lane vectors or of 24-32 fill
-// the lanes.  In FP32, where one chunk of at most 32 lane vectors holds
+// against 1.71), from 33 in chunks of 16 lane vectors.  In FP32, where one chunk of at most 32 lane vectors holds
 // the column: the gradient from 12 to 128 levels (16: 0.82 against 1.37 ms
 // for the flat form, 64: 1.50 against 2.07 for the register-staged sweep,
 // 91: 2.58 against 3.02 for the column form; at 137 one position per
@@ -3182,11 +3180,13 @@ static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nl
         want = v;
       }
     }
-  } else if (dt == ATLAS_F64 && !grad && nlev >= 90) {
-    want = 16;  // long vector columns: chunks of 16 (four positions per
-                // wavefront) at two workgroups per CU; O1280: 110 levels
-                // 4.78 against 5.82 ms for the column form, 137 levels 6.19
-                // against 6.57 for three chunks of 46
+  } else if (dt == ATLAS_F64 && !grad && nlev > 32) {
+    want = 16;  // vector columns wider than 32 lane vectors: chunks of 16
+                // (four positions per wavefront) at two workgroups per CU;
+                // O1280: 48 levels 2.07 against 2.74 ms for one chunk of
+                // 48, 72 levels 3.33 against 3.88, 110 levels 4.78 against
+                // 5.82 for the column form, 137 levels 6.19 against 6.57
+                // for three chunks of 46
   } else if (dt == ATLAS_F32 && !grad && nlev > 64 && nlev <= 96 && m.ntiles >= 4096) {
     want = 16;  // (O1280, 91 levels: 3.15 against 3.30 ms for the column
                 // form; at O640 the column form stays ahead)
@@ -3617,7 +3617,8 @@ static atlas_status launch_div_curl_typed(const MeshStore &ms, atlas_dtype dt, c
       int nch = 0, vpc = 0;
       constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP_DIV>::V);
       (void)sweepw_chunks(m, kSgeoWords, (nlev + nv16 - 1) / nv16, 0, &nch, &vpc, nullptr, nullptr);
-      if (sizeof(T) == 8 && nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))) {
+      if (sizeof(T) == 8 &&
+          (nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))))) {
         sh.level_chunk = 0;
         sh.block = 1024;
       } else {
