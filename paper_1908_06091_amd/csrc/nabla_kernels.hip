@@ -3148,10 +3148,10 @@ size_t sweepw_chunks(const DevMesh &m, int gw, int nvec, int want_vpc, int *nchu
 // against 1.71), from 33 in chunks of 16 lane vectors.  In FP32, where one chunk of at most 32 lane vectors holds
 // the column: the gradient from 12 to 128 levels (16: 0.82 against 1.37 ms
 // for the flat form, 64: 1.50 against 2.07 for the register-staged sweep,
-// 91: 2.58 against 3.02 for the column form; at 137 one position per
-// wavefront is slower than the column form's 3.84 ms) and the divergence
-// and curl from 6 to 64 levels (8: 0.65 against 0.96 ms, 48: 2.06 against
-// 2.80), on the largest meshes to 96 in chunks of 16.  Workgroups of 768
+// 91: 2.58 against 3.02 for the column form), from 88 to 160 levels in
+// chunks of 16 lane vectors, and the divergence and curl from 6 to 64
+// levels (8: 0.65 against 0.96 ms, 48: 2.06 against 2.80), from 41 in
+// chunks of 16, on the largest meshes to 96.  Workgroups of 768
 // threads where the LDS fits twice in a compute unit, in FP32 (24 levels of
 // a vector field: 1.59 against 1.92 ms with 1024), for the FP64 divergence
 // in chunks of 16, and for FP64 chunks of at most 8 lane vectors (4 levels
@@ -3187,9 +3187,14 @@ static bool sweepw_default(const DevMesh &m, atlas_op op, atlas_dtype dt, int nl
                 // 48, 72 levels 3.33 against 3.88, 110 levels 4.78 against
                 // 5.82 for the column form, 137 levels 6.19 against 6.57
                 // for three chunks of 46
-  } else if (dt == ATLAS_F32 && !grad && nlev > 64 && nlev <= 96 && m.ntiles >= 4096) {
-    want = 16;  // (O1280, 91 levels: 3.15 against 3.30 ms for the column
-                // form; at O640 the column form stays ahead)
+  } else if (dt == ATLAS_F32 && !grad && nlev > 40 &&
+             (nlev <= 64 || (nlev <= 96 && m.ntiles >= 4096))) {
+    want = 16;  // (O1280, 48 levels: 1.86 against 2.05 ms in one chunk;
+                // 91 levels: 3.15 against 3.30 for the column form, which
+                // stays ahead at O640 from 65 levels)
+  } else if (dt == ATLAS_F32 && grad && nlev >= 88 && nlev <= 160) {
+    want = 16;  // (O1280, 91 levels: 2.51 against 2.70 ms in one chunk;
+                // 137 levels: 3.81 against 3.87 for the column form)
   }
   if (want && want * nv <= 64) {  // a level_chunk a caller may pass back
     int nch2 = 0, vpc2 = 0;
@@ -3616,11 +3621,14 @@ static atlas_status launch_div_curl_typed(const MeshStore &ms, atlas_dtype dt, c
       // fill the lanes, else the column form
       int nch = 0, vpc = 0;
       constexpr int nv16 = 16 / (int)sizeof(typename Pol<T, OP_DIV>::V);
-      (void)sweepw_chunks(m, kSgeoWords, (nlev + nv16 - 1) / nv16, 0, &nch, &vpc, nullptr, nullptr);
-      if (sizeof(T) == 8 &&
-          (nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32))))) {
+      const size_t lds = sweepw_chunks(m, kSgeoWords, (nlev + nv16 - 1) / nv16, 0, &nch, &vpc,
+                                       nullptr, nullptr);
+      const bool wide = sizeof(T) == 8
+                            ? nlev < 48 || (nch <= 3 && (vpc >= 36 || (vpc >= 24 && vpc <= 32)))
+                            : nch == 1 && vpc <= 32;
+      if (wide) {
         sh.level_chunk = 0;
-        sh.block = 1024;
+        sh.block = sizeof(T) == 4 && 2 * lds <= kMaxLds ? 768 : 1024;
       } else {
         sh.variant = ATLAS_VARIANT_COLUMN;
       }

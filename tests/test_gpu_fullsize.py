@@ -176,24 +176,23 @@ def test_o1280_256_levels(big, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("nlev", [1, 2, 3, 4, 5, 6, 8, 11, 12, 16, 17, 24, 33, 37, 48, 64, 65,
-                                  72, 79, 80, 89, 90, 91, 96, 97, 100, 128, 129])
+@pytest.mark.parametrize("nlev", [1, 2, 3, 4, 5, 6, 8, 11, 12, 16, 17, 24, 32, 33, 37, 40, 41, 48,
+                                  64, 65, 72, 79, 80, 87, 88, 91, 96, 97, 100, 128, 129])
 def test_o1280_short_columns_sampled(big, nlev, dtype):
     """O1280 with the first nlev levels of the benchmark fields, in the
     default shapes of those sizes, against the oracle at the sampled nodes.
     The sizes cover every built-in shape switch: the flat form (1 to 11
     levels depending on the operator; 17 is one GPU's slab when 137 levels
     are split over eight GPUs), the wave-specialised sweep of the FP64
-    divergence and curl from 2 levels and of the FP64 gradient from 4, of
-    the FP32 divergence and curl from 6 to 64 and of the FP32 gradient from
-    12 to 128, with 8, 5, 4, 3, 2 and 1 positions per wavefront as the
-    level chunk narrows (768 and 1024 threads), chunks of 16 lane vectors
-    for the FP64 divergence and curl from 90 levels and the FP32 ones at
-    65-96, the column forms, one level per lane for the FP32 gradient from
-    129; 137 (the test above) and 256 levels take the FP64 gradient's
-    chunk count that fills the most lanes.  The oracle treats every level on
-    its own, so its values for the first nlev levels are the first nlev
-    levels of its 137-level values."""
+    divergence and curl from 2 levels (in chunks of 16 lane vectors from
+    33) and of the FP64 gradient from 4, of the FP32 divergence and curl
+    from 6 to 64 (chunks of 16 from 41; to 96 on this mesh) and of the FP32
+    gradient from 12 (chunks of 16 from 88), with 8, 5, 4, 3, 2 and 1
+    positions per wavefront as the level chunk narrows (768 and 1024
+    threads), and the column forms; 137 (the test above) and 256 levels
+    take the FP64 gradient's chunk count that fills the most lanes.  The
+    oracle treats every level on its own, so its values for the first nlev
+    levels are the first nlev levels of its 137-level values."""
     _sampled(big, nlev, dtype)
 
 
