@@ -3240,9 +3240,13 @@ LaunchShape default_shape(const MeshStore &m, atlas_op op, int nlev, atlas_dtype
   if (op == ATLAS_OP_LAPLACIAN) {
     // large meshes: the fused one-pass form, wave-specialised (it moves a
     // third of the two passes' field bytes; measured faster than the two
-    // passes at 16 to 137 levels at O640 and O1280 in both precisions)
-    if (nlev >= 16 && m.d.l2_ok && m.d.ntiles >= kSweepMinTiles && m.d.maxdeg <= 6 &&
-        m.d.mindeg >= kMinRow) {
+    // passes up to 137 levels at O640 and O1280 in both precisions from 17
+    // levels in FP64 and 33 in FP32).  Shorter columns take the two passes,
+    // each on its own sweep with several positions per wavefront (O1280
+    // FP64 16 levels: 1.61 against 1.89 ms; FP32 32 levels: 2.05 against
+    // 2.57)
+    if (nlev >= (dt == ATLAS_F64 ? 17 : 33) && m.d.l2_ok && m.d.ntiles >= kSweepMinTiles &&
+        m.d.maxdeg <= 6 && m.d.mindeg >= kMinRow) {
       s.variant = ATLAS_VARIANT_FUSED;
       s.block = 1024;
       s.nodes_per_block = 0;
